@@ -1,0 +1,336 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each check raises AssertionError on failure.  They are collected as tests in
+test_oracle_pins.py and re-run against deliberately broken copies of the
+oracle in test_oracle_mutants.py, to show that a plausible slip anywhere in
+the oracle (a dropped term, a wrong index, a flipped comparison, a transposed
+operand) trips at least one of them.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import os
+
+import numpy as np
+
+from bruteforce import bf_filter, bf_join, bf_query, bf_scan, bf_union
+from synth import Pattern, Plan, pat
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+def _rows(t):
+    return [tuple(int(x) for x in r) for r in t.rows]
+
+
+def tiny_graph(seed: int, n: int = 12, ids: int = 4) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return rng.integers(1, ids + 1, size=(n, 3)).astype(np.uint32)
+
+
+# ---------------------------------------------------------------------------
+# values the paper prints
+# ---------------------------------------------------------------------------
+
+def check_rule11(O):
+    """Sec. 5.7, Rule 11 worked example: both positionArrays, both hash
+    tables, and the combined (x, z) result."""
+    gd = _gold("rule11_example.json")
+    g = np.array(gd["data"], dtype=np.uint32)
+    k1 = gd["step1_key"]
+    f1 = O.scan_flags(g, Pattern(k1[0], k1[1], k1[2]))
+    assert f1.tolist() == gd["step1_positionArray"], f1
+    # hashTable1: object -> subjects of the step-1 matches
+    t1 = O.scan(g, pat("?x 84 ?y"))
+    ht1 = {}
+    for x, y in _rows(t1):
+        ht1.setdefault(str(y), []).append(x)
+    assert {k: sorted(v) for k, v in ht1.items()} == \
+        {k: sorted(v) for k, v in gd["step1_hashTable1_object_to_subjects"].items()}
+    # step 2 searches the distinct step-1 objects as keys (keysArray)
+    keys = sorted({y for _, y in _rows(t1)})
+    assert [[k, 84, 0] for k in keys] == gd["step2_keysArray"]
+    member = O.scan_multi(g, [Pattern(k, 84, 0) for k in keys])
+    f2 = (member != 0).astype(int).tolist()
+    assert f2 == gd["step2_positionArray"], f2
+    ht2 = {}
+    for i in np.nonzero(member)[0]:
+        ht2.setdefault(str(int(g[i, 0])), []).append(int(g[i, 2]))
+    assert {k: sorted(v) for k, v in ht2.items()} == \
+        {k: sorted(v) for k, v in gd["step2_hashTable2_subject_to_objects"].items()}
+    want = sorted(tuple(r) for r in gd["result_x_z"])
+    n = {}
+    plan = (Plan().scan(pat("?x 84 ?y", n)).scan(pat("?y 84 ?z", n)).join(n["?y"])
+            .project([n["?x"], n["?z"]]).distinct())
+    res = O.query(g, plan)
+    assert _rows(res) == want, _rows(res)
+    # the same result through the raw join (OS relation: object of q0 with subject of q1)
+    for method in ("nested", "sortmerge"):
+        j = O.join(O.scan(g, pat("?x 84 ?y")), 1, O.scan(g, pat("?y 84 ?z")), 0, method)
+        assert sorted({(r[0], r[2]) for r in _rows(j)}) == want
+
+
+def check_toy_sec3(O):
+    """Sec. 3 walk-through: 'ABCPress publishes ?' becomes key (1,2,?) and
+    finds TripleID (1,2,1)."""
+    gd = _gold("toy_sec3.json")
+    g, dicts = O.encode_graph(gd["triples"], shared=False)
+    key = [dicts[i][t] if t != "?" else 0 for i, t in enumerate(gd["query_terms"])]
+    assert key == gd["key"]
+    flags = O.scan_flags(g, Pattern(*key))
+    found = g[flags.astype(bool)].tolist()
+    assert found == gd["found"], found
+    t = O.scan(g, Pattern(key[0], key[1], key[2], vo=0))
+    assert _rows(t) == [(1,)]
+
+
+# ---------------------------------------------------------------------------
+# brute force on tiny inputs
+# ---------------------------------------------------------------------------
+
+VAR_LAYOUTS = [(0, 1, 2), (-1, -1, -1), (0, 0, 0), (0, 1, 0), (0, 0, 1), (1, 0, 1),
+               (2, 1, 0), (-1, 0, -1), (0, -1, 1)]
+
+
+def _layout_pattern(consts, layout, rng_spec=None):
+    vs = [layout[x] if consts[x] == 0 else -1 for x in range(3)]
+    kw = {}
+    if rng_spec:
+        kw = dict(range_pos=rng_spec[0], lo=rng_spec[1], hi=rng_spec[2])
+    return Pattern(consts[0], consts[1], consts[2], vs[0], vs[1], vs[2], **kw)
+
+
+def check_exhaustive_scan(O, seeds=(0, 1, 2), ids=4):
+    """All 125 constant patterns over IDs 0..4, under several variable
+    layouts and a few ranges, against brute force, on graphs with duplicates."""
+    for seed in seeds:
+        g = tiny_graph(seed, 12, ids)
+        g = np.concatenate([g, g[:3]])          # guaranteed duplicate triples
+        for consts in itertools.product(range(ids + 1), repeat=3):
+            for layout in VAR_LAYOUTS:
+                for rs in (None, (2, 2, 4), (0, 3, 3), (1, 1, 5)):
+                    p = _layout_pattern(consts, layout, rs)
+                    rows, vs = bf_scan(g, p)
+                    t = O.scan(g, p)
+                    assert t.vars == vs, (p, t.vars, vs)
+                    assert _rows(t) == rows, (p, _rows(t), rows)
+                    f = O.scan_flags(g, p)
+                    assert int(f.sum()) == len(rows)
+
+
+def check_exhaustive_join(O, ids=4):
+    """Joins on every column pair of a set of tiny tables, both oracle join
+    methods, against brute force; includes empty tables."""
+    g = tiny_graph(7, 14, ids)
+    pats = [pat("?a ? ?b"), pat("?a 1 ?b"), pat("?a ?b 2"), pat("3 ?a ?b"), pat("?a ?b ?c"),
+            pat("?a 4 ?a"), pat("4 4 ?a")]
+    tabs = [O.scan(g, p) for p in pats]
+    for L, R in itertools.product(tabs, repeat=2):
+        for lc in range(L.ncols):
+            for rc in range(R.ncols):
+                want = bf_join(_rows(L), lc, _rows(R), rc)
+                for method in ("nested", "sortmerge"):
+                    j = O.join(L, lc, R, rc, method)
+                    assert _rows(j) == want, (method, lc, rc)
+                    assert j.vars == L.vars + [v for i, v in enumerate(R.vars) if i != rc]
+
+
+def check_table3_matrix(O, ids=3):
+    """The nine relation types of Table 3, each with every choice of its four
+    constants from 1..ids, as scan-scan-join plans against brute force."""
+    gd = _gold("table3_reltypes.json")
+    g = np.concatenate([tiny_graph(11, 20, ids), tiny_graph(12, 6, ids)])
+    nonempty = {}
+    for name, (qi, qj) in gd["types"].items():
+        const_names = [t for t in qi + qj if not t.startswith("?")]
+        for vals in itertools.product(range(1, ids + 1), repeat=len(const_names)):
+            env = dict(zip(const_names, vals))
+            def mk(q):
+                return Pattern(*[env.get(t, 0) for t in q],
+                               *[0 if t == "?V" else -1 for t in q])
+            plan = Plan().scan(mk(qi)).scan(mk(qj)).join(0)
+            want, wv = bf_query(g, plan)
+            got = O.query(g, plan)
+            assert _rows(got) == want and got.vars == wv, (name, env)
+            nonempty[name] = nonempty.get(name, 0) + (len(want) > 0)
+    assert all(v > 0 for v in nonempty.values()), nonempty
+
+
+def check_union_listing4(O):
+    """Sec. 4.1: one triple can answer two subqueries (Listing 4 shape
+    '{C ?v0 ?v1} UNION {?v2 P ?v3}').  Without DISTINCT it appears under both
+    subqueries; the outer-union schema fills unbound variables with 0."""
+    C, P = 5, 9
+    g = np.array([[C, P, 1], [C, 2, 3], [4, P, 6], [7, 8, 9], [C, P, 1]], dtype=np.uint32)
+    a = O.scan(g, Pattern(C, 0, 0, -1, 0, 1))
+    b = O.scan(g, Pattern(0, P, 0, 2, -1, 3))
+    u = O.union([a, b], False)
+    assert u.vars == [0, 1, 2, 3]
+    assert _rows(u) == [(P, 1, 0, 0), (2, 3, 0, 0), (P, 1, 0, 0),
+                        (0, 0, C, 1), (0, 0, 4, 6), (0, 0, C, 1)]
+    # same schema: the triple (C,P,1) answers '?s P ?o' and '?s ? ?o' with o in
+    # [1,2); without DISTINCT it appears under both, with DISTINCT once
+    a2 = O.scan(g, Pattern(0, P, 0, 0, -1, 1))
+    b2 = O.scan(g, Pattern(0, 0, 0, 0, -1, 1, range_pos=2, lo=1, hi=2))
+    assert _rows(O.union([a2, b2], False)) == [(C, 1), (4, 6), (C, 1), (C, 1), (C, 1)]
+    assert _rows(O.union([a2, b2], True)) == [(4, 6), (C, 1)]
+    # a narrower schema is padded with 0 before rows are compared
+    b3 = O.scan(g, Pattern(0, 0, 1, 0, -1, -1))
+    u3 = O.union([a2, b3], True)
+    want, _ = bf_union([(_rows(a2), a2.vars), (_rows(b3), b3.vars)], True)
+    assert _rows(u3) == want
+    assert _rows(u3) == sorted({(C, 1), (4, 6), (C, 0)})
+
+
+def check_scan_multi_bruteforce(O):
+    """Sec. 4.1: the membership of triple i lists exactly the subqueries it
+    answers (bit j set iff triple i matches pattern j)."""
+    from bruteforce import bf_match
+    g = tiny_graph(21, 25, 3)
+    pats = [Pattern(*c) for c in itertools.product(range(4), repeat=3)][:40]
+    member = O.scan_multi(g, pats)
+    for i, t in enumerate(g):
+        want = 0
+        for j, p in enumerate(pats):
+            if bf_match(t, p):
+                want |= 1 << j
+        assert int(member[i]) == want, (i, hex(int(member[i])), hex(want))
+
+
+def check_union_bruteforce(O):
+    g = tiny_graph(3, 16, 4)
+    pats = [pat("?a 1 ?b"), pat("?b 2 ?a"), pat("?a ?c 3"), pat("?c ? ?c"), pat("? ? ?")]
+    tabs = [O.scan(g, p) for p in pats]
+    for k in (1, 2, 3, 5):
+        for combo in itertools.combinations(range(len(tabs)), k):
+            ins = [tabs[i] for i in combo]
+            for d in (False, True):
+                want, wv = bf_union([(_rows(t), t.vars) for t in ins], d)
+                got = O.union(ins, d)
+                assert got.vars == wv
+                assert _rows(got) == want, (combo, d)
+
+
+def check_filter_bruteforce(O):
+    g = tiny_graph(5, 30, 6)
+    t = O.scan(g, pat("?a ?b ?c"))
+    for col in range(3):
+        for lo in range(0, 8):
+            for hi in range(0, 8):
+                want = bf_filter(_rows(t), col, lo, hi)
+                assert _rows(O.filter(t, col, lo, hi)) == want, (col, lo, hi)
+
+
+def random_plan(rng, ids=4):
+    """A random postfix plan of 1..3 patterns over variables 0..2."""
+    def rpat():
+        while True:
+            consts = [int(rng.integers(0, ids + 1)) if rng.random() < 0.4 else 0
+                      for _ in range(3)]
+            vs = [int(rng.integers(0, 3)) if c == 0 else -1 for c in consts]
+            if any(v >= 0 for v in vs):
+                return Pattern(*consts, *vs)
+    plan = Plan()
+    p = rpat()
+    plan.scan(p)
+    schema = set(p.out_vars())
+    for _ in range(int(rng.integers(0, 3))):
+        q = rpat()
+        shared = schema & set(q.out_vars())
+        if shared and rng.random() < 0.6:
+            plan.scan(q).join(sorted(shared)[0])
+            schema |= set(q.out_vars())
+        else:
+            plan.scan(q).union(2, bool(rng.integers(0, 2)))
+            schema |= set(q.out_vars())
+    if rng.random() < 0.4:
+        v = sorted(schema)[0]
+        plan.filter(v, int(rng.integers(0, 3)), int(rng.integers(2, 6)))
+    if rng.random() < 0.4:
+        keep = sorted(schema)[: int(rng.integers(1, len(schema) + 1))]
+        plan.project(keep)
+    if rng.random() < 0.4:
+        plan.distinct()
+    return plan
+
+
+def check_random_plans(O, n=300, seed=99):
+    rng = np.random.default_rng(seed)
+    for i in range(n):
+        g = tiny_graph(1000 + i, int(rng.integers(0, 16)), 4)
+        plan = random_plan(rng)
+        want, wv = bf_query(g, plan)
+        got = O.query(g, plan)
+        assert got.vars == wv and _rows(got) == want, (i, plan)
+
+
+# ---------------------------------------------------------------------------
+# invariants at size (independent numpy arithmetic)
+# ---------------------------------------------------------------------------
+
+def check_invariants_small_config(O, g):
+    N = g.shape[0]
+    # sum over predicates of |scan(?, p, ?)| = N, and per-p counts = histogram
+    hist = np.bincount(g[:, 1])
+    total = 0
+    for p in np.nonzero(hist)[0]:
+        t = O.scan(g, Pattern(0, int(p), 0, 0, -1, 1))
+        assert t.nrows == hist[p]
+        total += t.nrows
+    assert total == N
+    # scan result = the matching rows of the input, in position order
+    t = O.scan(g, pat("?s 7 ?o"))
+    sel = g[g[:, 1] == 7]
+    assert np.array_equal(t.rows, sel[:, [0, 2]])
+    # |L join R| = sum_k cL(k) cR(k)
+    L = O.scan(g, pat("?s 3 ?o1"))
+    R = O.scan(g, pat("?s 11 ?o2"))
+    cl = np.bincount(L.rows[:, 0], minlength=10_001).astype(np.int64)
+    cr = np.bincount(R.rows[:, 0], minlength=10_001).astype(np.int64)
+    j1 = O.join(L, 0, R, 0, "nested")
+    j2 = O.join(L, 0, R, 0, "sortmerge")
+    assert j1.nrows == int((cl * cr).sum())
+    assert np.array_equal(j1.rows, j2.rows)
+    # output rows are in strict lexicographic order up to duplicates
+    r = j1.rows.astype(np.int64)
+    key = (r[:, 0] << 40) | (r[:, 1] << 20) | r[:, 2]
+    assert np.all(np.diff(key) >= 0)
+    # union with DISTINCT = set union
+    a = O.scan(g, pat("?s 7 ?o"))
+    b = O.scan(g, pat("?s 8 ?o"))
+    u = O.union([a, b], True)
+    want = sorted(set(map(tuple, a.rows.tolist())) | set(map(tuple, b.rows.tolist())))
+    assert _rows(u) == want
+    # filter: idempotent, monotone, empty when lo >= hi
+    f = O.filter(a, 1, 100, 5000)
+    assert np.array_equal(O.filter(f, 1, 100, 5000).rows, f.rows)
+    wide = O.filter(a, 1, 50, 9000)
+    assert set(map(tuple, f.rows.tolist())) <= set(map(tuple, wide.rows.tolist()))
+    assert O.filter(a, 1, 5000, 100).nrows == 0
+    # fused range in the scan = scan then filter
+    fs = O.scan(g, Pattern(0, 7, 0, 0, -1, 1, range_pos=2, lo=100, hi=5000))
+    assert np.array_equal(fs.rows, f.rows)
+    # star on ?s: |result| = sum_s prod_i c_i(s)
+    n = {}
+    plan = (Plan().scan(pat("?s 3 ?a", n)).scan(pat("?s 11 ?b", n)).join(n["?s"])
+            .scan(pat("?s 20 ?c", n)).join(n["?s"]))
+    q = O.query(g, plan)
+    c3 = np.bincount(O.scan(g, pat("?s 20 ?c")).rows[:, 0], minlength=10_001).astype(np.int64)
+    assert q.nrows == int((cl * cr * c3).sum())
+
+
+def check_invariants_tiny_config(O):
+    from synth import CONFIGS, make_graph
+    check_invariants_small_config(O, make_graph(CONFIGS["small"].with_n(20_000)))
+
+
+ALL_CHECKS = [check_rule11, check_toy_sec3, check_exhaustive_scan, check_exhaustive_join,
+              check_table3_matrix, check_union_listing4, check_scan_multi_bruteforce,
+              check_union_bruteforce, check_filter_bruteforce, check_random_plans,
+              check_invariants_tiny_config]
