@@ -1,0 +1,203 @@
+/*
+ * tid.h -- C ABI of libtid.so, the MI355X (gfx950) TripleID-Q query library.
+ *
+ * The method (Chantrapornchai & Choksuchat, "TripleID-Q: RDF Query Processing
+ * Framework using GPU"): an RDF graph is dictionary-encoded into rows of three
+ * 32-bit IDs (subject, predicate, object) -- the TripleID form of Sec. 3 --
+ * and kept in GPU memory; a triple pattern is answered by testing every triple
+ * in parallel with no index (Sec. 3, Algorithm 1, GPUSearch), and subquery
+ * results are combined by union (Sec. 4.1), join on a shared variable
+ * (Sec. 4.2, Table 3), filter, projection and DISTINCT (Sec. 4.3, Fig. 6).
+ *
+ * Conventions for every call:
+ *  - Status: each call returns a tid_status; TID_OK (0) on success, a negative
+ *    code otherwise.  On error no output handle is written and no device
+ *    memory stays owned by the failed call; tid_last_error() describes it.
+ *  - IDs: ID 0 is reserved for the free variable "?" (Sec. 3); graph triples
+ *    must hold IDs in [1, 2^32-1].  One ID space is shared by all positions.
+ *  - Device and stream: a context is bound to one device and one HIP stream.
+ *    Every call enqueues its work on that stream and returns without waiting,
+ *    except where a result count must reach the host (noted per call).
+ *  - Ownership: the library owns every handle it returns; the caller releases
+ *    it with the matching *_free.  Inputs are borrowed for the duration of the
+ *    call only (tid_load copies the triples).  Handles must be released before
+ *    their context is destroyed.
+ *  - Threading: one host thread at a time per context.
+ *  - There is no CPU fallback: every step runs in the library's HIP kernels.
+ */
+#ifndef TRIPLEID_TID_H
+#define TRIPLEID_TID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tid_status;
+#define TID_OK             0
+#define TID_E_INVALID_ARG (-1)  /* bad argument, pattern, plan or reserved ID 0 in a triple */
+#define TID_E_OOM         (-2)  /* the allocator returned NULL */
+#define TID_E_CAPACITY    (-3)  /* a result outgrew its buffer and retry is switched off */
+#define TID_E_UNSUPPORTED (-4)  /* a valid request this build does not handle */
+#define TID_E_SCHEMA      (-5)  /* a variable named by a plan or join is not in the table */
+#define TID_E_HIP         (-6)  /* a HIP runtime call failed */
+#define TID_E_INTERNAL    (-7)  /* a kernel reported an inconsistency (a bug) */
+
+#define TID_MAX_COLS 32         /* widest table */
+#define TID_MAX_MULTI 16        /* patterns per multi-pattern pass */
+
+typedef struct tid_ctx tid_ctx;
+typedef struct tid_graph tid_graph;
+typedef struct tid_table tid_table;
+
+/* Device-memory callbacks.  alloc returns a device pointer of at least
+   `bytes` usable in stream order on `stream`, or NULL; free releases it.  Pass
+   NULL for both to use the library's own caching pool over hipMalloc. */
+typedef void *(*tid_alloc_fn)(void *user, size_t bytes, void *stream);
+typedef void (*tid_free_fn)(void *user, void *ptr, size_t bytes, void *stream);
+
+/* ---- context --------------------------------------------------------- */
+
+/* Create a context on HIP device `device`, enqueueing on `stream` (a
+   hipStream_t; NULL means the library creates and owns a stream). */
+tid_status tid_ctx_create(int device, void *stream, tid_alloc_fn alloc, tid_free_fn free_fn,
+                          void *user, tid_ctx **out);
+void tid_ctx_destroy(tid_ctx *ctx);
+/* Text of the last error on this context ("" if none); valid until the next call. */
+const char *tid_last_error(const tid_ctx *ctx);
+/* Wait for all work enqueued by this context. */
+tid_status tid_ctx_synchronize(tid_ctx *ctx);
+/* Tuning and test options, by name:
+     "capacity_override"  >0: force every scan/filter output buffer to this many
+                          rows (forces the overflow path in tests); 0 = off
+     "retry"              1 (default): on overflow, resize and run again;
+                          0: return TID_E_CAPACITY instead
+     "scan_items"         triples per thread in the scan kernel (autotuner)
+     "scan_block"         threads per workgroup in the scan kernel (autotuner)
+     "stage_words"        LDS words per workgroup for staging compacted rows
+                          (0 = default, at most 16384) */
+tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value);
+tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value);
+
+/* ---- graph (Sec. 3: the TripleID array kept in GPU memory) ----------- */
+
+/* Copy n triples, row-major (s,p,o) uint32 (12 bytes per triple, the TripleID
+   file layout), into device memory owned by the new graph.  `triples` is a
+   host pointer (src_on_device = 0) or a device pointer on the context's device
+   (src_on_device = 1).  Rejects any triple holding ID 0 with TID_E_INVALID_ARG.
+   Builds per-position ID histograms used to size scan outputs.  Synchronises. */
+tid_status tid_load(tid_ctx *ctx, const uint32_t *triples, uint64_t n, int src_on_device,
+                    tid_graph **out);
+/* Same, reading a raw TripleID file (n x 12 bytes, little-endian, no header). */
+tid_status tid_load_file(tid_ctx *ctx, const char *path, tid_graph **out);
+/* Number of triples and the device address of the resident array. */
+tid_status tid_graph_info(const tid_graph *g, uint64_t *n, const uint32_t **device_triples);
+void tid_graph_free(tid_graph *g);
+
+/* ---- triple pattern (Sec. 3: key with 0 as "?") ----------------------- */
+
+typedef struct {
+    uint32_t s, p, o;     /* constant ID >= 1, or 0 = free position */
+    int32_t vs, vp, vo;   /* variable id (>= 0) naming a free position, or -1:
+                             free and not projected.  A bound position must
+                             carry -1.  Free positions sharing an id must hold
+                             equal values. */
+    int32_t range_pos;    /* -1, or the position (0 s, 1 p, 2 o) whose value must
+                             lie in [lo, hi); lo >= hi matches nothing */
+    uint32_t lo, hi;
+} tid_pattern;
+
+/* ---- tables ----------------------------------------------------------- */
+/* A table is ncols device columns of uint32 (one per variable), nrows rows.
+   Column c holds variable vars[c]; 0 marks an unbound cell after a union. */
+
+/* Row count, column count and variable ids (vars must hold TID_MAX_COLS
+   entries; may be NULL).  Synchronises if the count is still on the device. */
+tid_status tid_table_info(tid_ctx *ctx, tid_table *t, uint64_t *nrows, int32_t *ncols,
+                          int32_t *vars);
+/* Device address of column `col` (valid while the table lives). */
+tid_status tid_table_column(const tid_table *t, int32_t col, const uint32_t **device_ptr);
+/* Copy the rows to host memory, row-major (nrows x ncols uint32).  Fails with
+   TID_E_CAPACITY if cap_rows < nrows.  Synchronises. */
+tid_status tid_table_to_host(tid_ctx *ctx, tid_table *t, uint32_t *host_rowmajor,
+                             uint64_t cap_rows);
+/* Build a table from caller data: ncols columns, each a pointer to nrows
+   uint32 on the host (on_device = 0) or on the device (on_device = 1); the
+   data is copied. */
+tid_status tid_table_from_columns(tid_ctx *ctx, const uint32_t *const *cols, int32_t ncols,
+                                  const int32_t *vars, uint64_t nrows, int on_device,
+                                  tid_table **out);
+void tid_table_free(tid_table *t);
+
+/* ---- operators -------------------------------------------------------- */
+
+/* Sec. 3 (GPUSearch, Algorithm 1): every triple is tested against the pattern;
+   the bindings of the matching triples are returned in ascending triple
+   position.  Output columns: the distinct variable ids of the pattern in
+   s, p, o order (none if all free positions carry -1: the table then only
+   counts matches). */
+tid_status tid_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pattern,
+                    tid_table **out);
+/* Sec. 4.1 (keysArray / positionArray[i].query): k <= TID_MAX_MULTI patterns
+   answered in one pass over the graph; outs[j] receives exactly what
+   tid_scan would return for patterns[j]. */
+tid_status tid_scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *patterns,
+                          int32_t k, tid_table **outs);
+/* Sec. 4.3 (FILTER, here on an ID range): the rows with lo <= row[col] < hi,
+   in input order.  lo >= hi gives an empty table. */
+tid_status tid_filter(tid_ctx *ctx, const tid_table *t, int32_t col, uint32_t lo, uint32_t hi,
+                      tid_table **out);
+/* Sec. 4.2 (join on the shared variable; any of the Table 3 position pairs):
+   the inner equi-join of l and r on l[lcol] = r[rcol].  Output columns are
+   l's columns followed by r's columns without rcol; rows are returned in
+   lexicographic order over all output columns.  algo: 0 automatic, 1 hash
+   join, 2 sort-merge join (same result).  Synchronises (output size). */
+tid_status tid_join(tid_ctx *ctx, const tid_table *l, int32_t lcol, const tid_table *r,
+                    int32_t rcol, int32_t algo, tid_table **out);
+/* Sec. 4.1 and Sec. 4.3 (union, DISTINCT): the schema is the ordered union of
+   the inputs' variable ids (first appearance first), unbound cells are 0.
+   dedupe = 0: the rows of ts[0], then ts[1], ... ; dedupe = 1: the distinct
+   rows in lexicographic order.  Synchronises when dedupe = 1. */
+tid_status tid_union(tid_ctx *ctx, const tid_table *const *ts, int32_t k, int32_t dedupe,
+                     tid_table **out);
+/* Lexicographic row order (the canonical order of query results); distinct = 1
+   also drops repeated rows (Sec. 4.3, DISTINCT).  Synchronises. */
+tid_status tid_sort(tid_ctx *ctx, const tid_table *t, int32_t distinct, tid_table **out);
+
+/* ---- query plans (Sec. 4.3, Fig. 6) ----------------------------------- */
+
+/* Postfix op words (uint32):
+     TID_OP_SCAN i              push the bindings of patterns[i]
+     TID_OP_JOIN v              pop R, pop L; push the join of L and R on variable
+                                v; every other variable both hold must also
+                                agree and is kept once
+     TID_OP_UNION k d           pop k tables; push their union (d = 1: distinct)
+     TID_OP_FILTER v lo hi      keep rows with lo <= v < hi
+     TID_OP_PROJECT n v1..vn    keep variables v1..vn in that order
+     TID_OP_DISTINCT            drop repeated rows
+   Exactly one table must remain; it is returned in lexicographic row order. */
+#define TID_OP_SCAN 1
+#define TID_OP_JOIN 2
+#define TID_OP_UNION 3
+#define TID_OP_FILTER 4
+#define TID_OP_PROJECT 5
+#define TID_OP_DISTINCT 6
+
+typedef struct {
+    int32_t n_patterns;
+    const tid_pattern *patterns;
+    int32_t n_ops;
+    const uint32_t *ops;
+} tid_plan;
+
+/* Evaluate a plan: all its patterns in one pass over the graph, then its
+   joins, unions, filters, projections and DISTINCT on the device.
+   Synchronises (intermediate sizes). */
+tid_status tid_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan, tid_table **out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,188 @@
+// internal.hpp -- host-side runtime structures of libtid (context, device
+// buffers, graphs, tables, error plumbing).  Included by every .hip file.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/tid.h"
+
+namespace tid {
+
+// An error carrying a tid_status; thrown inside the library and turned into a
+// return code at the C boundary.
+struct Error : std::runtime_error {
+    tid_status code;
+    Error(tid_status c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define TID_HIP(call)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            throw ::tid::Error(TID_E_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define TID_REQUIRE(cond, code, msg)                        \
+    do {                                                    \
+        if (!(cond)) throw ::tid::Error((code), (msg));     \
+    } while (0)
+
+// Size-class caching pool over hipMalloc, used when the caller gives no
+// allocator.  Blocks are reused in stream order on the context's one stream,
+// so a freed block may be handed out again at once.
+class Pool {
+  public:
+    ~Pool();
+    void *alloc(size_t bytes);
+    void free(void *p, size_t bytes);
+    void release_all();
+
+  private:
+    static size_t size_class(size_t bytes);
+    std::multimap<size_t, void *> free_;
+    std::map<void *, size_t> live_;
+};
+
+struct Options {
+    int64_t capacity_override = 0;
+    int64_t retry = 1;
+    int64_t scan_items = 0;   // 0 = built-in default
+    int64_t scan_block = 0;
+    int64_t stage_words = 0;  // LDS staging words per workgroup (0 = default)
+};
+
+}  // namespace tid
+
+struct tid_ctx {
+    int device = 0;
+    int num_cus = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    tid_alloc_fn alloc_fn = nullptr;
+    tid_free_fn free_fn = nullptr;
+    void *user = nullptr;
+    tid::Pool pool;
+    std::string last_error;
+    tid::Options opt;
+    uint64_t *host_counts = nullptr;  // pinned host words for count readback
+    // scratch for look-back state: grown on demand, owned by the context
+    void *lb_state = nullptr;
+    size_t lb_bytes = 0;
+    uint32_t *d_flags = nullptr;      // device error/overflow flags (2 words)
+
+    void *alloc(size_t bytes);
+    void free(void *p, size_t bytes);
+    void *lookback_state(size_t bytes);  // all zero between kernels
+    void sync();
+};
+
+namespace tid {
+
+// RAII device allocation through the context's allocator.
+class DevBuf {
+  public:
+    DevBuf() = default;
+    DevBuf(tid_ctx *c, size_t bytes) : ctx_(c), bytes_(bytes) {
+        if (bytes) ptr_ = c->alloc(bytes);
+    }
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        reset();
+        ctx_ = o.ctx_;
+        ptr_ = o.ptr_;
+        bytes_ = o.bytes_;
+        o.ptr_ = nullptr;
+        o.bytes_ = 0;
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (ptr_ && ctx_) ctx_->free(ptr_, bytes_);
+        ptr_ = nullptr;
+        bytes_ = 0;
+    }
+    template <class T = void> T *get() const { return static_cast<T *>(ptr_); }
+    size_t bytes() const { return bytes_; }
+    void *release() {
+        void *p = ptr_;
+        ptr_ = nullptr;
+        bytes_ = 0;
+        return p;
+    }
+
+  private:
+    tid_ctx *ctx_ = nullptr;
+    void *ptr_ = nullptr;
+    size_t bytes_ = 0;
+};
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+}  // namespace tid
+
+// Per-position ID histograms kept on the host as cumulative counts:
+// cdf[x][id] = number of triples whose position x holds an ID < id.  Used to
+// bound scan output sizes without a device round trip.
+struct tid_graph {
+    tid_ctx *ctx = nullptr;
+    uint64_t n = 0;
+    tid::DevBuf data;                 // n*12 bytes (+ padding), AoS s,p,o
+    std::vector<uint64_t> cdf[3];     // empty if the position's max ID is too large
+    uint32_t max_id[3] = {0, 0, 0};
+    // number of triples with lo <= position value < hi (n if no histogram)
+    uint64_t count_in(int pos, uint64_t lo, uint64_t hi) const;
+};
+
+struct tid_table {
+    tid_ctx *ctx = nullptr;
+    int32_t ncols = 0;
+    int32_t vars[TID_MAX_COLS] = {};
+    uint64_t cap = 0;                 // rows allocated per column
+    uint64_t nrows = 0;               // valid when count_known
+    bool count_known = false;
+    tid::DevBuf block;                // columns (each align_up(cap*4)) + 8-byte device count
+    uint32_t *col[TID_MAX_COLS] = {};
+    uint64_t *d_count = nullptr;
+
+    uint64_t rows();                  // host row count (may synchronise)
+};
+
+namespace tid {
+
+// Allocate a table with `cap` rows per column and the given schema; the
+// device count word is not initialised.
+std::unique_ptr<tid_table> make_table(tid_ctx *ctx, int32_t ncols, const int32_t *vars,
+                                      uint64_t cap);
+// Read a batch of device counts into table->nrows with one synchronisation;
+// also checks the device error flag.
+void resolve_counts(tid_ctx *ctx, tid_table *const *ts, int k);
+// Write a known row count to the table's device word and host copy.
+void set_count(tid_ctx *ctx, tid_table *t, uint64_t n);
+
+// ---- launchers implemented in the .hip files ------------------------------
+
+struct CompiledPattern;  // scan.hip
+
+// Scan: fill `outs[j]` for k patterns in one pass.  Tables are allocated here.
+void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+                std::unique_ptr<tid_table> *outs);
+std::unique_ptr<tid_table> filter_range(tid_ctx *ctx, const tid_table *t, int col, uint32_t lo,
+                                        uint32_t hi);
+// validate and return the schema of a pattern; throws on a malformed pattern
+int pattern_schema(const tid_pattern &p, int32_t *vars, int32_t *src);
+// per-position histograms (device) -> host cdf
+void build_stats(tid_ctx *ctx, tid_graph *g);
+void check_no_zero(tid_ctx *ctx, const tid_graph *g);
+
+}  // namespace tid

@@ -1,0 +1,306 @@
+// runtime.hip -- context, device memory, tables, graph load and load-time
+// statistics of libtid.
+#include "device_common.hpp"
+#include "internal.hpp"
+
+#include <algorithm>
+#include <cstdio>
+
+namespace tid {
+
+// ---------------------------------------------------------------------------
+// caching pool
+// ---------------------------------------------------------------------------
+
+size_t Pool::size_class(size_t bytes) {
+    if (bytes <= 4096) return 4096;
+    // round to 1/8 of the next power of two: at most 12.5% slack
+    size_t p = 1;
+    while (p < bytes) p <<= 1;
+    size_t step = std::max<size_t>(p / 8, 4096);
+    return (bytes + step - 1) / step * step;
+}
+
+void *Pool::alloc(size_t bytes) {
+    const size_t sz = size_class(bytes);
+    auto it = free_.lower_bound(sz);
+    if (it != free_.end() && it->first <= sz + sz / 4) {
+        void *p = it->second;
+        live_[p] = it->first;
+        free_.erase(it);
+        return p;
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        release_all();  // give cached blocks back and try once more
+        if (hipMalloc(&p, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    live_[p] = sz;
+    return p;
+}
+
+void Pool::free(void *p, size_t) {
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    free_.emplace(it->second, p);
+    live_.erase(it);
+}
+
+void Pool::release_all() {
+    for (auto &kv : free_) (void)hipFree(kv.second);
+    free_.clear();
+}
+
+Pool::~Pool() {
+    release_all();
+    for (auto &kv : live_) (void)hipFree(kv.first);
+    live_.clear();
+}
+
+// ---------------------------------------------------------------------------
+// tables
+// ---------------------------------------------------------------------------
+
+__global__ void set_u64(uint64_t *p, uint64_t v) { *p = v; }
+
+std::unique_ptr<tid_table> make_table(tid_ctx *ctx, int32_t ncols, const int32_t *vars,
+                                      uint64_t cap) {
+    TID_REQUIRE(ncols >= 0 && ncols <= TID_MAX_COLS, TID_E_SCHEMA, "table: too many columns");
+    auto t = std::make_unique<tid_table>();
+    t->ctx = ctx;
+    t->ncols = ncols;
+    for (int c = 0; c < ncols; ++c) t->vars[c] = vars[c];
+    t->cap = cap;
+    const size_t stride = align_up(std::max<uint64_t>(cap, 1) * sizeof(uint32_t));
+    const size_t bytes = stride * (size_t)ncols + kAlign;
+    t->block = DevBuf(ctx, bytes);
+    char *base = t->block.get<char>();
+    for (int c = 0; c < ncols; ++c) t->col[c] = reinterpret_cast<uint32_t *>(base + stride * c);
+    t->d_count = reinterpret_cast<uint64_t *>(base + stride * (size_t)ncols);
+    return t;
+}
+
+void set_count(tid_ctx *ctx, tid_table *t, uint64_t n) {
+    hipLaunchKernelGGL(set_u64, dim3(1), dim3(1), 0, ctx->stream, t->d_count, n);
+    TID_HIP(hipGetLastError());
+    t->nrows = n;
+    t->count_known = true;
+}
+
+void resolve_counts(tid_ctx *ctx, tid_table *const *ts, int k) {
+    constexpr int kSlots = 255;  // host_counts holds kSlots counts + the flags word
+    for (int start = 0; start < k; start += kSlots) {
+        const int m = std::min(kSlots, k - start);
+        int pending = 0;
+        for (int j = 0; j < m; ++j) {
+            tid_table *t = ts[start + j];
+            if (t->count_known) continue;
+            TID_HIP(hipMemcpyAsync(&ctx->host_counts[j], t->d_count, sizeof(uint64_t),
+                                   hipMemcpyDeviceToHost, ctx->stream));
+            ++pending;
+        }
+        if (!pending) continue;
+        TID_HIP(hipMemcpyAsync(&ctx->host_counts[kSlots], ctx->d_flags, sizeof(uint64_t),
+                               hipMemcpyDeviceToHost, ctx->stream));
+        TID_HIP(hipStreamSynchronize(ctx->stream));
+        const uint32_t err = (uint32_t)(ctx->host_counts[kSlots] & 0xFFFFFFFFu);
+        TID_REQUIRE(err == 0, TID_E_INTERNAL,
+                    "a look-back wait exceeded its spin bound (device state inconsistent)");
+        for (int j = 0; j < m; ++j) {
+            tid_table *t = ts[start + j];
+            if (t->count_known) continue;
+            t->nrows = ctx->host_counts[j];
+            t->count_known = true;
+        }
+    }
+}
+
+std::unique_ptr<tid_table> copy_columns(tid_ctx *ctx, const uint32_t *const *cols, int32_t ncols,
+                                        const int32_t *vars, uint64_t nrows, int on_device) {
+    auto t = make_table(ctx, ncols, vars, nrows);
+    for (int c = 0; c < ncols; ++c) {
+        TID_REQUIRE(nrows == 0 || cols[c], TID_E_INVALID_ARG, "null column");
+        if (nrows)
+            TID_HIP(hipMemcpyAsync(t->col[c], cols[c], nrows * sizeof(uint32_t),
+                                   on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                   ctx->stream));
+    }
+    set_count(ctx, t.get(), nrows);
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// load-time checks and statistics
+// ---------------------------------------------------------------------------
+
+// per position minimum and maximum ID (mm[0..2] = min, mm[3..5] = max)
+__global__ void minmax_kernel(const uint32_t *__restrict__ g, uint64_t n, uint32_t *mm) {
+    uint32_t lo[3] = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu}, hi[3] = {0, 0, 0};
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            uint32_t v = g[3 * i + x];
+            lo[x] = min(lo[x], v);
+            hi[x] = max(hi[x], v);
+        }
+    }
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+        for (int d = 32; d >= 1; d >>= 1) {
+            lo[x] = min(lo[x], (uint32_t)__shfl_xor((int)lo[x], d, 64));
+            hi[x] = max(hi[x], (uint32_t)__shfl_xor((int)hi[x], d, 64));
+        }
+    }
+    if (dev::lane_id() == 0) {
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            atomicMin(&mm[x], lo[x]);
+            atomicMax(&mm[3 + x], hi[x]);
+        }
+    }
+}
+
+__global__ void init_minmax(uint32_t *mm) {
+    if (threadIdx.x < 3) mm[threadIdx.x] = 0xFFFFFFFFu;
+    else if (threadIdx.x < 6) mm[threadIdx.x] = 0u;
+}
+
+// histogram of one position; small ID ranges are counted in LDS first
+template <int LDS_BINS>
+__global__ void hist_kernel(const uint32_t *__restrict__ g, uint64_t n, int pos, uint32_t nbins,
+                            uint32_t *hist) {
+    __shared__ uint32_t s_h[LDS_BINS > 0 ? LDS_BINS : 1];
+    if (LDS_BINS > 0) {
+        for (uint32_t b = threadIdx.x; b < nbins; b += blockDim.x) s_h[b] = 0;
+        __syncthreads();
+    }
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t v = g[3 * i + pos];
+        if (LDS_BINS > 0)
+            atomicAdd(&s_h[v], 1u);
+        else
+            atomicAdd(&hist[v], 1u);
+    }
+    if (LDS_BINS > 0) {
+        __syncthreads();
+        for (uint32_t b = threadIdx.x; b < nbins; b += blockDim.x)
+            if (s_h[b]) atomicAdd(&hist[b], s_h[b]);
+    }
+}
+
+constexpr uint32_t kMaxHistIds = 1u << 28;  // 1 GiB of uint32 counts per position
+
+void build_stats(tid_ctx *ctx, tid_graph *g) {
+    if (g->n == 0) return;
+    DevBuf mm(ctx, 6 * sizeof(uint32_t));
+    hipLaunchKernelGGL(init_minmax, dim3(1), dim3(64), 0, ctx->stream, mm.get<uint32_t>());
+    const int blocks = (int)std::min<uint64_t>((g->n + 255) / 256, 4096);
+    hipLaunchKernelGGL(minmax_kernel, dim3(blocks), dim3(256), 0, ctx->stream,
+                       g->data.get<const uint32_t>(), g->n, mm.get<uint32_t>());
+    TID_HIP(hipGetLastError());
+    uint32_t h[6];
+    TID_HIP(hipMemcpyAsync(h, mm.get(), sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    TID_HIP(hipStreamSynchronize(ctx->stream));
+    for (int x = 0; x < 3; ++x)
+        TID_REQUIRE(h[x] != 0, TID_E_INVALID_ARG,
+                    "load: ID 0 is reserved for the free variable and may not appear in a triple");
+    if (g->n >= (1ull << 32)) return;  // counts would not fit the uint32 bins
+    for (int x = 0; x < 3; ++x) {
+        g->max_id[x] = h[3 + x];
+        if (h[3 + x] >= kMaxHistIds) continue;
+        const uint32_t nbins = h[3 + x] + 1;
+        DevBuf hist(ctx, (size_t)nbins * sizeof(uint32_t));
+        TID_HIP(hipMemsetAsync(hist.get(), 0, (size_t)nbins * sizeof(uint32_t), ctx->stream));
+        const int hb = (int)std::min<uint64_t>((g->n + 1023) / 1024, 8192);
+        if (nbins <= 8192)
+            hipLaunchKernelGGL((hist_kernel<8192>), dim3(hb), dim3(1024), 0, ctx->stream,
+                               g->data.get<const uint32_t>(), g->n, x, nbins,
+                               hist.get<uint32_t>());
+        else
+            hipLaunchKernelGGL((hist_kernel<0>), dim3(hb), dim3(1024), 0, ctx->stream,
+                               g->data.get<const uint32_t>(), g->n, x, nbins,
+                               hist.get<uint32_t>());
+        TID_HIP(hipGetLastError());
+        std::vector<uint32_t> hh(nbins);
+        TID_HIP(hipMemcpyAsync(hh.data(), hist.get(), (size_t)nbins * sizeof(uint32_t),
+                               hipMemcpyDeviceToHost, ctx->stream));
+        TID_HIP(hipStreamSynchronize(ctx->stream));
+        auto &c = g->cdf[x];
+        c.resize((size_t)nbins + 1);
+        c[0] = 0;
+        for (uint32_t b = 0; b < nbins; ++b) c[b + 1] = c[b] + hh[b];
+    }
+}
+
+}  // namespace tid
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+
+void *tid_ctx::alloc(size_t bytes) {
+    void *p = alloc_fn ? alloc_fn(user, bytes, (void *)stream) : pool.alloc(bytes);
+    if (!p) throw tid::Error(TID_E_OOM, "device allocation of " + std::to_string(bytes) +
+                                            " bytes failed");
+    return p;
+}
+
+void tid_ctx::free(void *p, size_t bytes) {
+    if (!p) return;
+    if (free_fn)
+        free_fn(user, p, bytes, (void *)stream);
+    else
+        pool.free(p, bytes);
+}
+
+// Look-back state shared by the context's kernels (one stream, so launches
+// never overlap).  Kernels leave it all zero when they finish; a new buffer is
+// cleared here once.
+void *tid_ctx::lookback_state(size_t bytes) {
+    if (lb_bytes < bytes) {
+        const size_t want = tid::align_up(std::max(bytes, lb_bytes + lb_bytes / 2), 4096);
+        if (lb_state) free(lb_state, lb_bytes);
+        lb_state = nullptr;
+        lb_bytes = 0;
+        lb_state = alloc(want);
+        lb_bytes = want;
+        TID_HIP(hipMemsetAsync(lb_state, 0, want, stream));
+    }
+    return lb_state;
+}
+
+void tid_ctx::sync() { TID_HIP(hipStreamSynchronize(stream)); }
+
+uint64_t tid_graph::count_in(int pos, uint64_t lo, uint64_t hi) const {
+    if (hi <= lo) return 0;
+    const auto &c = cdf[pos];
+    if (c.empty()) return n;
+    const uint64_t last = c.size() - 1;  // c[last] = n
+    const uint64_t a = std::min<uint64_t>(lo, last), b = std::min<uint64_t>(hi, last);
+    return c[b] - c[a];
+}
+
+namespace tid {
+int device_cus(tid_ctx *ctx) {
+    if (ctx->num_cus <= 0) {
+        int n = 0;
+        TID_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, ctx->device));
+        ctx->num_cus = n > 0 ? n : 1;
+    }
+    return ctx->num_cus;
+}
+}  // namespace tid
+
+uint64_t tid_table::rows() {
+    if (!count_known) {
+        tid_table *self = this;
+        tid::resolve_counts(ctx, &self, 1);
+    }
+    return nrows;
+}

@@ -1,0 +1,314 @@
+"""Python binding of libtid: argument marshalling over the C ABI only.
+
+Every function named tid_* here calls the C entry point of the same name;
+every step of the query path runs in the library's HIP kernels.  PyTorch
+supplies the device memory (its caching allocator, through the allocation
+callbacks) and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+
+class TidError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{L.STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(ctx_ptr, st: int):
+    if st != 0:
+        lib = L.load_library()
+        msg = lib.tid_last_error(ctx_ptr).decode() if ctx_ptr else ""
+        raise TidError(st, msg)
+
+
+def _pattern(p) -> L.tid_pattern:
+    return L.tid_pattern(int(p.s), int(p.p), int(p.o), int(p.vs), int(p.vp), int(p.vo),
+                         int(p.range_pos), int(p.lo), int(p.hi))
+
+
+class Context:
+    """A tid_ctx bound to one device and stream.
+
+    The context enqueues on `stream` (a torch.cuda.Stream); by default it makes
+    a stream of its own, so that its work never rides on the legacy default
+    stream.  allocator="torch" routes device memory through torch's caching
+    allocator on that stream; allocator="pool" uses the library's own pool."""
+
+    def __init__(self, device: int = 0, stream=None, allocator: str = "torch"):
+        import torch
+        lib = L.load_library()
+        self._torch = torch
+        self.device = int(device)
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        if int(self.stream.cuda_stream) == 0:
+            raise ValueError("pass a non-default stream (the legacy default stream has handle 0)")
+        sptr = ctypes.c_void_p(int(self.stream.cuda_stream))
+        if allocator == "torch":
+            dev = self.device
+
+            def _alloc(user, nbytes, stream):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+                except Exception:  # noqa: BLE001 - reported to the library as NULL (OOM)
+                    return None
+
+            def _free(user, ptr, nbytes, stream):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._cb = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
+        elif allocator == "pool":
+            self._cb = (L.ALLOC_FN(), L.FREE_FN())
+        else:
+            raise ValueError("allocator must be 'torch' or 'pool'")
+        out = ctypes.c_void_p()
+        st = lib.tid_ctx_create(self.device, sptr, self._cb[0], self._cb[1], None,
+                                ctypes.byref(out))
+        if st != 0:
+            raise TidError(st, "tid_ctx_create failed")
+        self._p = out
+        self._lib = lib
+        self._children: list = []
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_p", None):
+            self._lib.tid_ctx_synchronize(self._p)
+            self._lib.tid_ctx_destroy(self._p)
+            self._p = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def ptr(self):
+        return self._p
+
+    # -- options ------------------------------------------------------------
+    def set_option(self, key: str, value: int):
+        _check(self._p, self._lib.tid_ctx_set_option(self._p, key.encode(), int(value)))
+
+    def get_option(self, key: str) -> int:
+        v = ctypes.c_int64()
+        _check(self._p, self._lib.tid_ctx_get_option(self._p, key.encode(), ctypes.byref(v)))
+        return int(v.value)
+
+    def synchronize(self):
+        _check(self._p, self._lib.tid_ctx_synchronize(self._p))
+
+    # -- graph --------------------------------------------------------------
+    def load(self, triples) -> "Graph":
+        return tid_load(self, triples)
+
+    # -- operators -------------------------------------------------------------
+    def scan(self, g: "Graph", pattern) -> "Table":
+        return tid_scan(self, g, pattern)
+
+    def scan_multi(self, g: "Graph", patterns) -> List["Table"]:
+        return tid_scan_multi(self, g, patterns)
+
+    def filter(self, t: "Table", col: int, lo: int, hi: int) -> "Table":
+        return tid_filter(self, t, col, lo, hi)
+
+    def join(self, l: "Table", lcol: int, r: "Table", rcol: int, algo: int = 0) -> "Table":
+        return tid_join(self, l, lcol, r, rcol, algo)
+
+    def union(self, ts: Sequence["Table"], dedupe: bool) -> "Table":
+        return tid_union(self, ts, dedupe)
+
+    def sort(self, t: "Table", distinct: bool = False) -> "Table":
+        return tid_sort(self, t, distinct)
+
+    def query(self, g: "Graph", plan) -> "Table":
+        return tid_query(self, g, plan)
+
+    def table(self, rows: np.ndarray, vars_: Sequence[int]) -> "Table":
+        return tid_table_from_columns(self, rows, vars_)
+
+
+class Graph:
+    def __init__(self, ctx: Context, ptr):
+        self.ctx = ctx
+        self._p = ptr
+        n = ctypes.c_uint64()
+        d = ctypes.c_void_p()
+        _check(ctx.ptr, ctx._lib.tid_graph_info(ptr, ctypes.byref(n), ctypes.byref(d)))
+        self.n = int(n.value)
+        self.device_ptr = int(d.value or 0)
+
+    def free(self):
+        if self._p:
+            self.ctx._lib.tid_graph_free(self._p)
+            self._p = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            if self._p and self.ctx._p:
+                self.free()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Table:
+    def __init__(self, ctx: Context, ptr):
+        self.ctx = ctx
+        self._p = ptr
+
+    def info(self):
+        n = ctypes.c_uint64()
+        k = ctypes.c_int32()
+        vs = (ctypes.c_int32 * L.TID_MAX_COLS)()
+        _check(self.ctx.ptr, self.ctx._lib.tid_table_info(self.ctx.ptr, self._p, ctypes.byref(n),
+                                                          ctypes.byref(k), vs))
+        return int(n.value), int(k.value), [int(vs[i]) for i in range(k.value)]
+
+    @property
+    def nrows(self) -> int:
+        return self.info()[0]
+
+    @property
+    def ncols(self) -> int:
+        return self.info()[1]
+
+    @property
+    def vars(self) -> List[int]:
+        return self.info()[2]
+
+    def column_ptr(self, c: int) -> int:
+        d = ctypes.c_void_p()
+        _check(self.ctx.ptr, self.ctx._lib.tid_table_column(self._p, c, ctypes.byref(d)))
+        return int(d.value or 0)
+
+    def to_numpy(self) -> np.ndarray:
+        n, k, _ = self.info()
+        out = np.zeros((n, k), dtype=np.uint32)
+        if n and k:
+            _check(self.ctx.ptr, self.ctx._lib.tid_table_to_host(
+                self.ctx.ptr, self._p, out.ctypes.data_as(ctypes.c_void_p), n))
+        return out
+
+    def free(self):
+        if self._p:
+            self.ctx._lib.tid_table_free(self._p)
+            self._p = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            if self._p and self.ctx._p:
+                self.free()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+# ---------------------------------------------------------------------------
+# entry points, same names as the C ABI
+# ---------------------------------------------------------------------------
+
+def tid_load(ctx: Context, triples) -> Graph:
+    out = ctypes.c_void_p()
+    torch = ctx._torch
+    if isinstance(triples, torch.Tensor):
+        if triples.dtype not in (torch.int32, torch.uint32) or triples.dim() != 2 \
+                or triples.shape[1] != 3:
+            raise ValueError("triples must be an (N, 3) 32-bit tensor")
+        t = triples.contiguous()
+        on_dev = 1 if t.is_cuda else 0
+        _check(ctx.ptr, ctx._lib.tid_load(ctx.ptr, ctypes.c_void_p(t.data_ptr()), t.shape[0],
+                                          on_dev, ctypes.byref(out)))
+    else:
+        a = np.ascontiguousarray(triples, dtype=np.uint32)
+        if a.ndim != 2 or a.shape[1] != 3:
+            raise ValueError("triples must be an (N, 3) uint32 array")
+        _check(ctx.ptr, ctx._lib.tid_load(ctx.ptr, a.ctypes.data_as(ctypes.c_void_p),
+                                          a.shape[0], 0, ctypes.byref(out)))
+    return Graph(ctx, out)
+
+
+def tid_load_file(ctx: Context, path: str) -> Graph:
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_load_file(ctx.ptr, path.encode(), ctypes.byref(out)))
+    return Graph(ctx, out)
+
+
+def tid_scan(ctx: Context, g: Graph, pattern) -> Table:
+    out = ctypes.c_void_p()
+    q = _pattern(pattern)
+    _check(ctx.ptr, ctx._lib.tid_scan(ctx.ptr, g._p, ctypes.byref(q), ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+def tid_scan_multi(ctx: Context, g: Graph, patterns) -> List[Table]:
+    k = len(patterns)
+    arr = (L.tid_pattern * k)(*[_pattern(p) for p in patterns])
+    outs = (ctypes.c_void_p * k)()
+    _check(ctx.ptr, ctx._lib.tid_scan_multi(ctx.ptr, g._p, arr, k, outs))
+    return [Table(ctx, ctypes.c_void_p(outs[j])) for j in range(k)]
+
+
+def tid_filter(ctx: Context, t: Table, col: int, lo: int, hi: int) -> Table:
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_filter(ctx.ptr, t._p, int(col), int(lo), int(hi),
+                                        ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+def tid_join(ctx: Context, l: Table, lcol: int, r: Table, rcol: int, algo: int = 0) -> Table:
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_join(ctx.ptr, l._p, int(lcol), r._p, int(rcol), int(algo),
+                                      ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+def tid_union(ctx: Context, ts: Sequence[Table], dedupe: bool) -> Table:
+    k = len(ts)
+    arr = (ctypes.c_void_p * k)(*[t._p.value if isinstance(t._p, ctypes.c_void_p) else t._p
+                                  for t in ts])
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_union(ctx.ptr, arr, k, int(bool(dedupe)), ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+def tid_sort(ctx: Context, t: Table, distinct: bool = False) -> Table:
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_sort(ctx.ptr, t._p, int(bool(distinct)), ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+def tid_query(ctx: Context, g: Graph, plan) -> Table:
+    pats = (L.tid_pattern * max(1, len(plan.patterns)))(*[_pattern(p) for p in plan.patterns])
+    ops = np.ascontiguousarray(np.asarray(plan.ops, dtype=np.int64).astype(np.uint32))
+    cp = L.tid_plan(len(plan.patterns), pats, len(ops),
+                    ops.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_query(ctx.ptr, g._p, ctypes.byref(cp), ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+def tid_table_from_columns(ctx: Context, rows: np.ndarray, vars_: Sequence[int]) -> Table:
+    a = np.asarray(rows, dtype=np.uint32)
+    if a.ndim != 2:
+        raise ValueError("rows must be 2-D")
+    k = a.shape[1]
+    cols = [np.ascontiguousarray(a[:, c]) for c in range(k)]
+    ptrs = (ctypes.c_void_p * max(1, k))(*[c.ctypes.data for c in cols])
+    vs = (ctypes.c_int32 * max(1, k))(*[int(v) for v in vars_])
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_table_from_columns(ctx.ptr, ptrs, k, vs, a.shape[0], 0,
+                                                    ctypes.byref(out)))
+    return Table(ctx, out)

@@ -21,3 +21,32 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+@pytest.fixture(scope="session")
+def ctx():
+    """One library context on cuda:0 for the GPU tests (torch allocator)."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_01409_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+_GRAPHS = {}
+
+
+@pytest.fixture(scope="session")
+def graphs():
+    """Memoised synthetic graphs by (config name, n)."""
+    from synth import CONFIGS, make_graph
+
+    def get(name, n=None):
+        key = (name, n)
+        if key not in _GRAPHS:
+            spec = CONFIGS[name] if n is None else CONFIGS[name].with_n(n)
+            _GRAPHS[key] = make_graph(spec)
+        return _GRAPHS[key]
+    return get
