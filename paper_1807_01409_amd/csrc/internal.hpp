@@ -179,6 +179,11 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
                 std::unique_ptr<tid_table> *outs);
 std::unique_ptr<tid_table> filter_range(tid_ctx *ctx, const tid_table *t, int col, uint32_t lo,
                                         uint32_t hi);
+// columns of L and of R kept, in that order, in a join's output
+struct JoinPlan {
+    std::vector<int> lkeep, rkeep;
+};
+
 // validate and return the schema of a pattern; throws on a malformed pattern
 int pattern_schema(const tid_pattern &p, int32_t *vars, int32_t *src);
 // per-position histograms (device) -> host cdf

@@ -1,0 +1,432 @@
+// join.hip -- inner equi-join of two binding tables on one column pair
+// (Sec. 4.2: any of the nine relation types of Table 3 is a choice of the two
+// columns).  The paper sorts both key vectors, merge-joins them into pairs of
+// positions with equal keys, and gathers the value parts through those pairs.
+// Both algorithms here produce the pairs implicitly, as per-row match counts,
+// their exclusive scan (output offsets), and an expansion in which every
+// output row finds its (left, right) pair by binary search over the offsets:
+//   sort-merge  radix-sort both sides on the key; each left key finds its
+//               run in the sorted right keys by binary search;
+//   hash        build an open-addressing table of distinct keys on the
+//               smaller side, with each key's rows laid out contiguously
+//               (count, scan, fill), and probe it with the other side.
+// Output rows are then put in lexicographic order by the caller.
+#include "compact.hpp"
+
+#include <algorithm>
+
+namespace tid {
+
+// from sort.hip
+bool radix_sort_pairs(tid_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                      uint64_t n, int bits);
+void iota(tid_ctx *ctx, uint32_t *p, uint64_t n);
+void fill(tid_ctx *ctx, uint32_t *p, uint64_t n, uint32_t v);
+std::unique_ptr<tid_table> sort_rows(tid_ctx *ctx, const tid_table *t, uint64_t n, int distinct);
+
+static unsigned grid_of(uint64_t n, unsigned block = 256, unsigned cap = 8192) {
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + block - 1) / block, cap));
+}
+
+// ---------------------------------------------------------------------------
+// device-wide exclusive scan: uint32 counts -> uint64 offsets (n + 1 entries)
+// ---------------------------------------------------------------------------
+
+constexpr int kScanBlock = 256;
+constexpr int kScanIPT = 4;
+constexpr uint64_t kScanTile = (uint64_t)kScanBlock * kScanIPT;
+
+__global__ __launch_bounds__(kScanBlock) void range_sums(const uint32_t *__restrict__ in,
+                                                          uint64_t n, uint64_t range,
+                                                          uint64_t *sums) {
+    __shared__ uint64_t s_w[kScanBlock / dev::kWave];
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const uint64_t r0 = (uint64_t)blockIdx.x * range, r1 = min(n, r0 + range);
+    uint64_t s = 0;
+    for (uint64_t i = r0 + tid; i < r1; i += kScanBlock) s += in[i];
+    s = dev::wave_sum(s);
+    if (lane == 0) s_w[wave] = s;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t t = 0;
+        for (int w = 0; w < kScanBlock / dev::kWave; ++w) t += s_w[w];
+        sums[blockIdx.x] = t;
+    }
+}
+
+// exclusive scan of P <= 4096 uint64 in one workgroup; base[P] = total
+__global__ __launch_bounds__(1024) void small_exclusive_scan(const uint64_t *in, uint64_t *base,
+                                                              uint32_t P) {
+    __shared__ uint64_t s_w[16];
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const uint32_t chunk = (P + 1023) / 1024;
+    const uint32_t a = min(P, tid * chunk), b = min(P, a + chunk);
+    uint64_t sum = 0;
+    for (uint32_t i = a; i < b; ++i) sum += in[i];
+    const uint64_t incl = dev::wave_inclusive_sum(sum);
+    if (lane == dev::kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint64_t before = 0;
+    for (int w = 0; w < wave; ++w) before += s_w[w];
+    uint64_t run = before + incl - sum;
+    for (uint32_t i = a; i < b; ++i) {
+        base[i] = run;
+        run += in[i];
+    }
+    if (tid == 1023) base[P] = before + incl;
+}
+
+__global__ __launch_bounds__(kScanBlock) void range_scan(const uint32_t *__restrict__ in,
+                                                          uint64_t n, uint64_t range,
+                                                          const uint64_t *base, uint64_t *out) {
+    __shared__ uint64_t s_w[kScanBlock / dev::kWave];
+    __shared__ uint64_t s_run;
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const uint64_t r0 = (uint64_t)blockIdx.x * range, r1 = min(n, r0 + range);
+    if (tid == 0) s_run = base[blockIdx.x];
+    __syncthreads();
+    for (uint64_t t0 = r0; t0 < r1; t0 += kScanTile) {
+        uint32_t v[kScanIPT];
+        uint64_t local = 0;
+#pragma unroll
+        for (int u = 0; u < kScanIPT; ++u) {
+            const uint64_t i = t0 + (uint64_t)tid * kScanIPT + u;
+            v[u] = i < r1 ? in[i] : 0u;
+            local += v[u];
+        }
+        const uint64_t incl = dev::wave_inclusive_sum(local);
+        if (lane == dev::kWave - 1) s_w[wave] = incl;
+        __syncthreads();
+        uint64_t before = s_run;
+        for (int w = 0; w < wave; ++w) before += s_w[w];
+        uint64_t run = before + incl - local;
+#pragma unroll
+        for (int u = 0; u < kScanIPT; ++u) {
+            const uint64_t i = t0 + (uint64_t)tid * kScanIPT + u;
+            if (i < r1) out[i] = run;
+            run += v[u];
+        }
+        __syncthreads();
+        if (tid == kScanBlock - 1) s_run = run;
+        __syncthreads();
+    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) out[n] = s_run;
+}
+
+// out[0..n] = exclusive prefix sums of in[0..n); out[n] = total.  Returns total.
+uint64_t exclusive_scan_u64(tid_ctx *ctx, const uint32_t *in, uint64_t n, uint64_t *out) {
+    if (n == 0) {
+        TID_HIP(hipMemsetAsync(out, 0, sizeof(uint64_t), ctx->stream));
+        return 0;
+    }
+    const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+    uint64_t P = std::max<uint64_t>(1, std::min<uint64_t>(tiles, 4096));
+    const uint64_t range = (tiles + P - 1) / P * kScanTile;
+    P = (n + range - 1) / range;
+    DevBuf sums(ctx, P * 8), base(ctx, (P + 1) * 8);
+    hipLaunchKernelGGL(range_sums, dim3((uint32_t)P), dim3(kScanBlock), 0, ctx->stream, in, n,
+                       range, sums.get<uint64_t>());
+    TID_HIP(hipGetLastError());
+    hipLaunchKernelGGL(small_exclusive_scan, dim3(1), dim3(1024), 0, ctx->stream,
+                       sums.get<const uint64_t>(), base.get<uint64_t>(), (uint32_t)P);
+    TID_HIP(hipGetLastError());
+    hipLaunchKernelGGL(range_scan, dim3((uint32_t)P), dim3(kScanBlock), 0, ctx->stream, in, n,
+                       range, base.get<const uint64_t>(), out);
+    TID_HIP(hipGetLastError());
+    uint64_t total = 0;
+    TID_HIP(hipMemcpyAsync(&total, out + n, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    return total;
+}
+
+// ---------------------------------------------------------------------------
+// sort-merge matching
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t *a, uint64_t n, uint64_t x) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (a[mid] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t upper_bound_u64(const uint64_t *a, uint64_t n, uint64_t x) {
+    uint64_t lo = 0, hi = n;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// for each sorted probe key: where its run starts in the sorted build keys, and its length
+__global__ void merge_counts(const uint64_t *qk, uint64_t nq, const uint64_t *bk, uint64_t nb,
+                             uint32_t *start, uint32_t *count) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nq; i += stride) {
+        const uint64_t x = qk[i];
+        const uint64_t lo = lower_bound_u64(bk, nb, x);
+        start[i] = (uint32_t)lo;
+        count[i] = (uint32_t)upper_bound_u64(bk + lo, nb - lo, x);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// hash build and probe
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+    // 32-bit finaliser (MurmurHash3 fmix32)
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+// slot words hold key + 1 (0 = empty)
+__global__ void hash_insert(const uint32_t *keys, uint64_t n, unsigned long long *slots,
+                            uint32_t mask, uint32_t *slot_of, uint32_t *slot_count) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const unsigned long long want = (unsigned long long)keys[i] + 1ull;
+        uint32_t h = hash32(keys[i]) & mask;
+        for (uint32_t probe = 0; probe <= mask; ++probe) {
+            unsigned long long cur = slots[h];
+            if (cur == 0ull) cur = atomicCAS(&slots[h], 0ull, want);
+            if (cur == 0ull || cur == want) {
+                slot_of[i] = h;
+                atomicAdd(&slot_count[h], 1u);
+                break;
+            }
+            h = (h + 1) & mask;
+        }
+    }
+}
+
+__global__ void hash_fill(const uint32_t *slot_of, uint64_t n, const uint64_t *slot_start,
+                          uint32_t *cursor, uint32_t *rows) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t h = slot_of[i];
+        const uint32_t at = atomicAdd(&cursor[h], 1u);
+        rows[slot_start[h] + at] = (uint32_t)i;
+    }
+}
+
+__global__ void hash_probe(const uint32_t *keys, uint64_t n, const unsigned long long *slots,
+                           uint32_t mask, const uint32_t *slot_count, const uint64_t *slot_start,
+                           uint32_t *start, uint32_t *count) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const unsigned long long want = (unsigned long long)keys[i] + 1ull;
+        uint32_t h = hash32(keys[i]) & mask;
+        uint32_t c = 0, s = 0;
+        for (uint32_t probe = 0; probe <= mask; ++probe) {
+            const unsigned long long cur = slots[h];
+            if (cur == want) {
+                c = slot_count[h];
+                s = (uint32_t)slot_start[h];
+                break;
+            }
+            if (cur == 0ull) break;
+            h = (h + 1) & mask;
+        }
+        start[i] = s;
+        count[i] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// expansion: output row o -> (probe position a, build position j)
+// ---------------------------------------------------------------------------
+
+struct ExpandArgs {
+    const uint64_t *off;    // nq + 1 output offsets per probe position
+    const uint32_t *start;  // per probe position: first matching build position
+    const uint32_t *qrow;   // probe position -> probe table row (null: identity)
+    const uint32_t *brow;   // build position -> build table row
+    uint64_t nq, total;
+    int probe_is_left;
+    const uint32_t *lcol[TID_MAX_COLS];
+    const uint32_t *rcol[TID_MAX_COLS];
+    uint32_t *out[TID_MAX_COLS];
+    int nl, nr;  // output columns taken from left rows, then from right rows
+};
+
+__global__ void join_expand(ExpandArgs a) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < a.total; o += stride) {
+        // last probe position whose offset is <= o
+        uint64_t lo = 0, hi = a.nq;
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (a.off[mid] <= o) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t j = a.start[lo] + (o - a.off[lo]);
+        const uint32_t pr = a.qrow ? a.qrow[lo] : (uint32_t)lo;
+        const uint32_t br = a.brow[j];
+        const uint32_t lr = a.probe_is_left ? pr : br;
+        const uint32_t rr = a.probe_is_left ? br : pr;
+        for (int c = 0; c < a.nl; ++c) a.out[c][o] = a.lcol[c][lr];
+        for (int c = 0; c < a.nr; ++c) a.out[a.nl + c][o] = a.rcol[c][rr];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+__global__ void widen_kernel(const uint32_t *in, uint64_t n, uint64_t *out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = in[i];
+}
+
+void widen_u32(tid_ctx *ctx, const uint32_t *in, uint64_t n, uint64_t *out) {
+    hipLaunchKernelGGL(widen_kernel, dim3(grid_of(n)), dim3(256), 0, ctx->stream, in, n, out);
+    TID_HIP(hipGetLastError());
+}
+
+
+static int bitw(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
+std::vector<uint32_t> column_maxima(tid_ctx *ctx, const tid_table *t, uint64_t n);
+
+// Matches of L[lc] = R[rc] as an unsorted table of the columns lkeep of L
+// followed by the columns rkeep of R.
+std::unique_ptr<tid_table> join_unsorted(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
+                                         const tid_table *R, uint64_t nr, int rc, int algo,
+                                         const JoinPlan &jp) {
+    std::vector<int32_t> vars;
+    for (int c : jp.lkeep) vars.push_back(L->vars[c]);
+    for (int c : jp.rkeep) vars.push_back(R->vars[c]);
+    TID_REQUIRE(vars.size() <= TID_MAX_COLS, TID_E_SCHEMA, "join: too many output columns");
+    if (nl == 0 || nr == 0) {
+        auto out = make_table(ctx, (int)vars.size(), vars.data(), 0);
+        set_count(ctx, out.get(), 0);
+        return out;
+    }
+    TID_REQUIRE(nl < (1ull << 32) && nr < (1ull << 32), TID_E_UNSUPPORTED,
+                "join: inputs of 2^32 rows or more");
+    if (algo == 0) algo = 1;
+
+    ExpandArgs ea{};
+    DevBuf start, count, off, qk, qv, bk, bv, qk2, qv2, bk2, bv2;
+    DevBuf slots, slot_of, slot_count, slot_start, cursor, rows;
+    uint64_t nq;
+    if (algo == 2) {
+        // sort both sides on the key, then find each left key's run on the right
+        const std::vector<uint32_t> ml = column_maxima(ctx, L, nl);
+        const std::vector<uint32_t> mr = column_maxima(ctx, R, nr);
+        const int bits = bitw(std::max(ml[lc], mr[rc]));
+        auto sort_side = [&](const tid_table *T, uint64_t n, int col, DevBuf &k, DevBuf &v,
+                             DevBuf &k2, DevBuf &v2) -> std::pair<uint64_t *, uint32_t *> {
+            k = DevBuf(ctx, n * 8);
+            v = DevBuf(ctx, n * 4);
+            k2 = DevBuf(ctx, n * 8);
+            v2 = DevBuf(ctx, n * 4);
+            // key = column value widened to 64 bits
+            widen_u32(ctx, T->col[col], n, k.get<uint64_t>());
+            iota(ctx, v.get<uint32_t>(), n);
+            const bool moved = radix_sort_pairs(ctx, k.get<uint64_t>(), v.get<uint32_t>(),
+                                                k2.get<uint64_t>(), v2.get<uint32_t>(), n, bits);
+            return moved ? std::make_pair(k2.get<uint64_t>(), v2.get<uint32_t>())
+                         : std::make_pair(k.get<uint64_t>(), v.get<uint32_t>());
+        };
+        auto [lk, lv] = sort_side(L, nl, lc, qk, qv, qk2, qv2);
+        auto [rk, rv] = sort_side(R, nr, rc, bk, bv, bk2, bv2);
+        nq = nl;
+        start = DevBuf(ctx, nq * 4);
+        count = DevBuf(ctx, nq * 4);
+        hipLaunchKernelGGL(merge_counts, dim3(grid_of(nq)), dim3(256), 0, ctx->stream, lk, nq, rk,
+                           nr, start.get<uint32_t>(), count.get<uint32_t>());
+        TID_HIP(hipGetLastError());
+        ea.qrow = lv;
+        ea.brow = rv;
+        ea.probe_is_left = 1;
+    } else {
+        // build on the smaller side
+        const bool build_right = nr <= nl;
+        const tid_table *B = build_right ? R : L;
+        const tid_table *Q = build_right ? L : R;
+        const uint64_t nb = build_right ? nr : nl;
+        nq = build_right ? nl : nr;
+        const uint32_t *bkey = B->col[build_right ? rc : lc];
+        const uint32_t *qkey = Q->col[build_right ? lc : rc];
+        uint64_t cap = 1024;
+        while (cap < 2 * nb) cap <<= 1;
+        TID_REQUIRE(cap <= (1ull << 31), TID_E_UNSUPPORTED, "join: hash table too large");
+        const uint32_t mask = (uint32_t)(cap - 1);
+        slots = DevBuf(ctx, cap * 8);
+        slot_count = DevBuf(ctx, cap * 4);
+        cursor = DevBuf(ctx, cap * 4);
+        slot_of = DevBuf(ctx, nb * 4);
+        slot_start = DevBuf(ctx, (cap + 1) * 8);
+        rows = DevBuf(ctx, nb * 4);
+        TID_HIP(hipMemsetAsync(slots.get(), 0, cap * 8, ctx->stream));
+        TID_HIP(hipMemsetAsync(slot_count.get(), 0, cap * 4, ctx->stream));
+        TID_HIP(hipMemsetAsync(cursor.get(), 0, cap * 4, ctx->stream));
+        hipLaunchKernelGGL(hash_insert, dim3(grid_of(nb)), dim3(256), 0, ctx->stream, bkey, nb,
+                           slots.get<unsigned long long>(), mask, slot_of.get<uint32_t>(),
+                           slot_count.get<uint32_t>());
+        TID_HIP(hipGetLastError());
+        exclusive_scan_u64(ctx, slot_count.get<const uint32_t>(), cap, slot_start.get<uint64_t>());
+        hipLaunchKernelGGL(hash_fill, dim3(grid_of(nb)), dim3(256), 0, ctx->stream,
+                           slot_of.get<const uint32_t>(), nb, slot_start.get<const uint64_t>(),
+                           cursor.get<uint32_t>(), rows.get<uint32_t>());
+        TID_HIP(hipGetLastError());
+        start = DevBuf(ctx, nq * 4);
+        count = DevBuf(ctx, nq * 4);
+        hipLaunchKernelGGL(hash_probe, dim3(grid_of(nq)), dim3(256), 0, ctx->stream, qkey, nq,
+                           slots.get<const unsigned long long>(), mask,
+                           slot_count.get<const uint32_t>(), slot_start.get<const uint64_t>(),
+                           start.get<uint32_t>(), count.get<uint32_t>());
+        TID_HIP(hipGetLastError());
+        ea.qrow = nullptr;
+        ea.brow = rows.get<uint32_t>();
+        ea.probe_is_left = build_right ? 1 : 0;
+    }
+    off = DevBuf(ctx, (nq + 1) * 8);
+    const uint64_t total = exclusive_scan_u64(ctx, count.get<const uint32_t>(), nq, off.get<uint64_t>());
+    auto out = make_table(ctx, (int)vars.size(), vars.data(), total);
+    if (total) {
+        TID_REQUIRE(total < (1ull << 40), TID_E_UNSUPPORTED, "join: output too large");
+        ea.off = off.get<const uint64_t>();
+        ea.start = start.get<const uint32_t>();
+        ea.nq = nq;
+        ea.total = total;
+        ea.nl = (int)jp.lkeep.size();
+        ea.nr = (int)jp.rkeep.size();
+        for (int c = 0; c < ea.nl; ++c) ea.lcol[c] = L->col[jp.lkeep[c]];
+        for (int c = 0; c < ea.nr; ++c) ea.rcol[c] = R->col[jp.rkeep[c]];
+        for (int c = 0; c < (int)vars.size(); ++c) ea.out[c] = out->col[c];
+        hipLaunchKernelGGL(join_expand, dim3(grid_of(total, 256, 16384)), dim3(256), 0,
+                           ctx->stream, ea);
+        TID_HIP(hipGetLastError());
+    }
+    set_count(ctx, out.get(), total);
+    return out;
+}
+
+std::unique_ptr<tid_table> join_tables(tid_ctx *ctx, const tid_table *l, int lcol,
+                                       const tid_table *r, int rcol, int algo) {
+    TID_REQUIRE(lcol >= 0 && lcol < l->ncols && rcol >= 0 && rcol < r->ncols, TID_E_INVALID_ARG,
+                "join: column out of range");
+    TID_REQUIRE(l->ncols + r->ncols - 1 <= TID_MAX_COLS, TID_E_SCHEMA, "join: too many columns");
+    tid_table *both[2] = {const_cast<tid_table *>(l), const_cast<tid_table *>(r)};
+    resolve_counts(ctx, both, 2);
+    JoinPlan jp;
+    for (int c = 0; c < l->ncols; ++c) jp.lkeep.push_back(c);
+    for (int c = 0; c < r->ncols; ++c)
+        if (c != rcol) jp.rkeep.push_back(c);
+    auto raw = join_unsorted(ctx, l, l->nrows, lcol, r, r->nrows, rcol, algo, jp);
+    return sort_rows(ctx, raw.get(), raw->nrows, 0);
+}
+
+}  // namespace tid

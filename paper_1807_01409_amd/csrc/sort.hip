@@ -1,0 +1,440 @@
+// sort.hip -- stable LSD radix sort of (64-bit key, 32-bit value) pairs, the
+// canonical lexicographic row order of tables, DISTINCT, and union.
+//
+// The paper sorts subquery results before joining them and merges final
+// results to distinct values (Sec. 4.2 step 3 with Mgpu's mergesort, Sec. 4.3
+// DISTINCT).  Here every ordering is an LSD radix sort written for wave64:
+//   hist     each workgroup owns one contiguous range of the input and counts
+//            the digits of its range (wave-private LDS histograms, updated
+//            by the leader lane of each group of lanes holding one digit);
+//   scan     one flat exclusive scan over the digit-major count matrix gives,
+//            for every (digit, range), where its elements go;
+//   scatter  each workgroup walks its range tile by tile and writes every
+//            element at its digit's running offset plus its stable rank,
+//            found with ballots that group the lanes holding equal digits.
+// A row of k columns is sorted as one or more packed 64-bit keys (as many
+// leading columns as fit their bit widths), least significant group first,
+// carrying the row permutation as the value.
+#include "compact.hpp"
+
+#include <algorithm>
+#include <numeric>
+
+namespace tid {
+
+constexpr int kRadixBits = 8;
+constexpr uint32_t kRadix = 1u << kRadixBits;
+constexpr int kSortBlock = 256;
+constexpr int kSortIPT = 16;
+constexpr int kSortNW = kSortBlock / dev::kWave;
+constexpr uint64_t kSortTile = (uint64_t)kSortBlock * kSortIPT;
+
+// lanes (among the valid ones) that hold the same digit as the calling lane
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
+    uint64_t peers = dev::ballot(valid);
+#pragma unroll
+    for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = dev::ballot(bit);
+        peers &= bit ? m : ~m;
+    }
+    return valid ? peers : 0ull;
+}
+
+// item `it` of lane `lane` in wave `wave` of the tile at t0: each wave owns 64*IPT
+// consecutive items, so every load instruction reads 64 consecutive keys
+__device__ __forceinline__ uint64_t sort_item(uint64_t t0, int wave, int it, int lane) {
+    return t0 + (uint64_t)wave * (dev::kWave * kSortIPT) + (uint64_t)it * dev::kWave + lane;
+}
+
+__global__ __launch_bounds__(kSortBlock) void radix_hist(const uint64_t *__restrict__ keys,
+                                                          uint64_t n, uint64_t range, int shift,
+                                                          uint32_t *counts, uint32_t P) {
+    __shared__ uint32_t s_h[kSortNW][kRadix];
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    for (uint32_t d = tid; d < kSortNW * kRadix; d += kSortBlock) (&s_h[0][0])[d] = 0;
+    __syncthreads();
+    const uint32_t w = blockIdx.x;
+    const uint64_t r0 = (uint64_t)w * range, r1 = min(n, r0 + range);
+    for (uint64_t t0 = r0; t0 < r1; t0 += kSortTile) {
+        uint32_t d[kSortIPT];
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            const uint64_t i = sort_item(t0, wave, it, lane);
+            d[it] = i < r1 ? (uint32_t)(keys[i] >> shift) & (kRadix - 1) : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            const bool valid = sort_item(t0, wave, it, lane) < r1;
+            const uint64_t peers = match_digit(d[it], valid);
+            if (valid && lane == __builtin_ctzll(peers)) s_h[wave][d[it]] += (uint32_t)__popcll(peers);
+        }
+    }
+    __syncthreads();
+    for (uint32_t dd = tid; dd < kRadix; dd += kSortBlock) {
+        uint32_t s = 0;
+        for (int ww = 0; ww < kSortNW; ++ww) s += s_h[ww][dd];
+        counts[(size_t)dd * P + w] = s;
+    }
+}
+
+// exclusive scan of m uint32 in one workgroup (m is at most kRadix * 2048)
+__global__ __launch_bounds__(1024) void flat_exclusive_scan(const uint32_t *in, uint32_t *out,
+                                                             uint32_t m) {
+    __shared__ uint32_t s_w[16];
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const uint32_t chunk = (m + 1023) / 1024;
+    const uint32_t a = min(m, tid * chunk), b = min(m, a + chunk);
+    uint32_t sum = 0;
+    for (uint32_t i = a; i < b; ++i) sum += in[i];
+    const uint32_t incl = dev::wave_inclusive_sum(sum);
+    if (lane == dev::kWave - 1) s_w[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int ww = 0; ww < wave; ++ww) before += s_w[ww];
+    uint32_t run = before + incl - sum;
+    for (uint32_t i = a; i < b; ++i) {
+        const uint32_t v = in[i];
+        out[i] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void radix_scatter(
+    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ vout, uint64_t n, uint64_t range, int shift, const uint32_t *offs,
+    uint32_t P) {
+    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_wh[kSortNW][kRadix];
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const uint32_t w = blockIdx.x;
+    for (uint32_t d = tid; d < kRadix; d += kSortBlock) s_run[d] = offs[(size_t)d * P + w];
+    const uint64_t r0 = (uint64_t)w * range, r1 = min(n, r0 + range);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint64_t t0 = r0; t0 < r1; t0 += kSortTile) {
+        uint64_t key[kSortIPT];
+        uint32_t val[kSortIPT], rank[kSortIPT];
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            const uint64_t i = sort_item(t0, wave, it, lane);
+            key[it] = i < r1 ? kin[i] : 0ull;
+            val[it] = i < r1 ? vin[i] : 0u;
+        }
+        for (uint32_t d = lane; d < kRadix; d += dev::kWave) s_wh[wave][d] = 0;
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            const bool valid = sort_item(t0, wave, it, lane) < r1;
+            const uint32_t d = (uint32_t)(key[it] >> shift) & (kRadix - 1);
+            const uint64_t peers = match_digit(d, valid);
+            const uint32_t before = valid ? s_wh[wave][d] : 0u;
+            rank[it] = before + (uint32_t)__popcll(peers & lt);
+            if (valid && lane == __builtin_ctzll(peers)) s_wh[wave][d] = before + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        // per-wave counts -> per-wave bases (waves in item order)
+        for (uint32_t d = tid; d < kRadix; d += kSortBlock) {
+            uint32_t run = s_run[d];
+            for (int ww = 0; ww < kSortNW; ++ww) {
+                const uint32_t c = s_wh[ww][d];
+                s_wh[ww][d] = run;
+                run += c;
+            }
+            s_run[d] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            if (sort_item(t0, wave, it, lane) < r1) {
+                const uint32_t d = (uint32_t)(key[it] >> shift) & (kRadix - 1);
+                const uint32_t pos = s_wh[wave][d] + rank[it];
+                kout[pos] = key[it];
+                vout[pos] = val[it];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void iota_u32(uint32_t *v, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        v[i] = (uint32_t)i;
+}
+
+struct PackArgs {
+    const uint32_t *col[TID_MAX_COLS];
+    int shift[TID_MAX_COLS];
+    int ncols;
+};
+
+// key[i] = concatenation of the group's columns of row perm[i] (or row i)
+__global__ void pack_keys(PackArgs a, const uint32_t *perm, uint64_t n, uint64_t *key) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint64_t r = perm ? perm[i] : i;
+        uint64_t k = 0;
+        for (int c = 0; c < a.ncols; ++c) k |= (uint64_t)a.col[c][r] << a.shift[c];
+        key[i] = k;
+    }
+}
+
+struct GatherArgs {
+    const uint32_t *in[TID_MAX_COLS];
+    uint32_t *out[TID_MAX_COLS];
+    int ncols;
+};
+
+__global__ void gather_rows(GatherArgs a, const uint32_t *perm, uint64_t n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const uint32_t r = perm[i];
+        for (int c = 0; c < a.ncols; ++c) a.out[c][i] = a.in[c][r];
+    }
+}
+
+__global__ void column_max(const uint32_t *const *cols, uint64_t n, uint32_t *mx) {
+    const uint32_t *col = cols[blockIdx.y];
+    uint32_t m = 0;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        m = max(m, col[i]);
+    for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
+    if (dev::lane_id() == 0) atomicMax(&mx[blockIdx.y], m);
+}
+
+__global__ void fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// rows of a sorted table that differ from the row before them
+struct UniqueSrc {
+    const uint32_t *col[TID_MAX_COLS];
+    int ncols;
+    uint64_t n;
+    using Item = uint64_t;
+    __device__ __forceinline__ Item load(uint64_t i) const { return i; }
+    __device__ __forceinline__ bool match(int, Item i) const {
+        if (i == 0) return true;
+        for (int c = 0; c < ncols; ++c)
+            if (col[c][i] != col[c][i - 1]) return true;
+        return false;
+    }
+    __device__ __forceinline__ uint32_t value(int, int c, Item i, uint64_t) const {
+        return col[c][i];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+static unsigned grid_for(uint64_t n, unsigned block = 256, unsigned cap = 8192) {
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + block - 1) / block, cap));
+}
+
+void fill(tid_ctx *ctx, uint32_t *p, uint64_t n, uint32_t v) {
+    if (!n) return;
+    hipLaunchKernelGGL(fill_u32, dim3(grid_for(n)), dim3(256), 0, ctx->stream, p, n, v);
+    TID_HIP(hipGetLastError());
+}
+
+void iota(tid_ctx *ctx, uint32_t *p, uint64_t n) {
+    if (!n) return;
+    hipLaunchKernelGGL(iota_u32, dim3(grid_for(n)), dim3(256), 0, ctx->stream, p, n);
+    TID_HIP(hipGetLastError());
+}
+
+// Stable sort of n (key, value) pairs on key bits [0, bits).  The sorted pairs
+// end in (k0, v0) if the return value is false, in (k1, v1) if true.
+bool radix_sort_pairs(tid_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, uint32_t *v1,
+                      uint64_t n, int bits) {
+    if (n <= 1 || bits <= 0) return false;
+    TID_REQUIRE(n < (1ull << 32), TID_E_UNSUPPORTED, "sort: more than 2^32-1 rows");
+    const uint64_t tiles = (n + kSortTile - 1) / kSortTile;
+    uint64_t P = std::max<uint64_t>(1, std::min<uint64_t>(tiles, 2ull * device_cus(ctx)));
+    const uint64_t range = (tiles + P - 1) / P * kSortTile;
+    P = (n + range - 1) / range;
+    DevBuf counts(ctx, (size_t)kRadix * P * sizeof(uint32_t));
+    DevBuf offs(ctx, (size_t)kRadix * P * sizeof(uint32_t));
+    bool flip = false;
+    for (int shift = 0; shift < bits; shift += kRadixBits) {
+        const uint64_t *ki = flip ? k1 : k0;
+        const uint32_t *vi = flip ? v1 : v0;
+        uint64_t *ko = flip ? k0 : k1;
+        uint32_t *vo = flip ? v0 : v1;
+        hipLaunchKernelGGL(radix_hist, dim3((uint32_t)P), dim3(kSortBlock), 0, ctx->stream, ki, n,
+                           range, shift, counts.get<uint32_t>(), (uint32_t)P);
+        TID_HIP(hipGetLastError());
+        hipLaunchKernelGGL(flat_exclusive_scan, dim3(1), dim3(1024), 0, ctx->stream,
+                           counts.get<const uint32_t>(), offs.get<uint32_t>(),
+                           (uint32_t)(kRadix * P));
+        TID_HIP(hipGetLastError());
+        hipLaunchKernelGGL(radix_scatter, dim3((uint32_t)P), dim3(kSortBlock), 0, ctx->stream, ki,
+                           vi, ko, vo, n, range, shift, offs.get<const uint32_t>(), (uint32_t)P);
+        TID_HIP(hipGetLastError());
+        flip = !flip;
+    }
+    return flip;
+}
+
+std::vector<uint32_t> column_maxima(tid_ctx *ctx, const tid_table *t, uint64_t n) {
+    std::vector<uint32_t> mx(t->ncols, 0);
+    if (n == 0 || t->ncols == 0) return mx;
+    DevBuf cols(ctx, sizeof(uint32_t *) * t->ncols);
+    DevBuf dmx(ctx, sizeof(uint32_t) * t->ncols);
+    TID_HIP(hipMemcpyAsync(cols.get(), t->col, sizeof(uint32_t *) * t->ncols,
+                           hipMemcpyHostToDevice, ctx->stream));
+    TID_HIP(hipMemsetAsync(dmx.get(), 0, sizeof(uint32_t) * t->ncols, ctx->stream));
+    hipLaunchKernelGGL(column_max, dim3(grid_for(n, 256, 1024), t->ncols), dim3(256), 0,
+                       ctx->stream, cols.get<const uint32_t *const>(), n, dmx.get<uint32_t>());
+    TID_HIP(hipGetLastError());
+    TID_HIP(hipMemcpyAsync(mx.data(), dmx.get(), sizeof(uint32_t) * t->ncols,
+                           hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    return mx;
+}
+
+static int bit_width(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
+
+// Permutation that puts the rows of t (n rows) in lexicographic order.
+DevBuf sort_permutation(tid_ctx *ctx, const tid_table *t, uint64_t n) {
+    const std::vector<uint32_t> mx = column_maxima(ctx, t, n);
+    // columns grouped from the most significant one while their widths fit 64 bits
+    std::vector<std::pair<int, int>> groups;  // [first, last) columns
+    int c = 0;
+    while (c < t->ncols) {
+        int width = 0, e = c;
+        while (e < t->ncols && width + bit_width(mx[e]) <= 64) width += bit_width(mx[e++]);
+        if (e == c) e = c + 1;  // unreachable: a column is at most 32 bits
+        groups.emplace_back(c, e);
+        c = e;
+    }
+    DevBuf ka(ctx, n * 8), kb(ctx, n * 8), va(ctx, n * 4), vb(ctx, n * 4);
+    iota(ctx, va.get<uint32_t>(), n);
+    bool perm_in_b = false;
+    bool first = true;
+    for (int g = (int)groups.size() - 1; g >= 0; --g) {
+        PackArgs pa{};
+        int shift = 0;
+        for (int x = groups[g].second - 1; x >= groups[g].first; --x) {
+            pa.col[pa.ncols] = t->col[x];
+            pa.shift[pa.ncols] = shift;
+            ++pa.ncols;
+            shift += bit_width(mx[x]);
+        }
+        if (shift == 0) continue;  // all-zero columns order nothing
+        uint32_t *perm = perm_in_b ? vb.get<uint32_t>() : va.get<uint32_t>();
+        uint64_t *keys = perm_in_b ? kb.get<uint64_t>() : ka.get<uint64_t>();
+        hipLaunchKernelGGL(pack_keys, dim3(grid_for(n)), dim3(256), 0, ctx->stream, pa,
+                           first ? (const uint32_t *)nullptr : perm, n, keys);
+        TID_HIP(hipGetLastError());
+        first = false;
+        const bool moved = perm_in_b
+                               ? radix_sort_pairs(ctx, kb.get<uint64_t>(), vb.get<uint32_t>(),
+                                                  ka.get<uint64_t>(), va.get<uint32_t>(), n, shift)
+                               : radix_sort_pairs(ctx, ka.get<uint64_t>(), va.get<uint32_t>(),
+                                                  kb.get<uint64_t>(), vb.get<uint32_t>(), n, shift);
+        if (moved) perm_in_b = !perm_in_b;
+    }
+    return perm_in_b ? std::move(vb) : std::move(va);
+}
+
+// rows of src (n rows) placed in the order given by perm, into dst
+void gather_table(tid_ctx *ctx, const tid_table *src, const uint32_t *perm, uint64_t n,
+                  tid_table *dst) {
+    if (!n || !src->ncols) return;
+    GatherArgs ga{};
+    ga.ncols = src->ncols;
+    for (int c = 0; c < src->ncols; ++c) {
+        ga.in[c] = src->col[c];
+        ga.out[c] = dst->col[c];
+    }
+    hipLaunchKernelGGL(gather_rows, dim3(grid_for(n)), dim3(256), 0, ctx->stream, ga, perm, n);
+    TID_HIP(hipGetLastError());
+}
+
+// drop rows equal to their predecessor in a sorted table
+std::unique_ptr<tid_table> unique_sorted(tid_ctx *ctx, const tid_table *t, uint64_t n) {
+    auto out = make_table(ctx, t->ncols, t->vars, n);
+    if (n == 0) {
+        set_count(ctx, out.get(), 0);
+        return out;
+    }
+    UniqueSrc src{};
+    for (int c = 0; c < t->ncols; ++c) src.col[c] = t->col[c];
+    src.ncols = t->ncols;
+    src.n = n;
+    CompactArgs<1, TID_MAX_COLS> a{};
+    for (int c = 0; c < t->ncols; ++c) a.out[0].col[c] = out->col[c];
+    a.out[0].cap = n;
+    a.out[0].count = out->d_count;
+    a.out[0].ncols = t->ncols;
+    launch_compact<UniqueSrc, 256, 16, 1, TID_MAX_COLS>(ctx, src, a, 1, 8192);
+    return out;
+}
+
+std::unique_ptr<tid_table> sort_rows(tid_ctx *ctx, const tid_table *t, uint64_t n, int distinct) {
+    if (t->ncols == 0) {
+        // zero-width rows are all equal
+        auto out = make_table(ctx, 0, t->vars, 0);
+        set_count(ctx, out.get(), distinct ? std::min<uint64_t>(n, 1) : n);
+        return out;
+    }
+    auto sorted = make_table(ctx, t->ncols, t->vars, n);
+    if (n <= 1) {
+        for (int c = 0; c < t->ncols && n; ++c)
+            TID_HIP(hipMemcpyAsync(sorted->col[c], t->col[c], n * 4, hipMemcpyDeviceToDevice,
+                                   ctx->stream));
+        set_count(ctx, sorted.get(), n);
+        return sorted;
+    }
+    DevBuf perm = sort_permutation(ctx, t, n);
+    gather_table(ctx, t, perm.get<const uint32_t>(), n, sorted.get());
+    set_count(ctx, sorted.get(), n);
+    if (!distinct) return sorted;
+    return unique_sorted(ctx, sorted.get(), n);
+}
+
+std::unique_ptr<tid_table> sort_table(tid_ctx *ctx, const tid_table *t, int distinct) {
+    const uint64_t n = const_cast<tid_table *>(t)->rows();
+    return sort_rows(ctx, t, n, distinct);
+}
+
+// Outer union: schema = ordered union of the inputs' variables; unbound cells 0.
+std::unique_ptr<tid_table> union_tables(tid_ctx *ctx, const tid_table *const *ts, int k,
+                                        int dedupe) {
+    std::vector<int32_t> vars;
+    for (int j = 0; j < k; ++j)
+        for (int c = 0; c < ts[j]->ncols; ++c)
+            if (std::find(vars.begin(), vars.end(), ts[j]->vars[c]) == vars.end())
+                vars.push_back(ts[j]->vars[c]);
+    TID_REQUIRE((int)vars.size() <= TID_MAX_COLS, TID_E_SCHEMA, "union: too many columns");
+    std::vector<tid_table *> raw(k);
+    for (int j = 0; j < k; ++j) raw[j] = const_cast<tid_table *>(ts[j]);
+    resolve_counts(ctx, raw.data(), k);
+    uint64_t total = 0;
+    for (int j = 0; j < k; ++j) total += ts[j]->nrows;
+    auto out = make_table(ctx, (int)vars.size(), vars.data(), total);
+    uint64_t at = 0;
+    for (int j = 0; j < k; ++j) {
+        const uint64_t n = ts[j]->nrows;
+        if (!n) continue;
+        for (size_t c = 0; c < vars.size(); ++c) {
+            int src = -1;
+            for (int x = 0; x < ts[j]->ncols; ++x)
+                if (ts[j]->vars[x] == vars[c]) src = x;
+            if (src >= 0)
+                TID_HIP(hipMemcpyAsync(out->col[c] + at, ts[j]->col[src], n * 4,
+                                       hipMemcpyDeviceToDevice, ctx->stream));
+            else
+                fill(ctx, out->col[c] + at, n, 0u);
+        }
+        at += n;
+    }
+    set_count(ctx, out.get(), total);
+    if (!dedupe) return out;
+    return sort_rows(ctx, out.get(), total, 1);
+}
+
+}  // namespace tid

@@ -1,0 +1,164 @@
+"""GPU parity of sort / DISTINCT, union, join (hash and sort-merge, all nine
+Table 3 relation types) and query plans against the CPU oracle: results must
+be byte-identical."""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import Table as OTable
+from oracle_pins import GOLD, random_plan, tiny_graph
+from synth import Pattern, Plan, pat
+
+pytestmark = pytest.mark.gpu
+
+
+def same(gt, ot):
+    got = gt.to_numpy()
+    assert gt.vars == ot.vars, (gt.vars, ot.vars)
+    assert got.shape == ot.rows.shape, (got.shape, ot.rows.shape)
+    assert np.array_equal(got, ot.rows)
+
+
+def rand_table(rng, n, k, hi):
+    rows = rng.integers(0, hi, size=(n, k), dtype=np.int64).astype(np.uint32)
+    return rows
+
+
+@pytest.mark.parametrize("n,k,hi", [(0, 2, 10), (1, 3, 5), (100, 1, 7), (5000, 2, 50),
+                                    (70001, 3, 1000), (20000, 3, 2**32 - 1),
+                                    (30000, 5, 2**31), (4097, 4, 3)])
+def test_sort_and_distinct(ctx, n, k, hi):
+    rng = np.random.default_rng(n + k)
+    rows = rand_table(rng, n, k, hi)
+    t = ctx.table(rows, list(range(k)))
+    ot = OTable(rows, list(range(k)))
+    same(ctx.sort(t, False), oracle.sort_rows(ot))
+    same(ctx.sort(t, True), oracle.distinct(ot))
+
+
+def test_union(ctx):
+    rng = np.random.default_rng(3)
+    specs = [([0, 1], 300), ([1, 2], 200), ([0, 1], 0), ([3], 50), ([2, 0, 1], 1000)]
+    ts, ots = [], []
+    for vs, n in specs:
+        rows = rand_table(rng, n, len(vs), 20)
+        ts.append(ctx.table(rows, vs))
+        ots.append(OTable(rows, vs))
+    for r in (1, 2, 3, 5):
+        for combo in itertools.combinations(range(len(specs)), r):
+            for d in (False, True):
+                same(ctx.union([ts[i] for i in combo], d), oracle.union([ots[i] for i in combo], d))
+
+
+@pytest.mark.parametrize("algo", [1, 2])
+@pytest.mark.parametrize("nl,nr,keys", [(0, 10, 5), (10, 0, 5), (1, 1, 1), (500, 700, 40),
+                                        (3000, 2000, 3000), (20000, 50, 10),
+                                        (50, 20000, 10), (2000, 2000, 1)])
+def test_join_parity(ctx, algo, nl, nr, keys):
+    rng = np.random.default_rng(nl * 7 + nr)
+    L = rand_table(rng, nl, 2, keys)
+    R = rand_table(rng, nr, 3, keys)
+    gl, gr = ctx.table(L, [0, 1]), ctx.table(R, [2, 3, 4])
+    ol, orr = OTable(L, [0, 1]), OTable(R, [2, 3, 4])
+    for lc, rc in ((0, 0), (1, 2), (0, 1)):
+        want = oracle.join(ol, lc, orr, rc, "sortmerge")
+        same(ctx.join(gl, lc, gr, rc, algo), want)
+
+
+def test_join_hot_key_count_invariant(ctx):
+    rng = np.random.default_rng(11)
+    L = rand_table(rng, 40000, 2, 2000)
+    R = rand_table(rng, 30000, 2, 2000)
+    L[rng.random(40000) < 0.1, 0] = 7   # a hub key holding ~10% of each side
+    R[rng.random(30000) < 0.1, 0] = 7
+    cl = np.bincount(L[:, 0], minlength=2000).astype(np.int64)
+    cr = np.bincount(R[:, 0], minlength=2000).astype(np.int64)
+    want_n = int((cl * cr).sum())
+    for algo in (1, 2):
+        j = ctx.join(ctx.table(L, [0, 1]), 0, ctx.table(R, [0, 2]), 0, algo)
+        assert j.nrows == want_n
+    got = ctx.join(ctx.table(L[:3000], [0, 1]), 0, ctx.table(R[:3000], [0, 2]), 0, 1)
+    same(got, oracle.join(OTable(L[:3000], [0, 1]), 0, OTable(R[:3000], [0, 2]), 0, "sortmerge"))
+
+
+def test_table3_relation_types_queries(ctx):
+    with open(os.path.join(GOLD, "table3_reltypes.json")) as f:
+        gd = json.load(f)
+    g = np.concatenate([tiny_graph(11, 400, 6), tiny_graph(12, 60, 6)])
+    G = ctx.load(g)
+    for name, (qi, qj) in gd["types"].items():
+        consts = [t for t in qi + qj if not t.startswith("?")]
+        for vals in itertools.islice(itertools.product(range(1, 7), repeat=len(consts)), 0, 60, 7):
+            env = dict(zip(consts, vals))
+
+            def mk(q):
+                return Pattern(*[env.get(t, 0) for t in q], *[0 if t == "?V" else -1 for t in q])
+            plan = Plan().scan(mk(qi)).scan(mk(qj)).join(0)
+            same(ctx.query(G, plan), oracle.query(g, plan))
+
+
+def test_rule11_query(ctx):
+    g = np.array([(76, 84, 56), (31, 84, 77), (56, 84, 78), (56, 84, 77), (44, 83, 2)],
+                 dtype=np.uint32)
+    G = ctx.load(g)
+    n = {}
+    plan = (Plan().scan(pat("?x 84 ?y", n)).scan(pat("?y 84 ?z", n)).join(n["?y"])
+            .project([n["?x"], n["?z"]]).distinct())
+    assert ctx.query(G, plan).to_numpy().tolist() == [[76, 77], [76, 78]]
+
+
+def test_small_config_queries(ctx, graphs):
+    g = graphs("small")
+    G = ctx.load(g)
+    n = {}
+    q1a = Plan().scan(pat("?s 7 ?o", n))
+    n = {}
+    q1b = Plan().scan(pat("?s 3 ?o1", n)).scan(pat("?s 11 ?o2", n)).join(n["?s"])
+    for plan in (q1a, q1b):
+        same(ctx.query(G, plan), oracle.query(g, plan))
+    # filter after a scan (fused into the search) and after a join (separate)
+    n = {}
+    p = (Plan().scan(pat("?s 3 ?o1", n)).filter(n["?o1"], 100, 3000)
+         .scan(pat("?s 11 ?o2", n)).join(n["?s"]).filter(n["?o2"], 50, 9000))
+    same(ctx.query(G, p), oracle.query(g, p))
+    # union of 4 subqueries with DISTINCT, projected
+    n = {}
+    p = Plan()
+    for pid in (3, 4, 5, 6):
+        p.scan(pat(f"?s {pid} ?o", n))
+    p.union(4, True).project([n["?o"]]).distinct()
+    same(ctx.query(G, p), oracle.query(g, p))
+
+
+def test_natural_join_two_shared_vars(ctx):
+    g = tiny_graph(31, 3000, 5)
+    G = ctx.load(g)
+    n = {}
+    p = Plan().scan(pat("?a ?b ?c", n)).scan(pat("?c ?b ?a", n)).join(n["?b"])
+    same(ctx.query(G, p), oracle.query(g, p))
+
+
+def test_random_plans(ctx):
+    rng = np.random.default_rng(2024)
+    for i in range(150):
+        g = tiny_graph(500 + i, int(rng.integers(1, 40)), 4)
+        plan = random_plan(rng)
+        G = ctx.load(g)
+        same(ctx.query(G, plan), oracle.query(g, plan))
+        G.free()
+
+
+def test_query_errors(ctx, graphs):
+    from paper_1807_01409_amd import TidError
+    G = ctx.load(graphs("small", 1000))
+    with pytest.raises(TidError) as e:
+        ctx.query(G, Plan().scan(pat("?s 7 ?o")).join(5))        # one table for a JOIN
+    assert e.value.status == -1
+    n = {}
+    with pytest.raises(TidError) as e:
+        ctx.query(G, Plan().scan(pat("?a 7 ?b", n)).scan(pat("?c 8 ?d", n)).join(n["?a"]))
+    assert e.value.status == -5
