@@ -1,12 +1,16 @@
-"""Benchmark of the TripleID-Q hot path on one MI355X.
+"""Benchmark of the TripleID-Q query path on one MI355X.
 
-One step = one pass of the query path over the resident medium graph
-(50M triples; subjects Zipf(1.0) over 5M IDs, predicates Zipf(1.2) over 1000,
-objects Zipf(1.1) over 10M): single-pattern scans (?s p ?o) at selectivities
-near 0.1%, 1% and 10%.  Inputs are resident in HBM before timing starts.
+Workload: the medium graph, 50M triples resident in HBM (subjects Zipf(1.0)
+over 5M IDs, predicates Zipf(1.2) over 1000, objects Zipf(1.1) over 10M,
+seed 2).  One step runs every operator of the path once:
+  scan   (?s p ?o) at selectivities near 0.1%, 1% and 10%   3 graph passes
+  star   (?s pA oA) . (?s pB ?o1) . (?s pC ?o2), sorted      1 pass + 2 joins
+  union  8 subqueries (?s p_r ?o), r = 11..18, DISTINCT      1 pass + sort
+  filter (?s ?p ?o) with o in [lo, hi) keeping ~5%           1 pass
+value = graph passes x N / step time (triples/s).
 
-Prints one JSON line (see the keys below).  --gpus N with N > 1 is refused:
-this build measures one GPU.
+Prints one JSON line.  --gpus N with N > 1 is refused: this build measures
+one GPU.
 """
 from __future__ import annotations
 
@@ -29,16 +33,6 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def pick_predicates(g, sigmas):
-    hist = np.bincount(g[:, 1])
-    n = g.shape[0]
-    out = []
-    for s in sigmas:
-        p = int(np.argmin(np.abs(np.log(np.maximum(hist, 1) / n) - np.log(s))))
-        out.append((p, int(hist[p]) / n))
-    return out
-
-
 def source_hash(paths):
     h = hashlib.sha256()
     for p in paths:
@@ -47,9 +41,13 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
+SCAN_SOURCES = ["paper_1807_01409_amd/csrc/scan.hip", "paper_1807_01409_amd/csrc/compact.hpp",
+                "paper_1807_01409_amd/csrc/device_common.hpp"]
+
+
 def measured_traffic(kernel_hash):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; otherwise None."""
+    """HBM bytes per launch of the scan from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "scan_medium_counters.json")
     if not os.path.exists(path):
         return None
@@ -60,30 +58,62 @@ def measured_traffic(kernel_hash):
     return d.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(g, patterns, budget_s=20.0):
-    """The oracle, as it stands, on this host: the same scans over a bounded
-    prefix of the graph."""
+def build_workload(g):
+    from synth.queries import (predicate_for_selectivity, range_pattern, star_query,
+                               union_query)
+    from synth import Pattern
+    preds = [predicate_for_selectivity(g, s) for s in (1e-3, 1e-2, 1e-1)]
+    scans = [Pattern(0, p, 0, 0, -1, 1) for p, _ in preds]
+    star, star_info = star_query(g)
+    union, union_info = union_query(g)
+    rng, rng_info = range_pattern(g)
+    return {"preds": preds, "scans": scans, "star": star, "star_info": star_info,
+            "union": union, "union_info": union_info, "range": rng, "range_info": rng_info}
+
+
+def cpu_baseline(g, w):
+    """The oracle, as it stands, on this host: one full step of the same
+    workload (single-threaded plain C), repeated while under ~20 s."""
     import oracle
     oracle.build(force=False)
     n = g.shape[0]
-    # calibrate on 1M triples, then size the sample to about budget_s / 3
-    probe = g[: min(n, 1_000_000)]
-    t0 = time.perf_counter()
-    for p in patterns:
-        oracle.scan(probe, p)
-    per_triple = (time.perf_counter() - t0) / (probe.shape[0] * len(patterns))
-    m = int(min(n, max(probe.shape[0], budget_s / 3 / max(per_triple, 1e-12) / len(patterns))))
-    sample = np.ascontiguousarray(g[:m])
-    reps = 3
-    t0 = time.perf_counter()
+    reps, t_total = 0, 0.0
+    per = {}
+    while reps < 3 and t_total < 20.0:
+        t0 = time.perf_counter()
+        for p in w["scans"]:
+            oracle.scan(g, p)
+        t1 = time.perf_counter()
+        oracle.query(g, w["star"])
+        t2 = time.perf_counter()
+        oracle.query(g, w["union"])
+        t3 = time.perf_counter()
+        oracle.scan(g, w["range"])
+        t4 = time.perf_counter()
+        per = {"scans_s": t1 - t0, "star_s": t2 - t1, "union_s": t3 - t2, "filter_s": t4 - t3}
+        t_total += t4 - t0
+        reps += 1
+    step_s = t_total / reps
+    return {"value": 6 * n / step_s, "unit": "triples/s", "cores": 1, "kind": "oracle",
+            "sample": f"the full step on the same 50M-triple graph, {reps} rep(s), "
+                      f"single-threaded plain C (gcc -O2); last rep: "
+                      + ", ".join(f"{k} {v:.2f}" for k, v in per.items())}
+
+
+def event_time(torch, stream, fn, reps):
+    """Average seconds per call of fn, with HIP events on `stream`, calls
+    queued back to back."""
+    keep = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
     for _ in range(reps):
-        for p in patterns:
-            oracle.scan(sample, p)
-    dt = time.perf_counter() - t0
-    return {"value": reps * len(patterns) * m / dt, "unit": "triples/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first {m} triples of the medium graph, the same {len(patterns)} scans, "
-                      f"{reps} reps, single-threaded plain C (gcc -O2)"}
+        keep.append(fn())
+    ev1.record(stream)
+    ev1.synchronize()
+    for t in keep:
+        t.free()
+    return ev0.elapsed_time(ev1) / 1e3 / reps
 
 
 def main():
@@ -100,15 +130,15 @@ def main():
 
     import torch
     from paper_1807_01409_amd import Context
-    from synth import CONFIGS, Pattern, make_graph
+    from synth import CONFIGS, make_graph
 
     spec = CONFIGS["medium"] if args.n is None else CONFIGS["medium"].with_n(args.n)
     t0 = time.time()
     g = make_graph(spec)
     log(f"generated {spec.n} triples in {time.time() - t0:.1f}s")
-    preds = pick_predicates(g, (1e-3, 1e-2, 1e-1))
-    patterns = [Pattern(0, p, 0, 0, -1, 1) for p, _ in preds]
-    log(f"predicates {preds}")
+    w = build_workload(g)
+    log(f"workload: preds {w['preds']} star {w['star_info']} union {w['union_info']} "
+        f"range {w['range_info']}")
 
     ctx = Context(0)
     G = ctx.load(g)
@@ -116,8 +146,11 @@ def main():
     log("graph resident")
 
     def step():
-        for p in patterns:
+        for p in w["scans"]:
             ctx.scan(G, p).free()
+        ctx.query(G, w["star"]).free()
+        ctx.query(G, w["union"]).free()
+        ctx.scan(G, w["range"]).free()
 
     for _ in range(args.warmup):
         step()
@@ -127,45 +160,39 @@ def main():
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    passes = 6
     ms_per_step = elapsed / args.steps * 1e3
-    passes = len(patterns)
     value = passes * spec.n * args.steps / elapsed
-    log(f"{ms_per_step:.3f} ms/step")
+    log(f"{ms_per_step:.3f} ms/step, {value / 1e9:.1f} G triples/s")
 
-    # dominant kernel: the scan.  Average launch duration with HIP events on
-    # the context's stream (the stream the kernels are launched on), launches
-    # queued back to back so that host overhead is hidden.
+    # Dominant kernel: the single-pattern scan.  Average launch duration with
+    # HIP events on the context's stream (the stream its kernels run on).
     reps = 20
-    alg_bytes = 0.0
-    dur_s = 0.0
-    per_pattern = []
-    for p, (pid, sigma) in zip(patterns, preds):
-        rows = ctx.scan(G, p).nrows
-        tabs = []
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        ev0.record(ctx.stream)
-        for _ in range(reps):
-            tabs.append(ctx.scan(G, p))
-        ev1.record(ctx.stream)
-        ev1.synchronize()
-        for t in tabs:
-            t.free()
-        d = ev0.elapsed_time(ev1) / 1e3 / reps
-        b = 12.0 * spec.n + 4.0 * 2 * rows
+    alg_bytes = dur_s = 0.0
+    per_launch = []
+    for p in w["scans"] + [w["range"]]:
+        t = ctx.scan(G, p)
+        rows, ncols = t.nrows, t.ncols
+        t.free()
+        d = event_time(torch, ctx.stream, lambda: ctx.scan(G, p), reps)
+        b = 12.0 * spec.n + 4.0 * ncols * rows
         alg_bytes += b
         dur_s += d
-        per_pattern.append({"p": pid, "selectivity": sigma, "rows": rows,
-                            "us_per_launch": d * 1e6, "GBps": b / d / 1e9})
+        per_launch.append({"rows": rows, "cols": ncols, "us": round(d * 1e6, 2),
+                           "GBps": round(b / d / 1e9, 1)})
     achieved = alg_bytes / dur_s / 1e9
-    khash = source_hash(["paper_1807_01409_amd/csrc/scan.hip",
-                         "paper_1807_01409_amd/csrc/device_common.hpp"])
-    traffic = measured_traffic(khash)
-    log(f"scan per pattern: {per_pattern}")
+    khash = source_hash(SCAN_SOURCES)
+    breakdown = {
+        "star_query_ms": event_time(torch, ctx.stream, lambda: ctx.query(G, w["star"]), 5) * 1e3,
+        "union_query_ms": event_time(torch, ctx.stream, lambda: ctx.query(G, w["union"]), 5) * 1e3,
+        "star_rows": ctx.query(G, w["star"]).nrows,
+        "union_rows": ctx.query(G, w["union"]).nrows,
+    }
+    log(f"scan launches: {per_launch}; {breakdown}")
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(g, patterns)
+        cpu = cpu_baseline(g, w)
         log(f"cpu baseline {cpu}")
 
     out = {
@@ -181,14 +208,18 @@ def main():
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
-        "config": {"workload": f"medium graph, {spec.n} triples (Zipf s 1.0/5M, p 1.2/1000, "
-                               f"o 1.1/10M); step = scans (?s p ?o) at selectivity "
-                               f"{[round(s, 5) for _, s in preds]}",
-                   "n_triples": spec.n, "predicates": [p for p, _ in preds],
-                   "graph_passes_per_step": passes},
+        "config": {"workload": f"medium graph: {spec.n} triples (s Zipf 1.0/5M, p Zipf 1.2/1000, "
+                               "o Zipf 1.1/10M); step = 3 scans (0.1/1/10%), 3-star join, "
+                               "8-way union DISTINCT, 5% object-range filter",
+                   "n_triples": spec.n, "graph_passes_per_step": passes,
+                   "scan_predicates": [p for p, _ in w["preds"]],
+                   "scan_selectivity": [round(s, 6) for _, s in w["preds"]],
+                   "star": w["star_info"], "union": w["union_info"], "range": w["range_info"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "scan_kernel<256,16,1>", "per_launch": per_pattern},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(khash),
+                     "kernel": "compact_kernel<ScanSrc<1>,512,16,1,3> (single-pattern scan)",
+                     "per_launch": per_launch},
+        "breakdown": breakdown,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

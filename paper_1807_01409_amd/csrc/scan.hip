@@ -89,6 +89,224 @@ struct FilterSrc {
 };
 
 // ---------------------------------------------------------------------------
+// Multi-pattern pass (Sec. 4.1): up to 16 patterns tested against every triple
+// of one read of the graph.  The patterns and output descriptors live in LDS
+// and are walked by a runtime loop, so the register footprint does not grow
+// with the number of patterns.  Compaction and placement follow the range
+// scheme of compact.hpp, with one staging area per pattern.
+// ---------------------------------------------------------------------------
+
+struct MultiOut {
+    uint32_t *col[3];
+    uint64_t cap;
+    uint64_t *count;
+    int32_t ncols;
+    uint32_t stage_off, stage_cap;
+};
+
+struct MultiArgs {
+    DevPattern pat[TID_MAX_MULTI];
+    MultiOut out[TID_MAX_MULTI];
+    int32_t k;
+    uint32_t P;
+    uint64_t range;
+};
+
+template <int BLOCK, int IPT>
+__device__ __forceinline__ uint32_t multi_bits(const DevPattern &q, const Tri *t, uint64_t t0,
+                                               uint64_t r1) {
+    uint32_t mb = 0;
+#pragma unroll
+    for (int it = 0; it < IPT; ++it)
+        if (t0 + (uint64_t)it * BLOCK + threadIdx.x < r1 && match_pattern(q, t[it]))
+            mb |= 1u << it;
+    return mb;
+}
+
+template <int BLOCK, int IPT>
+__global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__restrict__ g,
+                                                            uint64_t n, MultiArgs a,
+                                                            uint64_t *sync, uint32_t *flags) {
+    constexpr int NW = BLOCK / dev::kWave;
+    constexpr int NV = IPT * NW;
+    constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
+    extern __shared__ uint32_t stage[];
+    __shared__ DevPattern s_pat[TID_MAX_MULTI];
+    __shared__ MultiOut s_out[TID_MAX_MULTI];
+    __shared__ uint32_t s_off[TID_MAX_MULTI][NV];
+    __shared__ uint32_t s_tot[TID_MAX_MULTI];
+    __shared__ uint64_t s_cnt[TID_MAX_MULTI], s_staged[TID_MAX_MULTI], s_ovf[TID_MAX_MULTI];
+    __shared__ uint64_t s_pre[TID_MAX_MULTI], s_run[TID_MAX_MULTI];
+    __shared__ uint64_t s_red[TID_MAX_MULTI][NW];
+    __shared__ uint32_t s_wg;
+
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const int k = a.k;
+    const uint32_t P = a.P;
+    uint32_t *counters = reinterpret_cast<uint32_t *>(sync + (size_t)k * P);
+    // thread j copies descriptor j (static indices into the kernel arguments)
+#pragma unroll
+    for (int j = 0; j < TID_MAX_MULTI; ++j)
+        if (tid == j && j < k) {
+            s_pat[j] = a.pat[j];
+            s_out[j] = a.out[j];
+            s_cnt[j] = 0;
+            s_staged[j] = 0;
+            s_ovf[j] = kNoTile;
+        }
+    if (tid == 0) s_wg = atomicAdd(&counters[0], 1u);
+    __syncthreads();
+    const uint32_t wg = s_wg;
+    const uint64_t r0 = (uint64_t)wg * a.range;
+    const uint64_t r1 = min(n, r0 + a.range);
+    Tri t[IPT];
+
+    auto load_tile = [&](uint64_t t0) {
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
+            if (i < r1) t[it] = *reinterpret_cast<const Tri *>(g + 3 * i);
+            else t[it].v[0] = t[it].v[1] = t[it].v[2] = 0;
+        }
+    };
+    auto count_tile = [&](uint64_t t0) {
+        for (int j = 0; j < k; ++j) {
+            const uint32_t mb = multi_bits<BLOCK, IPT>(s_pat[j], t, t0, r1);
+#pragma unroll
+            for (int it = 0; it < IPT; ++it) {
+                const uint64_t b = dev::ballot((mb >> it) & 1u);
+                if (lane == 0) s_off[j][it * NW + wave] = (uint32_t)__popcll(b);
+            }
+        }
+        __syncthreads();
+        for (int j = wave; j < k; j += NW) {
+            const uint32_t tot = dev::offsets_in_place<NV>(s_off[j]);
+            if (lane == 0) s_tot[j] = tot;
+        }
+        __syncthreads();
+    };
+
+    // ---- phase 1 ------------------------------------------------------------
+    for (uint64_t t0 = r0; t0 < r1; t0 += TILE) {
+        load_tile(t0);
+        count_tile(t0);
+        for (int j = 0; j < k; ++j) {
+            const MultiOut &o = s_out[j];
+            const uint64_t cnt = s_cnt[j];
+            if (o.ncols == 0 || s_ovf[j] != kNoTile || cnt + s_tot[j] > o.stage_cap) continue;
+            const DevPattern &q = s_pat[j];
+            const uint32_t mb = multi_bits<BLOCK, IPT>(q, t, t0, r1);
+#pragma unroll
+            for (int it = 0; it < IPT; ++it) {
+                const bool bit = (mb >> it) & 1u;
+                const uint64_t b = dev::ballot(bit);
+                if (bit) {
+                    const uint32_t r =
+                        (uint32_t)cnt + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
+                    for (int c = 0; c < o.ncols; ++c)
+                        stage[o.stage_off + (uint32_t)c * o.stage_cap + r] = pick(t[it], q.src[c]);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < k) {
+            if (s_ovf[tid] == kNoTile && s_cnt[tid] + s_tot[tid] > s_out[tid].stage_cap) {
+                s_ovf[tid] = t0;
+                s_staged[tid] = s_cnt[tid];
+            }
+            s_cnt[tid] += s_tot[tid];
+        }
+    }
+    __syncthreads();
+
+    // ---- prefix over earlier ranges ----------------------------------------
+    if (tid < k) {
+        if (s_ovf[tid] == kNoTile) s_staged[tid] = s_cnt[tid];
+        dev::publish(&sync[(size_t)tid * P + wg], kPublished | s_cnt[tid]);
+    }
+    for (int j = 0; j < k; ++j) {
+        uint64_t w[kPrefixPer];
+#pragma unroll
+        for (int u = 0; u < kPrefixPer; ++u) {
+            const uint32_t i = tid + u * BLOCK;
+            w[u] = i < wg ? dev::peek(&sync[(size_t)j * P + i]) : kPublished;
+        }
+        uint64_t part = 0;
+#pragma unroll
+        for (int u = 0; u < kPrefixPer; ++u) {
+            const uint32_t i = tid + u * BLOCK;
+            uint32_t spins = 0;
+            while (!(w[u] & kPublished)) {
+                if (++spins > kSpinLimit) {
+                    atomicOr(&flags[0], 1u);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                w[u] = dev::peek(&sync[(size_t)j * P + i]);
+            }
+            part += w[u] & ~kPublished;
+        }
+        part = dev::wave_sum(part);
+        if (lane == 0) s_red[j][wave] = part;
+    }
+    __syncthreads();
+    if (tid < k) {
+        uint64_t sum = 0;
+        for (int w = 0; w < NW; ++w) sum += s_red[tid][w];
+        s_pre[tid] = sum;
+        s_run[tid] = s_staged[tid];
+    }
+    __syncthreads();
+
+    // ---- phase 2 ------------------------------------------------------------
+    for (int j = 0; j < k; ++j) {
+        const MultiOut &o = s_out[j];
+        if (o.ncols == 0) continue;
+        const uint64_t pre = s_pre[j];
+        const uint32_t st = (uint32_t)s_staged[j];
+        for (uint32_t r = tid; r < st; r += BLOCK) {
+            const uint64_t dst = pre + r;
+            if (dst < o.cap) {
+                for (int c = 0; c < o.ncols; ++c)
+                    o.col[c][dst] = stage[o.stage_off + (uint32_t)c * o.stage_cap + r];
+            } else {
+                atomicOr(&flags[1], 1u);
+            }
+        }
+    }
+    uint64_t first = kNoTile;
+    for (int j = 0; j < k; ++j) first = min(first, s_ovf[j]);
+    for (uint64_t t0 = first; t0 < r1; t0 += TILE) {
+        load_tile(t0);
+        count_tile(t0);
+        for (int j = 0; j < k; ++j) {
+            if (s_ovf[j] > t0) continue;
+            const MultiOut &o = s_out[j];
+            const DevPattern &q = s_pat[j];
+            const uint64_t base = s_pre[j] + s_run[j];
+            const uint32_t mb = multi_bits<BLOCK, IPT>(q, t, t0, r1);
+#pragma unroll
+            for (int it = 0; it < IPT; ++it) {
+                const bool bit = (mb >> it) & 1u;
+                const uint64_t b = dev::ballot(bit);
+                if (bit) {
+                    const uint64_t dst = base + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
+                    if (dst < o.cap) {
+                        for (int c = 0; c < o.ncols; ++c) o.col[c][dst] = pick(t[it], q.src[c]);
+                    } else {
+                        atomicOr(&flags[1], 1u);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (tid < k && s_ovf[tid] <= t0) s_run[tid] += s_tot[tid];
+    }
+    if (wg == P - 1 && tid < k) *s_out[tid].count = s_pre[tid] + s_cnt[tid];
+    dev::release_state(sync, (size_t)k * P, counters, P);
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -197,14 +415,59 @@ static void run_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, 
     throw Error(TID_E_INVALID_ARG, "scan: unsupported (block, items) shape");
 }
 
+template <int BLOCK, int IPT>
+static void launch_multi(tid_ctx *ctx, const tid_graph *g, MultiArgs &a, int k, uint32_t sw) {
+    constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
+    auto kern = scan_multi_kernel<BLOCK, IPT>;
+    const size_t lds = (size_t)sw * sizeof(uint32_t);
+    static int blocks_per_cu = -1;
+    static size_t blocks_lds = 0;
+    if (blocks_per_cu < 0 || blocks_lds != lds) {
+        int nb = 0;
+        TID_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, BLOCK, lds));
+        blocks_per_cu = std::max(nb, 1);
+        blocks_lds = lds;
+    }
+    uint64_t cols_total = 0;
+    for (int j = 0; j < k; ++j) cols_total += (uint64_t)a.out[j].ncols;
+    const uint32_t rows_per = (uint32_t)(sw / std::max<uint64_t>(cols_total, 1));
+    uint32_t off = 0;
+    for (int j = 0; j < k; ++j) {
+        a.out[j].stage_off = off;
+        a.out[j].stage_cap = a.out[j].ncols ? rows_per : 0xFFFFFFFFu;
+        off += rows_per * (uint32_t)a.out[j].ncols;
+    }
+    const uint64_t n = g->n;
+    const uint64_t tiles = (n + TILE - 1) / TILE;
+    const uint64_t resident = (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx);
+    uint64_t P = std::max<uint64_t>(1, std::min({tiles, resident, (uint64_t)BLOCK * kPrefixPer}));
+    const uint64_t range = (tiles + P - 1) / P * TILE;
+    P = (n + range - 1) / range;
+    a.k = k;
+    a.P = (uint32_t)P;
+    a.range = range;
+    uint64_t *sync =
+        static_cast<uint64_t *>(ctx->lookback_state(((size_t)k * P + 1) * sizeof(uint64_t)));
+    hipLaunchKernelGGL(kern, dim3((uint32_t)P), dim3(BLOCK), lds, ctx->stream,
+                       g->data.get<const uint32_t>(), n, a, sync, ctx->d_flags);
+    TID_HIP(hipGetLastError());
+}
+
 static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                          tid_table *const *outs) {
-    if (k == 1)
+    if (k == 1) {
         run_scan<1>(ctx, g, pats, k, outs);
-    else if (k <= 4)
-        run_scan<4>(ctx, g, pats, k, outs);
-    else
-        run_scan<TID_MAX_MULTI>(ctx, g, pats, k, outs);
+        return;
+    }
+    MultiArgs a{};
+    for (int j = 0; j < k; ++j) {
+        a.pat[j] = compile_pattern(pats[j]);
+        for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
+        a.out[j].cap = outs[j]->cap;
+        a.out[j].count = outs[j]->d_count;
+        a.out[j].ncols = outs[j]->ncols;
+    }
+    launch_multi<512, 16>(ctx, g, a, k, stage_words(ctx));
 }
 
 void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,

@@ -7,8 +7,8 @@
 //   hist     each workgroup owns one contiguous range of the input and counts
 //            the digits of its range (wave-private LDS histograms, updated
 //            by the leader lane of each group of lanes holding one digit);
-//   scan     one flat exclusive scan over the digit-major count matrix gives,
-//            for every (digit, range), where its elements go;
+//   offsets  one workgroup turns the range-major count matrix into, for every
+//            (range, digit), the place where its first element goes;
 //   scatter  each workgroup walks its range tile by tile and writes every
 //            element at its digit's running offset plus its stable rank,
 //            found with ballots that group the lanes holding equal digits.
@@ -49,7 +49,7 @@ __device__ __forceinline__ uint64_t sort_item(uint64_t t0, int wave, int it, int
 
 __global__ __launch_bounds__(kSortBlock) void radix_hist(const uint64_t *__restrict__ keys,
                                                           uint64_t n, uint64_t range, int shift,
-                                                          uint32_t *counts, uint32_t P) {
+                                                          uint32_t *counts) {
     __shared__ uint32_t s_h[kSortNW][kRadix];
     const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
     for (uint32_t d = tid; d < kSortNW * kRadix; d += kSortBlock) (&s_h[0][0])[d] = 0;
@@ -74,41 +74,56 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist(const uint64_t *__restr
     for (uint32_t dd = tid; dd < kRadix; dd += kSortBlock) {
         uint32_t s = 0;
         for (int ww = 0; ww < kSortNW; ++ww) s += s_h[ww][dd];
-        counts[(size_t)dd * P + w] = s;
+        counts[(size_t)w * kRadix + dd] = s;
     }
 }
 
-// exclusive scan of m uint32 in one workgroup (m is at most kRadix * 2048)
-__global__ __launch_bounds__(1024) void flat_exclusive_scan(const uint32_t *in, uint32_t *out,
-                                                             uint32_t m) {
-    __shared__ uint32_t s_w[16];
-    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
-    const uint32_t chunk = (m + 1023) / 1024;
-    const uint32_t a = min(m, tid * chunk), b = min(m, a + chunk);
+// Where each (range, digit) goes: offs[w][d] = sum of all counts of digits
+// below d, plus the counts of digit d in ranges before w.  One workgroup:
+// thread t takes digit t % 256 over one quarter of the ranges, so every load
+// of the range-major count matrix is coalesced across digits.
+constexpr int kOffThreads = 1024;
+constexpr int kOffParts = kOffThreads / (int)kRadix;
+__global__ __launch_bounds__(kOffThreads) void digit_offsets(const uint32_t *__restrict__ counts,
+                                                              uint32_t *__restrict__ offs,
+                                                              uint32_t P) {
+    __shared__ uint32_t s_part[kOffParts][kRadix];
+    __shared__ uint32_t s_base[kRadix];
+    __shared__ uint32_t s_w[kRadix / dev::kWave];
+    const int tid = threadIdx.x;
+    const uint32_t d = tid % kRadix, q = tid / kRadix;
+    const uint32_t per = (P + kOffParts - 1) / kOffParts;
+    const uint32_t w0 = min(P, q * per), w1 = min(P, w0 + per);
     uint32_t sum = 0;
-    for (uint32_t i = a; i < b; ++i) sum += in[i];
-    const uint32_t incl = dev::wave_inclusive_sum(sum);
-    if (lane == dev::kWave - 1) s_w[wave] = incl;
+    for (uint32_t w = w0; w < w1; ++w) sum += counts[(size_t)w * kRadix + d];
+    s_part[q][d] = sum;
     __syncthreads();
-    uint32_t before = 0;
-    for (int ww = 0; ww < wave; ++ww) before += s_w[ww];
-    uint32_t run = before + incl - sum;
-    for (uint32_t i = a; i < b; ++i) {
-        const uint32_t v = in[i];
-        out[i] = run;
-        run += v;
+    if (tid < (int)kRadix) {
+        uint32_t tot = 0;
+        for (int x = 0; x < kOffParts; ++x) tot += s_part[x][d];
+        const uint32_t incl = dev::wave_inclusive_sum(tot);
+        if (dev::lane_id() == dev::kWave - 1) s_w[tid / dev::kWave] = incl;
+        s_base[d] = incl - tot;  // exclusive within the wave for now
+    }
+    __syncthreads();
+    uint32_t run = s_base[d];
+    for (uint32_t x = 0; x < d / dev::kWave; ++x) run += s_w[x];
+    for (uint32_t x = 0; x < q; ++x) run += s_part[x][d];
+    for (uint32_t w = w0; w < w1; ++w) {
+        const uint32_t c = counts[(size_t)w * kRadix + d];
+        offs[(size_t)w * kRadix + d] = run;
+        run += c;
     }
 }
 
 __global__ __launch_bounds__(kSortBlock) void radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, uint64_t n, uint64_t range, int shift, const uint32_t *offs,
-    uint32_t P) {
+    uint32_t *__restrict__ vout, uint64_t n, uint64_t range, int shift, const uint32_t *offs) {
     __shared__ uint32_t s_run[kRadix];
     __shared__ uint32_t s_wh[kSortNW][kRadix];
     const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
     const uint32_t w = blockIdx.x;
-    for (uint32_t d = tid; d < kRadix; d += kSortBlock) s_run[d] = offs[(size_t)d * P + w];
+    for (uint32_t d = tid; d < kRadix; d += kSortBlock) s_run[d] = offs[(size_t)w * kRadix + d];
     const uint64_t r0 = (uint64_t)w * range, r1 = min(n, r0 + range);
     const uint64_t lt = (1ull << lane) - 1ull;
     for (uint64_t t0 = r0; t0 < r1; t0 += kSortTile) {
@@ -192,14 +207,19 @@ __global__ void gather_rows(GatherArgs a, const uint32_t *perm, uint64_t n) {
     }
 }
 
-__global__ void column_max(const uint32_t *const *cols, uint64_t n, uint32_t *mx) {
+// per-column maximum: one atomic per workgroup after an LDS reduction
+__global__ __launch_bounds__(256) void column_max(const uint32_t *const *cols, uint64_t n,
+                                                   uint32_t *mx) {
+    __shared__ uint32_t s_m[4];
     const uint32_t *col = cols[blockIdx.y];
     uint32_t m = 0;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         m = max(m, col[i]);
     for (int d = 32; d >= 1; d >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, 64));
-    if (dev::lane_id() == 0) atomicMax(&mx[blockIdx.y], m);
+    if (dev::lane_id() == 0) s_m[threadIdx.x / 64] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(&mx[blockIdx.y], max(max(s_m[0], s_m[1]), max(s_m[2], s_m[3])));
 }
 
 __global__ void fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
@@ -264,14 +284,13 @@ bool radix_sort_pairs(tid_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
         uint64_t *ko = flip ? k0 : k1;
         uint32_t *vo = flip ? v0 : v1;
         hipLaunchKernelGGL(radix_hist, dim3((uint32_t)P), dim3(kSortBlock), 0, ctx->stream, ki, n,
-                           range, shift, counts.get<uint32_t>(), (uint32_t)P);
+                           range, shift, counts.get<uint32_t>());
         TID_HIP(hipGetLastError());
-        hipLaunchKernelGGL(flat_exclusive_scan, dim3(1), dim3(1024), 0, ctx->stream,
-                           counts.get<const uint32_t>(), offs.get<uint32_t>(),
-                           (uint32_t)(kRadix * P));
+        hipLaunchKernelGGL(digit_offsets, dim3(1), dim3(kOffThreads), 0, ctx->stream,
+                           counts.get<const uint32_t>(), offs.get<uint32_t>(), (uint32_t)P);
         TID_HIP(hipGetLastError());
         hipLaunchKernelGGL(radix_scatter, dim3((uint32_t)P), dim3(kSortBlock), 0, ctx->stream, ki,
-                           vi, ko, vo, n, range, shift, offs.get<const uint32_t>(), (uint32_t)P);
+                           vi, ko, vo, n, range, shift, offs.get<const uint32_t>());
         TID_HIP(hipGetLastError());
         flip = !flip;
     }
@@ -286,7 +305,7 @@ std::vector<uint32_t> column_maxima(tid_ctx *ctx, const tid_table *t, uint64_t n
     TID_HIP(hipMemcpyAsync(cols.get(), t->col, sizeof(uint32_t *) * t->ncols,
                            hipMemcpyHostToDevice, ctx->stream));
     TID_HIP(hipMemsetAsync(dmx.get(), 0, sizeof(uint32_t) * t->ncols, ctx->stream));
-    hipLaunchKernelGGL(column_max, dim3(grid_for(n, 256, 1024), t->ncols), dim3(256), 0,
+    hipLaunchKernelGGL(column_max, dim3(grid_for(n, 256, 512), t->ncols), dim3(256), 0,
                        ctx->stream, cols.get<const uint32_t *const>(), n, dmx.get<uint32_t>());
     TID_HIP(hipGetLastError());
     TID_HIP(hipMemcpyAsync(mx.data(), dmx.get(), sizeof(uint32_t) * t->ncols,
