@@ -196,6 +196,14 @@ typedef struct {
    joins, unions, filters, projections and DISTINCT on the device.
    Synchronises (intermediate sizes). */
 tid_status tid_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan, tid_table **out);
+/* Evaluate nq plans together: outs[i] receives exactly what tid_query would
+   return for plans[i].  The patterns of all plans are searched in shared
+   multi-pattern passes over the graph (Sec. 4.1 keysArray, at batch scale)
+   and the plans' joins, unions and sorts advance in lockstep, so the host
+   waits for the device once per round for the whole batch.  On error no
+   output is written.  Synchronises. */
+tid_status tid_query_batch(tid_ctx *ctx, const tid_graph *g, const tid_plan *const *plans,
+                           int32_t nq, tid_table **outs);
 
 #ifdef __cplusplus
 }

@@ -71,6 +71,8 @@ def _setup(lib):
                              ctypes.c_int32, P(_Tab)]
     lib.or_table_free.argtypes = [P(_Tab)]
     lib.or_table_free.restype = None
+    lib.or_set_nested_join_limit.argtypes = [ctypes.c_double]
+    lib.or_set_nested_join_limit.restype = None
     return lib
 
 
@@ -217,6 +219,11 @@ def distinct(t: Table) -> Table:
     a = _to_c(Table(t.rows.copy(), list(t.vars)), keep)
     _check(_L().or_distinct(ctypes.byref(a)), "distinct")
     return Table(keep[0][: int(a.nrows)].copy(), list(t.vars))
+
+
+def set_nested_join_limit(pairs: float) -> None:
+    """Plan joins above this many row pairs use sort-merge (default 1e8)."""
+    _L().or_set_nested_join_limit(float(pairs))
 
 
 def query(g, plan) -> Table:

@@ -363,6 +363,12 @@ static int32_t col_of(const or_table *t, int32_t var)
     return -1;
 }
 
+/* Plan joins switch from nested loops to Sec. 4.2's sort-merge when the
+   number of row pairs exceeds this; both give the same multiset. */
+static double g_nested_limit = 1e8;
+
+void or_set_nested_join_limit(double pairs) { g_nested_limit = pairs; }
+
 /* Join of two subquery results on variable `var`: the inner join on that
    column pair (Sec. 4.2); any other variable the two sides share must also
    agree, and appears once in the output. */
@@ -380,34 +386,72 @@ static int natural_join(const or_table *l, const or_table *r, int32_t var, or_ta
     }
     int32_t nc = l->ncols + nkeep;
     if (nc > OR_MAXCOLS) return OR_E_SCHEMA;
+
+    /* candidate pairs (i, j) with equal keys: all pairs for nested loops, or
+       the equal-key runs of the two sorted key vectors for sort-merge */
+    int sortmerge = (double)l->nrows * (double)r->nrows > g_nested_limit;
+    key_idx *kl = NULL, *kr = NULL;
+    if (sortmerge) {
+        kl = (key_idx *)malloc((l->nrows ? l->nrows : 1) * sizeof(key_idx));
+        kr = (key_idx *)malloc((r->nrows ? r->nrows : 1) * sizeof(key_idx));
+        if (!kl || !kr) { free(kl); free(kr); return OR_E_OOM; }
+        for (uint64_t i = 0; i < l->nrows; ++i) { kl[i].key = l->rows[i * l->ncols + lc]; kl[i].idx = i; }
+        for (uint64_t j = 0; j < r->nrows; ++j) { kr[j].key = r->rows[j * r->ncols + rc]; kr[j].idx = j; }
+        qsort(kl, (size_t)l->nrows, sizeof(key_idx), key_idx_cmp);
+        qsort(kr, (size_t)r->nrows, sizeof(key_idx), key_idx_cmp);
+    }
     uint64_t cnt = 0;
     for (int pass = 0; pass < 2; ++pass) {
         uint64_t w = 0;
-        for (uint64_t i = 0; i < l->nrows; ++i) {
-            const uint32_t *lr = l->rows + i * l->ncols;
-            for (uint64_t j = 0; j < r->nrows; ++j) {
-                const uint32_t *rr = r->rows + j * r->ncols;
-                if (lr[lc] != rr[rc]) continue;
-                int ok = 1;
-                for (int32_t e = 0; e < neq; ++e)
-                    if (lr[eq_l[e]] != rr[eq_r[e]]) ok = 0;
-                if (!ok) continue;
-                if (pass == 1) {
-                    uint32_t *dst = out->rows + w * nc;
-                    for (int32_t x = 0; x < l->ncols; ++x) dst[x] = lr[x];
-                    for (int32_t x = 0; x < nkeep; ++x) dst[l->ncols + x] = rr[keep[x]];
+        uint64_t a = 0, b = 0;
+        /* iterate candidate pairs */
+        for (;;) {
+            uint64_t i0, i1, j0, j1;
+            if (sortmerge) {
+                while (a < l->nrows && b < r->nrows && kl[a].key != kr[b].key) {
+                    if (kl[a].key < kr[b].key) ++a; else ++b;
                 }
-                ++w;
+                if (a >= l->nrows || b >= r->nrows) break;
+                uint64_t a2 = a, b2 = b;
+                while (a2 < l->nrows && kl[a2].key == kl[a].key) ++a2;
+                while (b2 < r->nrows && kr[b2].key == kr[b].key) ++b2;
+                i0 = a; i1 = a2; j0 = b; j1 = b2;
+                a = a2; b = b2;
+            } else {
+                if (a > 0) break;
+                i0 = 0; i1 = l->nrows; j0 = 0; j1 = r->nrows;
+                a = 1;
+            }
+            for (uint64_t x = i0; x < i1; ++x) {
+                uint64_t i = sortmerge ? kl[x].idx : x;
+                const uint32_t *lr = l->rows + i * l->ncols;
+                for (uint64_t y = j0; y < j1; ++y) {
+                    uint64_t j = sortmerge ? kr[y].idx : y;
+                    const uint32_t *rr = r->rows + j * r->ncols;
+                    if (lr[lc] != rr[rc]) continue;
+                    int ok = 1;
+                    for (int32_t e = 0; e < neq; ++e)
+                        if (lr[eq_l[e]] != rr[eq_r[e]]) ok = 0;
+                    if (!ok) continue;
+                    if (pass == 1) {
+                        uint32_t *dst = out->rows + w * nc;
+                        for (int32_t c = 0; c < l->ncols; ++c) dst[c] = lr[c];
+                        for (int32_t c = 0; c < nkeep; ++c) dst[l->ncols + c] = rr[keep[c]];
+                    }
+                    ++w;
+                }
             }
         }
         if (pass == 0) {
             cnt = w;
             int st = table_alloc(out, cnt, nc);
-            if (st) return st;
-            for (int32_t x = 0; x < l->ncols; ++x) out->vars[x] = l->vars[x];
-            for (int32_t x = 0; x < nkeep; ++x) out->vars[l->ncols + x] = r->vars[keep[x]];
+            if (st) { free(kl); free(kr); return st; }
+            for (int32_t c = 0; c < l->ncols; ++c) out->vars[c] = l->vars[c];
+            for (int32_t c = 0; c < nkeep; ++c) out->vars[l->ncols + c] = r->vars[keep[c]];
         }
     }
+    free(kl);
+    free(kr);
     return OR_OK;
 }
 

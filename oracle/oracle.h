@@ -86,6 +86,8 @@ int or_distinct(or_table *t);
 int or_query(const uint32_t *g, uint64_t n, const or_pattern *pats, int32_t npats,
              const uint32_t *ops, int32_t nops, or_table *out);
 void or_table_free(or_table *t);
+/* plan joins above this many row pairs use sort-merge instead of nested loops */
+void or_set_nested_join_limit(double pairs);
 
 #ifdef __cplusplus
 }

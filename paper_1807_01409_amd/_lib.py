@@ -67,6 +67,8 @@ SIGNATURES = {
     "tid_union": (_S, [_VP, _PP, ctypes.c_int32, ctypes.c_int32, _PP]),
     "tid_sort": (_S, [_VP, _VP, ctypes.c_int32, _PP]),
     "tid_query": (_S, [_VP, _VP, ctypes.POINTER(tid_plan), _PP]),
+    "tid_query_batch": (_S, [_VP, _VP, ctypes.POINTER(ctypes.POINTER(tid_plan)), ctypes.c_int32,
+                             _PP]),
 }
 
 

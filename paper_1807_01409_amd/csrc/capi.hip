@@ -42,6 +42,8 @@ std::unique_ptr<tid_table> join_tables(tid_ctx *, const tid_table *, int, const 
 std::unique_ptr<tid_table> union_tables(tid_ctx *, const tid_table *const *, int, int);
 std::unique_ptr<tid_table> sort_table(tid_ctx *, const tid_table *, int);
 std::unique_ptr<tid_table> run_query(tid_ctx *, const tid_graph *, const tid_plan *);
+std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *, const tid_graph *,
+                                                  const tid_plan *const *, int);
 std::unique_ptr<tid_table> copy_columns(tid_ctx *, const uint32_t *const *, int32_t,
                                         const int32_t *, uint64_t, int);
 }  // namespace tid
@@ -69,8 +71,6 @@ tid_status tid_ctx_create(int device, void *stream, tid_alloc_fn alloc, tid_free
         ctx->alloc_fn = alloc;
         ctx->free_fn = free_fn;
         ctx->user = user;
-        TID_HIP(hipHostMalloc((void **)&ctx->host_counts, 256 * sizeof(uint64_t),
-                              hipHostMallocDefault));
         ctx->d_flags = static_cast<uint32_t *>(ctx->alloc(2 * sizeof(uint32_t)));
         TID_HIP(hipMemsetAsync(ctx->d_flags, 0, 2 * sizeof(uint32_t), ctx->stream));
         TID_HIP(hipStreamSynchronize(ctx->stream));
@@ -89,7 +89,9 @@ void tid_ctx_destroy(tid_ctx *ctx) {
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->lb_state) ctx->free(ctx->lb_state, ctx->lb_bytes);
     if (ctx->d_flags) ctx->free(ctx->d_flags, 2 * sizeof(uint32_t));
-    if (ctx->host_counts) (void)hipHostFree(ctx->host_counts);
+    if (ctx->rw_dev) ctx->free(ctx->rw_dev, ctx->rw_cap * 16);
+    if (ctx->rw_host_ptrs) (void)hipHostFree(ctx->rw_host_ptrs);
+    if (ctx->rw_host_vals) (void)hipHostFree(ctx->rw_host_vals);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -341,6 +343,20 @@ tid_status tid_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan, tid
         res = tid::run_query(ctx, g, plan);
     });
     if (st == TID_OK) *out = res.release();
+    return st;
+}
+
+tid_status tid_query_batch(tid_ctx *ctx, const tid_graph *g, const tid_plan *const *plans,
+                           int32_t nq, tid_table **outs) {
+    std::vector<std::unique_ptr<tid_table>> res;
+    tid_status st = guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(g && outs && nq >= 0 && (nq == 0 || plans), TID_E_INVALID_ARG,
+                    "null argument");
+        res = tid::run_plans(ctx, g, plans, nq);
+    });
+    if (st == TID_OK)
+        for (int i = 0; i < nq; ++i) outs[i] = res[i].release();
     return st;
 }
 

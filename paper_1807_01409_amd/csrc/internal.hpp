@@ -72,11 +72,15 @@ struct tid_ctx {
     tid::Pool pool;
     std::string last_error;
     tid::Options opt;
-    uint64_t *host_counts = nullptr;  // pinned host words for count readback
     // scratch for look-back state: grown on demand, owned by the context
     void *lb_state = nullptr;
     size_t lb_bytes = 0;
     uint32_t *d_flags = nullptr;      // device error/overflow flags (2 words)
+    // staging for read_words: pinned pointer list and values, device copies
+    const uint64_t **rw_host_ptrs = nullptr;
+    uint64_t *rw_host_vals = nullptr;
+    void *rw_dev = nullptr;
+    size_t rw_cap = 0;
 
     void *alloc(size_t bytes);
     void free(void *p, size_t bytes);
@@ -154,6 +158,10 @@ struct tid_table {
     tid::DevBuf block;                // columns (each align_up(cap*4)) + 8-byte device count
     uint32_t *col[TID_MAX_COLS] = {};
     uint64_t *d_count = nullptr;
+    // host-side upper bound of every column's values (valid when maxv_known);
+    // lets sorts size their passes without reading the device
+    uint32_t maxv[TID_MAX_COLS] = {};
+    bool maxv_known = false;
 
     uint64_t rows();                  // host row count (may synchronise)
 };
@@ -169,6 +177,8 @@ std::unique_ptr<tid_table> make_table(tid_ctx *ctx, int32_t ncols, const int32_t
 void resolve_counts(tid_ctx *ctx, tid_table *const *ts, int k);
 // Write a known row count to the table's device word and host copy.
 void set_count(tid_ctx *ctx, tid_table *t, uint64_t n);
+// Column value bounds: dst column c takes the bound of src column map[c].
+void copy_bounds(tid_table *dst, const tid_table *src, const int *map, int n, int dst_off = 0);
 
 // ---- launchers implemented in the .hip files ------------------------------
 
@@ -183,6 +193,32 @@ std::unique_ptr<tid_table> filter_range(tid_ctx *ctx, const tid_table *t, int co
 struct JoinPlan {
     std::vector<int> lkeep, rkeep;
 };
+
+// A join whose matches are counted on the device but whose output size has
+// not reached the host yet (the split lets many joins share one round trip).
+struct PendingJoin {
+    const tid_table *L = nullptr, *R = nullptr;
+    std::unique_ptr<tid_table> own_l, own_r;  // inputs kept alive until expanded
+    int lc = 0, rc = 0;
+    JoinPlan jp;
+    std::vector<int32_t> vars;
+    DevBuf start, count, off, keys[4], vals[4];
+    DevBuf slots, slot_of, slot_count, slot_start, cursor, rows;
+    const uint32_t *qrow = nullptr, *brow = nullptr;
+    int probe_is_left = 1;
+    uint64_t nq = 0;
+    uint64_t total = 0;
+    bool total_known = false;
+    const uint64_t *d_total() const { return off.get<const uint64_t>() + nq; }
+};
+std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
+                                        const tid_table *R, uint64_t nr, int rc, int algo,
+                                        const JoinPlan &jp);
+std::unique_ptr<tid_table> join_finish(tid_ctx *ctx, PendingJoin &pj);
+
+// Read device words (counts, totals) to the host with one copy and one
+// synchronisation; also checks the device error flag.
+void read_words(tid_ctx *ctx, const std::vector<const uint64_t *> &src, uint64_t *dst);
 
 // validate and return the schema of a pattern; throws on a malformed pattern
 int pattern_schema(const tid_pattern &p, int32_t *vars, int32_t *src);

@@ -113,11 +113,14 @@ __global__ __launch_bounds__(kScanBlock) void range_scan(const uint32_t *__restr
     if (blockIdx.x == gridDim.x - 1 && tid == 0) out[n] = s_run;
 }
 
-// out[0..n] = exclusive prefix sums of in[0..n); out[n] = total.  Returns total.
-uint64_t exclusive_scan_u64(tid_ctx *ctx, const uint32_t *in, uint64_t n, uint64_t *out) {
+__global__ void set_zero_u64(uint64_t *p) { *p = 0; }
+
+// out[0..n] = exclusive prefix sums of in[0..n); out[n] = total, left on the device.
+void exclusive_scan_async(tid_ctx *ctx, const uint32_t *in, uint64_t n, uint64_t *out) {
     if (n == 0) {
-        TID_HIP(hipMemsetAsync(out, 0, sizeof(uint64_t), ctx->stream));
-        return 0;
+        hipLaunchKernelGGL(set_zero_u64, dim3(1), dim3(1), 0, ctx->stream, out);
+        TID_HIP(hipGetLastError());
+        return;
     }
     const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
     uint64_t P = std::max<uint64_t>(1, std::min<uint64_t>(tiles, 4096));
@@ -133,10 +136,6 @@ uint64_t exclusive_scan_u64(tid_ctx *ctx, const uint32_t *in, uint64_t n, uint64
     hipLaunchKernelGGL(range_scan, dim3((uint32_t)P), dim3(kScanBlock), 0, ctx->stream, in, n,
                        range, base.get<const uint64_t>(), out);
     TID_HIP(hipGetLastError());
-    uint64_t total = 0;
-    TID_HIP(hipMemcpyAsync(&total, out + n, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
-    ctx->sync();
-    return total;
 }
 
 // ---------------------------------------------------------------------------
@@ -298,120 +297,161 @@ void widen_u32(tid_ctx *ctx, const uint32_t *in, uint64_t n, uint64_t *out) {
 static int bitw(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
 std::vector<uint32_t> column_maxima(tid_ctx *ctx, const tid_table *t, uint64_t n);
 
-// Matches of L[lc] = R[rc] as an unsorted table of the columns lkeep of L
-// followed by the columns rkeep of R.
-std::unique_ptr<tid_table> join_unsorted(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
-                                         const tid_table *R, uint64_t nr, int rc, int algo,
-                                         const JoinPlan &jp) {
-    std::vector<int32_t> vars;
-    for (int c : jp.lkeep) vars.push_back(L->vars[c]);
-    for (int c : jp.rkeep) vars.push_back(R->vars[c]);
-    TID_REQUIRE(vars.size() <= TID_MAX_COLS, TID_E_SCHEMA, "join: too many output columns");
+// Count the matches of L[lc] = R[rc] on the device (no synchronisation).
+std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
+                                        const tid_table *R, uint64_t nr, int rc, int algo,
+                                        const JoinPlan &jp) {
+    auto pj = std::make_unique<PendingJoin>();
+    pj->L = L;
+    pj->R = R;
+    pj->lc = lc;
+    pj->rc = rc;
+    pj->jp = jp;
+    for (int c : jp.lkeep) pj->vars.push_back(L->vars[c]);
+    for (int c : jp.rkeep) pj->vars.push_back(R->vars[c]);
+    TID_REQUIRE(pj->vars.size() <= TID_MAX_COLS, TID_E_SCHEMA, "join: too many output columns");
     if (nl == 0 || nr == 0) {
-        auto out = make_table(ctx, (int)vars.size(), vars.data(), 0);
-        set_count(ctx, out.get(), 0);
-        return out;
+        pj->total = 0;
+        pj->total_known = true;
+        return pj;
     }
     TID_REQUIRE(nl < (1ull << 32) && nr < (1ull << 32), TID_E_UNSUPPORTED,
                 "join: inputs of 2^32 rows or more");
     if (algo == 0) algo = 1;
-
-    ExpandArgs ea{};
-    DevBuf start, count, off, qk, qv, bk, bv, qk2, qv2, bk2, bv2;
-    DevBuf slots, slot_of, slot_count, slot_start, cursor, rows;
-    uint64_t nq;
     if (algo == 2) {
         // sort both sides on the key, then find each left key's run on the right
-        const std::vector<uint32_t> ml = column_maxima(ctx, L, nl);
-        const std::vector<uint32_t> mr = column_maxima(ctx, R, nr);
-        const int bits = bitw(std::max(ml[lc], mr[rc]));
-        auto sort_side = [&](const tid_table *T, uint64_t n, int col, DevBuf &k, DevBuf &v,
-                             DevBuf &k2, DevBuf &v2) -> std::pair<uint64_t *, uint32_t *> {
+        uint32_t ml, mr;
+        if (L->maxv_known && R->maxv_known) {
+            ml = L->maxv[lc];
+            mr = R->maxv[rc];
+        } else {
+            ml = column_maxima(ctx, L, nl)[lc];
+            mr = column_maxima(ctx, R, nr)[rc];
+        }
+        const int bits = bitw(std::max(ml, mr));
+        auto sort_side = [&](const tid_table *T, uint64_t n, int col,
+                             int slot) -> std::pair<uint64_t *, uint32_t *> {
+            DevBuf &k = pj->keys[slot], &k2 = pj->keys[slot + 1];
+            DevBuf &v = pj->vals[slot], &v2 = pj->vals[slot + 1];
             k = DevBuf(ctx, n * 8);
             v = DevBuf(ctx, n * 4);
             k2 = DevBuf(ctx, n * 8);
             v2 = DevBuf(ctx, n * 4);
-            // key = column value widened to 64 bits
-            widen_u32(ctx, T->col[col], n, k.get<uint64_t>());
+            widen_u32(ctx, T->col[col], n, k.get<uint64_t>());  // key = value, 64 bits wide
             iota(ctx, v.get<uint32_t>(), n);
             const bool moved = radix_sort_pairs(ctx, k.get<uint64_t>(), v.get<uint32_t>(),
                                                 k2.get<uint64_t>(), v2.get<uint32_t>(), n, bits);
             return moved ? std::make_pair(k2.get<uint64_t>(), v2.get<uint32_t>())
                          : std::make_pair(k.get<uint64_t>(), v.get<uint32_t>());
         };
-        auto [lk, lv] = sort_side(L, nl, lc, qk, qv, qk2, qv2);
-        auto [rk, rv] = sort_side(R, nr, rc, bk, bv, bk2, bv2);
-        nq = nl;
-        start = DevBuf(ctx, nq * 4);
-        count = DevBuf(ctx, nq * 4);
-        hipLaunchKernelGGL(merge_counts, dim3(grid_of(nq)), dim3(256), 0, ctx->stream, lk, nq, rk,
-                           nr, start.get<uint32_t>(), count.get<uint32_t>());
+        auto [lk, lv] = sort_side(L, nl, lc, 0);
+        auto [rk, rv] = sort_side(R, nr, rc, 2);
+        pj->nq = nl;
+        pj->start = DevBuf(ctx, nl * 4);
+        pj->count = DevBuf(ctx, nl * 4);
+        hipLaunchKernelGGL(merge_counts, dim3(grid_of(nl)), dim3(256), 0, ctx->stream, lk, nl, rk,
+                           nr, pj->start.get<uint32_t>(), pj->count.get<uint32_t>());
         TID_HIP(hipGetLastError());
-        ea.qrow = lv;
-        ea.brow = rv;
-        ea.probe_is_left = 1;
+        pj->qrow = lv;
+        pj->brow = rv;
+        pj->probe_is_left = 1;
     } else {
         // build on the smaller side
         const bool build_right = nr <= nl;
         const tid_table *B = build_right ? R : L;
         const tid_table *Q = build_right ? L : R;
         const uint64_t nb = build_right ? nr : nl;
-        nq = build_right ? nl : nr;
+        const uint64_t nq = build_right ? nl : nr;
         const uint32_t *bkey = B->col[build_right ? rc : lc];
         const uint32_t *qkey = Q->col[build_right ? lc : rc];
         uint64_t cap = 1024;
         while (cap < 2 * nb) cap <<= 1;
         TID_REQUIRE(cap <= (1ull << 31), TID_E_UNSUPPORTED, "join: hash table too large");
         const uint32_t mask = (uint32_t)(cap - 1);
-        slots = DevBuf(ctx, cap * 8);
-        slot_count = DevBuf(ctx, cap * 4);
-        cursor = DevBuf(ctx, cap * 4);
-        slot_of = DevBuf(ctx, nb * 4);
-        slot_start = DevBuf(ctx, (cap + 1) * 8);
-        rows = DevBuf(ctx, nb * 4);
-        TID_HIP(hipMemsetAsync(slots.get(), 0, cap * 8, ctx->stream));
-        TID_HIP(hipMemsetAsync(slot_count.get(), 0, cap * 4, ctx->stream));
-        TID_HIP(hipMemsetAsync(cursor.get(), 0, cap * 4, ctx->stream));
+        pj->slots = DevBuf(ctx, cap * 8);
+        pj->slot_count = DevBuf(ctx, cap * 4);
+        pj->cursor = DevBuf(ctx, cap * 4);
+        pj->slot_of = DevBuf(ctx, nb * 4);
+        pj->slot_start = DevBuf(ctx, (cap + 1) * 8);
+        pj->rows = DevBuf(ctx, nb * 4);
+        TID_HIP(hipMemsetAsync(pj->slots.get(), 0, cap * 8, ctx->stream));
+        TID_HIP(hipMemsetAsync(pj->slot_count.get(), 0, cap * 4, ctx->stream));
+        TID_HIP(hipMemsetAsync(pj->cursor.get(), 0, cap * 4, ctx->stream));
         hipLaunchKernelGGL(hash_insert, dim3(grid_of(nb)), dim3(256), 0, ctx->stream, bkey, nb,
-                           slots.get<unsigned long long>(), mask, slot_of.get<uint32_t>(),
-                           slot_count.get<uint32_t>());
+                           pj->slots.get<unsigned long long>(), mask, pj->slot_of.get<uint32_t>(),
+                           pj->slot_count.get<uint32_t>());
         TID_HIP(hipGetLastError());
-        exclusive_scan_u64(ctx, slot_count.get<const uint32_t>(), cap, slot_start.get<uint64_t>());
+        exclusive_scan_async(ctx, pj->slot_count.get<const uint32_t>(), cap,
+                             pj->slot_start.get<uint64_t>());
         hipLaunchKernelGGL(hash_fill, dim3(grid_of(nb)), dim3(256), 0, ctx->stream,
-                           slot_of.get<const uint32_t>(), nb, slot_start.get<const uint64_t>(),
-                           cursor.get<uint32_t>(), rows.get<uint32_t>());
+                           pj->slot_of.get<const uint32_t>(), nb,
+                           pj->slot_start.get<const uint64_t>(), pj->cursor.get<uint32_t>(),
+                           pj->rows.get<uint32_t>());
         TID_HIP(hipGetLastError());
-        start = DevBuf(ctx, nq * 4);
-        count = DevBuf(ctx, nq * 4);
+        pj->nq = nq;
+        pj->start = DevBuf(ctx, nq * 4);
+        pj->count = DevBuf(ctx, nq * 4);
         hipLaunchKernelGGL(hash_probe, dim3(grid_of(nq)), dim3(256), 0, ctx->stream, qkey, nq,
-                           slots.get<const unsigned long long>(), mask,
-                           slot_count.get<const uint32_t>(), slot_start.get<const uint64_t>(),
-                           start.get<uint32_t>(), count.get<uint32_t>());
+                           pj->slots.get<const unsigned long long>(), mask,
+                           pj->slot_count.get<const uint32_t>(),
+                           pj->slot_start.get<const uint64_t>(), pj->start.get<uint32_t>(),
+                           pj->count.get<uint32_t>());
         TID_HIP(hipGetLastError());
-        ea.qrow = nullptr;
-        ea.brow = rows.get<uint32_t>();
-        ea.probe_is_left = build_right ? 1 : 0;
+        pj->qrow = nullptr;
+        pj->brow = pj->rows.get<uint32_t>();
+        pj->probe_is_left = build_right ? 1 : 0;
     }
-    off = DevBuf(ctx, (nq + 1) * 8);
-    const uint64_t total = exclusive_scan_u64(ctx, count.get<const uint32_t>(), nq, off.get<uint64_t>());
-    auto out = make_table(ctx, (int)vars.size(), vars.data(), total);
+    pj->off = DevBuf(ctx, (pj->nq + 1) * 8);
+    exclusive_scan_async(ctx, pj->count.get<const uint32_t>(), pj->nq, pj->off.get<uint64_t>());
+    return pj;
+}
+
+// Materialise a counted join once its output size is on the host.
+std::unique_ptr<tid_table> join_finish(tid_ctx *ctx, PendingJoin &pj) {
+    TID_REQUIRE(pj.total_known, TID_E_INTERNAL, "join: output size not read yet");
+    const tid_table *L = pj.L, *R = pj.R;
+    const uint64_t total = pj.total;
+    auto out = make_table(ctx, (int)pj.vars.size(), pj.vars.data(), total);
+    out->maxv_known = L->maxv_known && R->maxv_known;
+    if (out->maxv_known) {
+        copy_bounds(out.get(), L, pj.jp.lkeep.data(), (int)pj.jp.lkeep.size(), 0);
+        copy_bounds(out.get(), R, pj.jp.rkeep.data(), (int)pj.jp.rkeep.size(),
+                    (int)pj.jp.lkeep.size());
+    }
     if (total) {
         TID_REQUIRE(total < (1ull << 40), TID_E_UNSUPPORTED, "join: output too large");
-        ea.off = off.get<const uint64_t>();
-        ea.start = start.get<const uint32_t>();
-        ea.nq = nq;
+        ExpandArgs ea{};
+        ea.off = pj.off.get<const uint64_t>();
+        ea.start = pj.start.get<const uint32_t>();
+        ea.qrow = pj.qrow;
+        ea.brow = pj.brow;
+        ea.probe_is_left = pj.probe_is_left;
+        ea.nq = pj.nq;
         ea.total = total;
-        ea.nl = (int)jp.lkeep.size();
-        ea.nr = (int)jp.rkeep.size();
-        for (int c = 0; c < ea.nl; ++c) ea.lcol[c] = L->col[jp.lkeep[c]];
-        for (int c = 0; c < ea.nr; ++c) ea.rcol[c] = R->col[jp.rkeep[c]];
-        for (int c = 0; c < (int)vars.size(); ++c) ea.out[c] = out->col[c];
+        ea.nl = (int)pj.jp.lkeep.size();
+        ea.nr = (int)pj.jp.rkeep.size();
+        for (int c = 0; c < ea.nl; ++c) ea.lcol[c] = L->col[pj.jp.lkeep[c]];
+        for (int c = 0; c < ea.nr; ++c) ea.rcol[c] = R->col[pj.jp.rkeep[c]];
+        for (int c = 0; c < (int)pj.vars.size(); ++c) ea.out[c] = out->col[c];
         hipLaunchKernelGGL(join_expand, dim3(grid_of(total, 256, 16384)), dim3(256), 0,
                            ctx->stream, ea);
         TID_HIP(hipGetLastError());
     }
     set_count(ctx, out.get(), total);
     return out;
+}
+
+// Matches of L[lc] = R[rc] as an unsorted table of the columns lkeep of L
+// followed by the columns rkeep of R.
+std::unique_ptr<tid_table> join_unsorted(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
+                                         const tid_table *R, uint64_t nr, int rc, int algo,
+                                         const JoinPlan &jp) {
+    auto pj = join_begin(ctx, L, nl, lc, R, nr, rc, algo, jp);
+    if (!pj->total_known) {
+        read_words(ctx, {pj->d_total()}, &pj->total);
+        pj->total_known = true;
+    }
+    return join_finish(ctx, *pj);
 }
 
 std::unique_ptr<tid_table> join_tables(tid_ctx *ctx, const tid_table *l, int lcol,

@@ -1,9 +1,10 @@
 // query.hip -- evaluation of postfix query plans (Sec. 4.3, Fig. 6): the
-// plan's subqueries are searched together in one pass over the graph (the
-// multi-key search of Sec. 4.1), filters on a scanned variable are applied
-// during that search, then joins go left to right over the subquery results,
-// followed by unions, projections and DISTINCT; the result is returned in
-// lexicographic row order.
+// plans' subqueries are searched together in multi-pattern passes over the
+// graph (the multi-key search of Sec. 4.1), filters on a scanned variable are
+// applied during that search, then joins go left to right over the subquery
+// results, followed by unions, projections and DISTINCT; every result is
+// returned in lexicographic row order.  A batch of plans advances in
+// lockstep, so the host waits for the device once per round for all plans.
 #include "compact.hpp"
 
 #include <algorithm>
@@ -12,9 +13,6 @@ namespace tid {
 
 std::unique_ptr<tid_table> union_tables(tid_ctx *, const tid_table *const *, int, int);
 std::unique_ptr<tid_table> sort_rows(tid_ctx *ctx, const tid_table *t, uint64_t n, int distinct);
-std::unique_ptr<tid_table> join_unsorted(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
-                                         const tid_table *R, uint64_t nr, int rc, int algo,
-                                         const JoinPlan &jp);
 
 // Rows whose column pairs (a[p], b[p]) are all equal, keeping the listed columns.
 struct EqSrc {
@@ -42,6 +40,8 @@ static std::unique_ptr<tid_table> select_equal(tid_ctx *ctx, const tid_table *t,
     std::vector<int32_t> vars;
     for (int c : keep) vars.push_back(t->vars[c]);
     auto out = make_table(ctx, (int)keep.size(), vars.data(), n);
+    out->maxv_known = t->maxv_known;
+    copy_bounds(out.get(), t, keep.data(), (int)keep.size());
     if (n == 0) {
         set_count(ctx, out.get(), 0);
         return out;
@@ -70,34 +70,6 @@ static int col_of(const tid_table *t, int32_t var) {
     return -1;
 }
 
-// Join on variable v; every other variable both sides hold must agree and is
-// kept once (the left copy).
-static std::unique_ptr<tid_table> natural_join(tid_ctx *ctx, tid_table *L, tid_table *R,
-                                               int32_t v) {
-    const int lc = col_of(L, v), rc = col_of(R, v);
-    TID_REQUIRE(lc >= 0 && rc >= 0, TID_E_SCHEMA, "join: variable not bound on both sides");
-    tid_table *both[2] = {L, R};
-    resolve_counts(ctx, both, 2);
-    JoinPlan jp;
-    for (int c = 0; c < L->ncols; ++c) jp.lkeep.push_back(c);
-    std::vector<std::pair<int, int>> eq;  // (left output column, right output column)
-    std::vector<int> keep;
-    for (int c = 0; c < L->ncols; ++c) keep.push_back(c);
-    for (int c = 0; c < R->ncols; ++c) {
-        if (c == rc) continue;
-        const int out_col = L->ncols + (int)jp.rkeep.size();
-        jp.rkeep.push_back(c);
-        const int lmatch = col_of(L, R->vars[c]);
-        if (lmatch >= 0)
-            eq.emplace_back(lmatch, out_col);
-        else
-            keep.push_back(out_col);
-    }
-    auto raw = join_unsorted(ctx, L, L->nrows, lc, R, R->nrows, rc, 0, jp);
-    if (eq.empty()) return raw;
-    return select_equal(ctx, raw.get(), eq, keep);
-}
-
 // Keep the listed variables, in that order, without copying: the columns of
 // the consumed table are re-pointed.
 static std::unique_ptr<tid_table> project(std::unique_ptr<tid_table> t,
@@ -112,7 +84,9 @@ static std::unique_ptr<tid_table> project(std::unique_ptr<tid_table> t,
             TID_REQUIRE(vars[i] != vars[j], TID_E_SCHEMA, "project: variable listed twice");
         out->vars[j] = vars[j];
         out->col[j] = t->col[c];
+        out->maxv[j] = t->maxv[c];
     }
+    out->maxv_known = t->maxv_known;
     out->cap = t->cap;
     out->nrows = t->nrows;
     out->count_known = t->count_known;
@@ -126,25 +100,46 @@ struct Entry {
     bool sorted = false;
 };
 
-std::unique_ptr<tid_table> run_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan) {
+// One plan in flight: its compiled scans, its stack, and the join (if any)
+// waiting for its output size.
+struct PlanRun {
+    const tid_plan *plan = nullptr;
+    std::vector<tid_pattern> scans;
+    std::vector<int> scan_at_op;
+    std::vector<char> fused;
+    std::vector<std::unique_ptr<tid_table>> scanned;
+    int pc = 0;
+    std::vector<Entry> st;
+    std::unique_ptr<PendingJoin> pj;
+    std::vector<std::pair<int, int>> pj_eq;
+    std::vector<int> pj_keep;
+    std::unique_ptr<tid_table> result;
+    bool done = false;
+};
+
+struct Needs {
+    std::vector<tid_table *> tables;
+    std::vector<PendingJoin *> joins;
+};
+
+// Check the op stream and list one scan per SCAN op.  A FILTER right after a
+// SCAN on a variable that the pattern binds (and with no range yet) becomes
+// the pattern's range: the filter runs inside the search (Fig. 6).
+static void compile_plan(const tid_plan *plan, PlanRun &r) {
+    TID_REQUIRE(plan, TID_E_INVALID_ARG, "plan: null");
     TID_REQUIRE(plan->n_patterns >= 0 && plan->n_ops >= 0, TID_E_INVALID_ARG, "plan: bad sizes");
     TID_REQUIRE(plan->n_patterns == 0 || plan->patterns, TID_E_INVALID_ARG, "plan: no patterns");
     TID_REQUIRE(plan->n_ops > 0 && plan->ops, TID_E_INVALID_ARG, "plan: no ops");
+    r.plan = plan;
     const uint32_t *ops = plan->ops;
     const int nops = plan->n_ops;
-
-    // Pass 1: check the op stream, and list one scan per SCAN op.  A FILTER
-    // right after a SCAN on a variable that the pattern binds at one position
-    // (and with no range yet) becomes the pattern's range: the filter runs
-    // inside the search (Fig. 6).
-    std::vector<tid_pattern> scans;
-    std::vector<int> scan_at_op(nops, -1);  // op index -> scan slot
-    std::vector<char> fused(nops, 0);       // FILTER ops folded into their scan
+    r.scan_at_op.assign(nops, -1);
+    r.fused.assign(nops, 0);
     int depth = 0;
     for (int pc = 0; pc < nops;) {
         const uint32_t op = ops[pc];
         auto need = [&](int words) {
-            TID_REQUIRE(pc + words < nops + 1, TID_E_INVALID_ARG, "plan: truncated op");
+            TID_REQUIRE(pc + words <= nops, TID_E_INVALID_ARG, "plan: truncated op");
         };
         if (op == TID_OP_SCAN) {
             need(2);
@@ -154,25 +149,21 @@ std::unique_ptr<tid_table> run_query(tid_ctx *ctx, const tid_graph *g, const tid
             int32_t vars[3], src[3];
             pattern_schema(plan->patterns[i], vars, src);
             tid_pattern p = plan->patterns[i];
-            // peephole: SCAN i; FILTER v lo hi
             if (pc + 6 <= nops && ops[pc + 2] == TID_OP_FILTER && p.range_pos < 0) {
                 const int32_t v = (int32_t)ops[pc + 3];
                 const int32_t pv[3] = {p.vs, p.vp, p.vo};
-                int pos = -1, hits = 0;
+                int pos = -1;
                 for (int x = 0; x < 3; ++x)
-                    if (pv[x] >= 0 && pv[x] == v) {
-                        pos = x;
-                        ++hits;
-                    }
-                if (hits >= 1) {
+                    if (pv[x] >= 0 && pv[x] == v) pos = x;
+                if (pos >= 0) {
                     p.range_pos = pos;
                     p.lo = ops[pc + 4];
                     p.hi = ops[pc + 5];
-                    fused[pc + 2] = 1;
+                    r.fused[pc + 2] = 1;
                 }
             }
-            scan_at_op[pc] = (int)scans.size();
-            scans.push_back(p);
+            r.scan_at_op[pc] = (int)r.scans.size();
+            r.scans.push_back(p);
             ++depth;
             pc += 2;
         } else if (op == TID_OP_JOIN) {
@@ -205,64 +196,173 @@ std::unique_ptr<tid_table> run_query(tid_ctx *ctx, const tid_graph *g, const tid
         }
     }
     TID_REQUIRE(depth == 1, TID_E_INVALID_ARG, "plan: must leave exactly one table");
+    r.scanned.resize(r.scans.size());
+}
 
-    // All subqueries searched together, up to 16 per pass over the graph.
-    std::vector<std::unique_ptr<tid_table>> scanned(scans.size());
-    for (size_t s0 = 0; s0 < scans.size(); s0 += TID_MAX_MULTI) {
-        const int k = (int)std::min<size_t>(TID_MAX_MULTI, scans.size() - s0);
-        scan_multi(ctx, g, scans.data() + s0, k, scanned.data() + s0);
-    }
+static bool need_count(tid_table *t, Needs &needs) {
+    if (t->count_known) return false;
+    needs.tables.push_back(t);
+    return true;
+}
 
-    // Pass 2: evaluate.
-    std::vector<Entry> st;
-    for (int pc = 0; pc < nops;) {
+// Run the plan's ops until one needs a value that is still on the device.
+static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
+    const uint32_t *ops = r.plan->ops;
+    const int nops = r.plan->n_ops;
+    while (!r.done) {
+        if (r.pj) {
+            if (!r.pj->total_known) {
+                needs.joins.push_back(r.pj.get());
+                return;
+            }
+            auto raw = join_finish(ctx, *r.pj);
+            r.pj.reset();  // inputs go back to the allocator in stream order
+            if (r.pj_eq.empty())
+                r.st.push_back({std::move(raw), false});
+            else
+                r.st.push_back({select_equal(ctx, raw.get(), r.pj_eq, r.pj_keep), false});
+            continue;
+        }
+        if (r.pc >= nops) {
+            Entry &top = r.st.back();
+            if (top.sorted) {
+                r.result = std::move(top.t);
+                r.done = true;
+                return;
+            }
+            if (need_count(top.t.get(), needs)) return;
+            r.result = sort_rows(ctx, top.t.get(), top.t->nrows, 0);
+            r.done = true;
+            return;
+        }
+        const int pc = r.pc;
         const uint32_t op = ops[pc];
         if (op == TID_OP_SCAN) {
-            st.push_back({std::move(scanned[scan_at_op[pc]]), false});
-            pc += 2;
+            r.st.push_back({std::move(r.scanned[r.scan_at_op[pc]]), false});
+            r.pc += 2;
         } else if (op == TID_OP_JOIN) {
+            tid_table *L = r.st[r.st.size() - 2].t.get();
+            tid_table *R = r.st.back().t.get();
+            const bool wl = need_count(L, needs), wr = need_count(R, needs);
+            if (wl || wr) return;
             const int32_t v = (int32_t)ops[pc + 1];
-            Entry r = std::move(st.back());
-            st.pop_back();
-            Entry l = std::move(st.back());
-            st.pop_back();
-            st.push_back({natural_join(ctx, l.t.get(), r.t.get(), v), false});
-            pc += 2;
+            const int lc = col_of(L, v), rc = col_of(R, v);
+            TID_REQUIRE(lc >= 0 && rc >= 0, TID_E_SCHEMA, "join: variable not bound on both sides");
+            // every other variable both sides hold must agree; it is kept once
+            JoinPlan jp;
+            for (int c = 0; c < L->ncols; ++c) jp.lkeep.push_back(c);
+            r.pj_eq.clear();
+            r.pj_keep.clear();
+            for (int c = 0; c < L->ncols; ++c) r.pj_keep.push_back(c);
+            for (int c = 0; c < R->ncols; ++c) {
+                if (c == rc) continue;
+                const int out_col = L->ncols + (int)jp.rkeep.size();
+                jp.rkeep.push_back(c);
+                const int lmatch = col_of(L, R->vars[c]);
+                if (lmatch >= 0)
+                    r.pj_eq.emplace_back(lmatch, out_col);
+                else
+                    r.pj_keep.push_back(out_col);
+            }
+            r.pj = join_begin(ctx, L, L->nrows, lc, R, R->nrows, rc, 0, jp);
+            r.pj->own_r = std::move(r.st.back().t);
+            r.st.pop_back();
+            r.pj->own_l = std::move(r.st.back().t);
+            r.st.pop_back();
+            r.pc += 2;
         } else if (op == TID_OP_UNION) {
             const int k = (int)ops[pc + 1];
             const int d = ops[pc + 2] ? 1 : 0;
+            bool wait = false;
             std::vector<const tid_table *> ins;
-            for (int j = 0; j < k; ++j) ins.push_back(st[st.size() - k + j].t.get());
-            auto u = union_tables(ctx, ins.data(), k, d);
-            st.resize(st.size() - k);
-            st.push_back({std::move(u), d == 1});
-            pc += 3;
-        } else if (op == TID_OP_FILTER) {
-            if (!fused[pc]) {
-                const int32_t v = (int32_t)ops[pc + 1];
-                const int c = col_of(st.back().t.get(), v);
-                TID_REQUIRE(c >= 0, TID_E_SCHEMA, "filter: variable not in the table");
-                auto f = filter_range(ctx, st.back().t.get(), c, ops[pc + 2], ops[pc + 3]);
-                st.back().t = std::move(f);  // filtering keeps row order
+            for (int j = 0; j < k; ++j) {
+                tid_table *t = r.st[r.st.size() - k + j].t.get();
+                wait |= need_count(t, needs);
+                ins.push_back(t);
             }
-            pc += 4;
+            if (wait) return;
+            auto u = union_tables(ctx, ins.data(), k, d);
+            r.st.resize(r.st.size() - k);
+            r.st.push_back({std::move(u), d == 1});
+            r.pc += 3;
+        } else if (op == TID_OP_FILTER) {
+            if (!r.fused[pc]) {
+                tid_table *t = r.st.back().t.get();
+                if (need_count(t, needs)) return;
+                const int c = col_of(t, (int32_t)ops[pc + 1]);
+                TID_REQUIRE(c >= 0, TID_E_SCHEMA, "filter: variable not in the table");
+                r.st.back().t = filter_range(ctx, t, c, ops[pc + 2], ops[pc + 3]);
+            }
+            r.pc += 4;  // filtering keeps row order
         } else if (op == TID_OP_PROJECT) {
             const int n = (int)ops[pc + 1];
             std::vector<int32_t> vars(ops + pc + 2, ops + pc + 2 + n);
-            st.back().t = project(std::move(st.back().t), vars);
-            st.back().sorted = false;
-            pc += 2 + n;
+            r.st.back().t = project(std::move(r.st.back().t), vars);
+            r.st.back().sorted = false;
+            r.pc += 2 + n;
         } else {  // DISTINCT
-            tid_table *t = st.back().t.get();
-            st.back().t = sort_rows(ctx, t, t->rows(), 1);
-            st.back().sorted = true;
-            pc += 1;
+            tid_table *t = r.st.back().t.get();
+            if (need_count(t, needs)) return;
+            r.st.back().t = sort_rows(ctx, t, t->nrows, 1);
+            r.st.back().sorted = true;
+            r.pc += 1;
         }
     }
-    Entry &res = st.back();
-    if (res.sorted) return std::move(res.t);
-    tid_table *t = res.t.get();
-    return sort_rows(ctx, t, t->rows(), 0);
+}
+
+// Evaluate nq plans together: all their patterns in shared multi-pattern
+// passes over the graph, then their remaining ops in lockstep, every round
+// of device reads shared by all plans.
+std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph *g,
+                                                  const tid_plan *const *plans, int nq) {
+    std::vector<PlanRun> runs(nq);
+    for (int i = 0; i < nq; ++i) compile_plan(plans[i], runs[i]);
+    std::vector<tid_pattern> all;
+    std::vector<std::pair<int, int>> where;
+    for (int i = 0; i < nq; ++i)
+        for (size_t s = 0; s < runs[i].scans.size(); ++s) {
+            all.push_back(runs[i].scans[s]);
+            where.emplace_back(i, (int)s);
+        }
+    for (size_t s0 = 0; s0 < all.size(); s0 += TID_MAX_MULTI) {
+        const int k = (int)std::min<size_t>(TID_MAX_MULTI, all.size() - s0);
+        std::unique_ptr<tid_table> outs[TID_MAX_MULTI];
+        scan_multi(ctx, g, all.data() + s0, k, outs);
+        for (int j = 0; j < k; ++j)
+            runs[where[s0 + j].first].scanned[where[s0 + j].second] = std::move(outs[j]);
+    }
+    for (;;) {
+        Needs needs;
+        bool all_done = true;
+        for (auto &r : runs) {
+            if (!r.done) advance(ctx, r, needs);
+            all_done &= r.done;
+        }
+        if (all_done) break;
+        std::vector<const uint64_t *> src;
+        for (tid_table *t : needs.tables) src.push_back(t->d_count);
+        for (PendingJoin *j : needs.joins) src.push_back(j->d_total());
+        TID_REQUIRE(!src.empty(), TID_E_INTERNAL, "query: no progress");
+        std::vector<uint64_t> v(src.size());
+        read_words(ctx, src, v.data());
+        size_t at = 0;
+        for (tid_table *t : needs.tables) {
+            t->nrows = v[at++];
+            t->count_known = true;
+        }
+        for (PendingJoin *j : needs.joins) {
+            j->total = v[at++];
+            j->total_known = true;
+        }
+    }
+    std::vector<std::unique_ptr<tid_table>> out(nq);
+    for (int i = 0; i < nq; ++i) out[i] = std::move(runs[i].result);
+    return out;
+}
+
+std::unique_ptr<tid_table> run_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan) {
+    auto v = run_plans(ctx, g, &plan, 1);
+    return std::move(v[0]);
 }
 
 }  // namespace tid

@@ -84,6 +84,14 @@ std::unique_ptr<tid_table> make_table(tid_ctx *ctx, int32_t ncols, const int32_t
     return t;
 }
 
+void copy_bounds(tid_table *dst, const tid_table *src, const int *map, int n, int dst_off) {
+    if (!src->maxv_known) {
+        dst->maxv_known = false;
+        return;
+    }
+    for (int c = 0; c < n; ++c) dst->maxv[dst_off + c] = src->maxv[map ? map[c] : c];
+}
+
 void set_count(tid_ctx *ctx, tid_table *t, uint64_t n) {
     hipLaunchKernelGGL(set_u64, dim3(1), dim3(1), 0, ctx->stream, t->d_count, n);
     TID_HIP(hipGetLastError());
@@ -91,31 +99,57 @@ void set_count(tid_ctx *ctx, tid_table *t, uint64_t n) {
     t->count_known = true;
 }
 
+__global__ void gather_words(const uint64_t *const *src, uint64_t *dst, int n,
+                             const uint32_t *flags) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x)
+        dst[i] = i < n ? *src[i] : (uint64_t)flags[0];
+}
+
+void read_words(tid_ctx *ctx, const std::vector<const uint64_t *> &src, uint64_t *dst) {
+    const size_t n = src.size();
+    if (n == 0) return;
+    if (ctx->rw_cap < n + 1) {
+        if (ctx->rw_host_ptrs) (void)hipHostFree(ctx->rw_host_ptrs);
+        if (ctx->rw_host_vals) (void)hipHostFree(ctx->rw_host_vals);
+        if (ctx->rw_dev) ctx->free(ctx->rw_dev, ctx->rw_cap * 16);
+        ctx->rw_host_ptrs = nullptr;
+        ctx->rw_host_vals = nullptr;
+        ctx->rw_dev = nullptr;
+        const size_t cap = std::max<size_t>(n + 1, 2 * ctx->rw_cap);
+        TID_HIP(hipHostMalloc((void **)&ctx->rw_host_ptrs, cap * 8, hipHostMallocDefault));
+        TID_HIP(hipHostMalloc((void **)&ctx->rw_host_vals, cap * 8, hipHostMallocDefault));
+        ctx->rw_dev = ctx->alloc(cap * 16);
+        ctx->rw_cap = cap;
+    }
+    for (size_t i = 0; i < n; ++i) ctx->rw_host_ptrs[i] = src[i];
+    const uint64_t **dptrs = static_cast<const uint64_t **>(ctx->rw_dev);
+    uint64_t *dvals = reinterpret_cast<uint64_t *>(static_cast<char *>(ctx->rw_dev) + ctx->rw_cap * 8);
+    TID_HIP(hipMemcpyAsync(dptrs, ctx->rw_host_ptrs, n * 8, hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(gather_words, dim3((unsigned)std::min<size_t>((n + 256) / 256, 1024)),
+                       dim3(256), 0, ctx->stream, dptrs, dvals, (int)n, ctx->d_flags);
+    TID_HIP(hipGetLastError());
+    TID_HIP(hipMemcpyAsync(ctx->rw_host_vals, dvals, (n + 1) * 8, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    TID_HIP(hipStreamSynchronize(ctx->stream));
+    TID_REQUIRE(ctx->rw_host_vals[n] == 0, TID_E_INTERNAL,
+                "a cross-workgroup wait exceeded its spin bound (device state inconsistent)");
+    for (size_t i = 0; i < n; ++i) dst[i] = ctx->rw_host_vals[i];
+}
+
 void resolve_counts(tid_ctx *ctx, tid_table *const *ts, int k) {
-    constexpr int kSlots = 255;  // host_counts holds kSlots counts + the flags word
-    for (int start = 0; start < k; start += kSlots) {
-        const int m = std::min(kSlots, k - start);
-        int pending = 0;
-        for (int j = 0; j < m; ++j) {
-            tid_table *t = ts[start + j];
-            if (t->count_known) continue;
-            TID_HIP(hipMemcpyAsync(&ctx->host_counts[j], t->d_count, sizeof(uint64_t),
-                                   hipMemcpyDeviceToHost, ctx->stream));
-            ++pending;
+    std::vector<const uint64_t *> src;
+    std::vector<tid_table *> who;
+    for (int j = 0; j < k; ++j)
+        if (!ts[j]->count_known) {
+            src.push_back(ts[j]->d_count);
+            who.push_back(ts[j]);
         }
-        if (!pending) continue;
-        TID_HIP(hipMemcpyAsync(&ctx->host_counts[kSlots], ctx->d_flags, sizeof(uint64_t),
-                               hipMemcpyDeviceToHost, ctx->stream));
-        TID_HIP(hipStreamSynchronize(ctx->stream));
-        const uint32_t err = (uint32_t)(ctx->host_counts[kSlots] & 0xFFFFFFFFu);
-        TID_REQUIRE(err == 0, TID_E_INTERNAL,
-                    "a look-back wait exceeded its spin bound (device state inconsistent)");
-        for (int j = 0; j < m; ++j) {
-            tid_table *t = ts[start + j];
-            if (t->count_known) continue;
-            t->nrows = ctx->host_counts[j];
-            t->count_known = true;
-        }
+    if (src.empty()) return;
+    std::vector<uint64_t> v(src.size());
+    read_words(ctx, src, v.data());
+    for (size_t i = 0; i < who.size(); ++i) {
+        who[i]->nrows = v[i];
+        who[i]->count_known = true;
     }
 }
 
@@ -207,12 +241,13 @@ void build_stats(tid_ctx *ctx, tid_graph *g) {
     uint32_t h[6];
     TID_HIP(hipMemcpyAsync(h, mm.get(), sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
     TID_HIP(hipStreamSynchronize(ctx->stream));
-    for (int x = 0; x < 3; ++x)
+    for (int x = 0; x < 3; ++x) {
         TID_REQUIRE(h[x] != 0, TID_E_INVALID_ARG,
                     "load: ID 0 is reserved for the free variable and may not appear in a triple");
+        g->max_id[x] = h[3 + x];
+    }
     if (g->n >= (1ull << 32)) return;  // counts would not fit the uint32 bins
     for (int x = 0; x < 3; ++x) {
-        g->max_id[x] = h[3 + x];
         if (h[3 + x] >= kMaxHistIds) continue;
         const uint32_t nbins = h[3 + x] + 1;
         DevBuf hist(ctx, (size_t)nbins * sizeof(uint32_t));

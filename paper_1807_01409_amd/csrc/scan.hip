@@ -481,6 +481,8 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
         uint64_t cap = ctx->opt.capacity_override > 0 ? (uint64_t)ctx->opt.capacity_override
                                                       : bound[j];
         outs[j] = make_table(ctx, nc, vars, cap);
+        for (int c = 0; c < nc; ++c) outs[j]->maxv[c] = g->max_id[src[c]];
+        outs[j]->maxv_known = true;
     }
     if (g->n == 0) {
         for (int j = 0; j < k; ++j) set_count(ctx, outs[j].get(), 0);
@@ -506,7 +508,10 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
     std::vector<tid_table *> rt;
     for (int j : redo) {
         const uint64_t need = outs[j]->nrows;
-        outs[j] = make_table(ctx, outs[j]->ncols, outs[j]->vars, need);
+        auto bigger = make_table(ctx, outs[j]->ncols, outs[j]->vars, need);
+        copy_bounds(bigger.get(), outs[j].get(), nullptr, outs[j]->ncols);
+        bigger->maxv_known = outs[j]->maxv_known;
+        outs[j] = std::move(bigger);
         rp.push_back(pats[j]);
         rt.push_back(outs[j].get());
     }
@@ -541,6 +546,8 @@ std::unique_ptr<tid_table> filter_range(tid_ctx *ctx, const tid_table *t, int co
     uint64_t cap = in_rows;
     if (ctx->opt.capacity_override > 0) cap = (uint64_t)ctx->opt.capacity_override;
     auto out = make_table(ctx, t->ncols, t->vars, cap);
+    out->maxv_known = t->maxv_known;
+    copy_bounds(out.get(), t, nullptr, t->ncols);
     if (in_rows == 0) {
         set_count(ctx, out.get(), 0);
         return out;
@@ -552,6 +559,8 @@ std::unique_ptr<tid_table> filter_range(tid_ctx *ctx, const tid_table *t, int co
     if (out->nrows <= out->cap) return out;
     TID_REQUIRE(ctx->opt.retry, TID_E_CAPACITY, "filter: result exceeds the output capacity");
     auto again = make_table(ctx, t->ncols, t->vars, out->nrows);
+    again->maxv_known = t->maxv_known;
+    copy_bounds(again.get(), t, nullptr, t->ncols);
     run_filter(ctx, t, in_rows, col, lo, hi, again.get());
     return again;
 }

@@ -318,7 +318,10 @@ static int bit_width(uint32_t v) { return v ? 32 - __builtin_clz(v) : 0; }
 
 // Permutation that puts the rows of t (n rows) in lexicographic order.
 DevBuf sort_permutation(tid_ctx *ctx, const tid_table *t, uint64_t n) {
-    const std::vector<uint32_t> mx = column_maxima(ctx, t, n);
+    // column bounds known on the host spare a device round trip
+    const std::vector<uint32_t> mx =
+        t->maxv_known ? std::vector<uint32_t>(t->maxv, t->maxv + t->ncols)
+                      : column_maxima(ctx, t, n);
     // columns grouped from the most significant one while their widths fit 64 bits
     std::vector<std::pair<int, int>> groups;  // [first, last) columns
     int c = 0;
@@ -376,6 +379,8 @@ void gather_table(tid_ctx *ctx, const tid_table *src, const uint32_t *perm, uint
 // drop rows equal to their predecessor in a sorted table
 std::unique_ptr<tid_table> unique_sorted(tid_ctx *ctx, const tid_table *t, uint64_t n) {
     auto out = make_table(ctx, t->ncols, t->vars, n);
+    out->maxv_known = t->maxv_known;
+    copy_bounds(out.get(), t, nullptr, t->ncols);
     if (n == 0) {
         set_count(ctx, out.get(), 0);
         return out;
@@ -401,6 +406,8 @@ std::unique_ptr<tid_table> sort_rows(tid_ctx *ctx, const tid_table *t, uint64_t 
         return out;
     }
     auto sorted = make_table(ctx, t->ncols, t->vars, n);
+    sorted->maxv_known = t->maxv_known;
+    copy_bounds(sorted.get(), t, nullptr, t->ncols);
     if (n <= 1) {
         for (int c = 0; c < t->ncols && n; ++c)
             TID_HIP(hipMemcpyAsync(sorted->col[c], t->col[c], n * 4, hipMemcpyDeviceToDevice,
@@ -435,6 +442,15 @@ std::unique_ptr<tid_table> union_tables(tid_ctx *ctx, const tid_table *const *ts
     uint64_t total = 0;
     for (int j = 0; j < k; ++j) total += ts[j]->nrows;
     auto out = make_table(ctx, (int)vars.size(), vars.data(), total);
+    out->maxv_known = true;
+    for (size_t c = 0; c < vars.size(); ++c) {
+        uint32_t m = 0;
+        for (int j = 0; j < k; ++j)
+            for (int x = 0; x < ts[j]->ncols; ++x)
+                if (ts[j]->vars[x] == vars[c]) m = std::max(m, ts[j]->maxv[x]);
+        out->maxv[c] = m;
+    }
+    for (int j = 0; j < k; ++j) out->maxv_known &= ts[j]->maxv_known;
     uint64_t at = 0;
     for (int j = 0; j < k; ++j) {
         const uint64_t n = ts[j]->nrows;

@@ -138,6 +138,9 @@ class Context:
     def query(self, g: "Graph", plan) -> "Table":
         return tid_query(self, g, plan)
 
+    def query_batch(self, g: "Graph", plans) -> List["Table"]:
+        return tid_query_batch(self, g, plans)
+
     def table(self, rows: np.ndarray, vars_: Sequence[int]) -> "Table":
         return tid_table_from_columns(self, rows, vars_)
 
@@ -290,11 +293,26 @@ def tid_sort(ctx: Context, t: Table, distinct: bool = False) -> Table:
     return Table(ctx, out)
 
 
-def tid_query(ctx: Context, g: Graph, plan) -> Table:
+def _plan(plan, keep: list) -> L.tid_plan:
     pats = (L.tid_pattern * max(1, len(plan.patterns)))(*[_pattern(p) for p in plan.patterns])
     ops = np.ascontiguousarray(np.asarray(plan.ops, dtype=np.int64).astype(np.uint32))
-    cp = L.tid_plan(len(plan.patterns), pats, len(ops),
-                    ops.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+    keep.extend([pats, ops])
+    return L.tid_plan(len(plan.patterns), pats, len(ops),
+                      ops.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
+
+
+def tid_query_batch(ctx: Context, g: Graph, plans) -> List[Table]:
+    keep: list = []
+    cps = [_plan(p, keep) for p in plans]
+    arr = (ctypes.POINTER(L.tid_plan) * max(1, len(cps)))(*[ctypes.pointer(c) for c in cps])
+    outs = (ctypes.c_void_p * max(1, len(cps)))()
+    _check(ctx.ptr, ctx._lib.tid_query_batch(ctx.ptr, g._p, arr, len(cps), outs))
+    return [Table(ctx, ctypes.c_void_p(outs[i])) for i in range(len(cps))]
+
+
+def tid_query(ctx: Context, g: Graph, plan) -> Table:
+    keep: list = []
+    cp = _plan(plan, keep)
     out = ctypes.c_void_p()
     _check(ctx.ptr, ctx._lib.tid_query(ctx.ptr, g._p, ctypes.byref(cp), ctypes.byref(out)))
     return Table(ctx, out)

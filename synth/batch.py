@@ -1,0 +1,204 @@
+"""Seeded query mixes for the batched and serving workloads.
+
+Each query has 1..6 patterns, is a star on ?s or a chain, half and half, and
+draws a target selectivity per pattern log-uniformly in [1e-6, 1e-1].  A
+target is met with a predicate whose share of the graph is closest (in log
+scale) or, below the rarest predicate's share, with a (predicate, object)
+pair of about the target count; in a chain only the last pattern may bind an
+object.  A query whose join prefix (in plan order, left to right) would
+exceed `max_rows` rows is drawn again.  Sizes are counted from a
+(predicate, subject)-ordered copy of the graph: counts only, no bindings.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+from .plan import Pattern, Plan
+
+
+class PredIndex:
+    """Triples ordered by (predicate, subject); per predicate the slice bounds."""
+
+    def __init__(self, g: np.ndarray):
+        key = (g[:, 1].astype(np.uint64) << np.uint64(32)) | g[:, 0].astype(np.uint64)
+        order = np.argsort(key, kind="stable")
+        del key
+        self.s = g[order, 0]
+        self.o = g[order, 2]
+        p = g[order, 1]
+        del order
+        self.n = g.shape[0]
+        hist = np.bincount(p)
+        self.start = np.concatenate([[0], np.cumsum(hist)]).astype(np.int64)
+        self.share = hist / self.n
+        self.preds = np.nonzero(hist)[0]
+        self._obj_counts: Dict[int, Tuple[np.ndarray, np.ndarray]] = {}
+        self._subj_counts: Dict[int, Tuple[np.ndarray, np.ndarray]] = {}
+
+    def subjects(self, p: int) -> np.ndarray:
+        return self.s[self.start[p]:self.start[p + 1]]
+
+    def objects(self, p: int) -> np.ndarray:
+        return self.o[self.start[p]:self.start[p + 1]]
+
+    def subject_counts(self, p: int) -> Tuple[np.ndarray, np.ndarray]:
+        """Distinct subjects of predicate p (sorted) and their triple counts."""
+        if p not in self._subj_counts:
+            s = self.subjects(p)  # already sorted
+            if s.size == 0:
+                self._subj_counts[p] = (s, s.astype(np.float64))
+            else:
+                edge = np.concatenate([[True], s[1:] != s[:-1]])
+                ids = s[edge]
+                idx = np.nonzero(edge)[0]
+                cnt = np.diff(np.concatenate([idx, [s.size]])).astype(np.float64)
+                self._subj_counts[p] = (ids, cnt)
+        return self._subj_counts[p]
+
+    def object_counts(self, p: int) -> Tuple[np.ndarray, np.ndarray]:
+        if p not in self._obj_counts:
+            ids, cnt = np.unique(self.objects(p), return_counts=True)
+            self._obj_counts[p] = (ids, cnt.astype(np.float64))
+        return self._obj_counts[p]
+
+
+def _lookup(ids: np.ndarray, cnt: np.ndarray, keys: np.ndarray) -> np.ndarray:
+    """cnt of each key in (ids, cnt), 0 where absent."""
+    if ids.size == 0:
+        return np.zeros(keys.size)
+    i = np.clip(np.searchsorted(ids, keys), 0, ids.size - 1)
+    return np.where(ids[i] == keys, cnt[i], 0.0)
+
+
+@dataclass
+class Term:
+    p: int
+    o: int = 0   # 0: free object
+
+
+def _realise(idx: PredIndex, sigma: float, rng, allow_object: bool) -> Term:
+    shares = idx.share[idx.preds]
+    smin = shares.min()
+    if sigma >= smin or not allow_object:
+        j = int(np.argmin(np.abs(np.log(shares) - np.log(max(sigma, smin)))))
+        return Term(int(idx.preds[j]))
+    target = sigma * idx.n
+    # rare predicates first: their objects give the small counts
+    order = idx.preds[np.argsort(shares)]
+    best = None
+    for p in order[:60]:
+        ids, cnt = idx.object_counts(int(p))
+        j = int(np.argmin(np.abs(np.log(cnt) - np.log(target))))
+        score = abs(np.log(cnt[j]) - np.log(target))
+        if best is None or score < best[0]:
+            best = (score, int(p), int(ids[j]))
+    return Term(best[1], best[2])
+
+
+def _star_prefix_counts(idx: PredIndex, terms: List[Term]) -> List[float]:
+    """Rows after each join of a star on ?s, in plan order."""
+    out = []
+    supp, w = None, None
+    for t in terms:
+        if t.o:
+            s = idx.subjects(t.p)[idx.objects(t.p) == t.o]
+            ids, cnt = np.unique(s, return_counts=True)
+            cnt = cnt.astype(np.float64)
+        else:
+            ids, cnt = idx.subject_counts(t.p)
+        if supp is None:
+            supp, w = ids, cnt
+        else:
+            c = _lookup(ids, cnt, supp)
+            keep = c > 0
+            supp, w = supp[keep], w[keep] * c[keep]
+        out.append(float(w.sum()))
+    return out
+
+
+def _chain_prefix_counts(idx: PredIndex, terms: List[Term], cap: float) -> List[float]:
+    """Rows after each join of a chain ?x0 p1 ?x1 . ?x1 p2 ?x2 . ..., in plan
+    order; stops early (returns inf) once a prefix exceeds `cap`."""
+    out = []
+    # weights on the chain's current end variable
+    t0 = terms[0]
+    s0, o0 = idx.subjects(t0.p), idx.objects(t0.p)
+    if t0.o:
+        o0 = o0[o0 == t0.o]
+    ends, w = np.unique(o0, return_counts=True)
+    w = w.astype(np.float64)
+    out.append(float(w.sum()))
+    for t in terms[1:]:
+        if out[-1] > cap:
+            return out + [np.inf] * (len(terms) - len(out))
+        sp = idx.subjects(t.p)
+        lo = np.searchsorted(sp, ends, side="left")
+        hi = np.searchsorted(sp, ends, side="right")
+        reps = hi - lo
+        total_paths = float((reps * w).sum()) if reps.size else 0.0
+        if not t.o and total_paths > cap:
+            return out + [np.inf] * (len(terms) - len(out))
+        base = idx.start[t.p]
+        tot = int(reps.sum())
+        if tot > 4 * cap:
+            return out + [np.inf] * (len(terms) - len(out))
+        sel = np.repeat(np.arange(ends.size), reps)
+        # positions lo[j] + 0 .. reps[j]-1 for every end j, vectorised
+        first = np.concatenate([[0], np.cumsum(reps)[:-1]]) if reps.size else reps
+        pos = base + np.repeat(lo - first, reps) + np.arange(tot)
+        objs = idx.o[pos]
+        ww = w[sel]
+        if t.o:
+            keep = objs == t.o
+            objs, ww = objs[keep], ww[keep]
+        ends, inv = np.unique(objs, return_inverse=True)
+        w = np.bincount(inv, weights=ww, minlength=ends.size) if ends.size else np.zeros(0)
+        out.append(float(w.sum()))
+    return out
+
+
+def _plan(shape: str, terms: List[Term]) -> Plan:
+    plan = Plan()
+    if shape == "star":
+        for i, t in enumerate(terms):
+            if t.o:
+                plan.scan(Pattern(0, t.p, t.o, 0, -1, -1))
+            else:
+                plan.scan(Pattern(0, t.p, 0, 0, -1, 1 + i))
+            if i:
+                plan.join(0)
+    else:
+        for i, t in enumerate(terms):
+            plan.scan(Pattern(0, t.p, t.o, i, -1, -1 if t.o else i + 1))
+            if i:
+                plan.join(i)
+    return plan
+
+
+def batch_queries(idx: PredIndex, nq: int = 1024, seed: int = 4, max_rows: int = 1 << 22,
+                  sigma_range=(1e-6, 1e-1), max_patterns: int = 6) -> Tuple[List[Plan], List[Dict]]:
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0xBA7C])))
+    lo, hi = np.log10(sigma_range[0]), np.log10(sigma_range[1])
+    plans, infos = [], []
+    for q in range(nq):
+        for attempt in range(1000):
+            k = int(rng.integers(1, max_patterns + 1))
+            shape = "star" if rng.random() < 0.5 else "chain"
+            sig = 10.0 ** rng.uniform(lo, hi, size=k)
+            terms = [_realise(idx, float(s), rng, shape == "star" or i == k - 1)
+                     for i, s in enumerate(sig)]
+            if shape == "star":
+                pref = _star_prefix_counts(idx, terms)
+            else:
+                pref = _chain_prefix_counts(idx, terms, max_rows)
+            pat_rows = [float(idx.start[t.p + 1] - idx.start[t.p]) for t in terms]
+            if max(pref) <= max_rows:
+                break
+        plans.append(_plan(shape, terms))
+        infos.append({"shape": shape, "k": k, "sigma": [float(s) for s in sig],
+                      "rows": int(pref[-1]), "prefix_rows": [int(x) for x in pref],
+                      "pattern_rows_max": int(max(pat_rows)), "attempts": attempt + 1})
+    return plans, infos

@@ -106,35 +106,93 @@ def _rank_counts(rng: np.random.Generator, col: ColSpec, count: int) -> np.ndarr
     return rng.multinomial(count, pv)
 
 
-def _draw_column(spec: GraphSpec, which: int, col: ColSpec, out: np.ndarray) -> None:
-    n = spec.n
+def _col_ids(spec: GraphSpec, which: int, col: ColSpec) -> np.ndarray:
     ids = np.arange(1, col.n_ids + 1, dtype=np.uint32)
     if col.permute:
         prng = np.random.Generator(np.random.PCG64(
             np.random.SeedSequence([spec.seed, which, 0xB1])))
         ids = prng.permutation(ids)
-    for ci, start in enumerate(range(0, n, CHUNK)):
+    return ids
+
+
+def _chunk_values(spec: GraphSpec, which: int, col: ColSpec, ids: np.ndarray, ci: int,
+                  cnt: int) -> np.ndarray:
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([spec.seed, which, ci])))
+    if col.dist == "uniform":
+        ranks = rng.integers(1, col.n_ids + 1, size=cnt, dtype=np.int64)
+        return ids[ranks - 1]
+    counts = _rank_counts(rng, col, cnt)
+    vals = np.repeat(ids, counts)
+    rng.shuffle(vals)
+    return vals
+
+
+def _draw_column(spec: GraphSpec, which: int, col: ColSpec, out: np.ndarray) -> None:
+    ids = _col_ids(spec, which, col)
+    for ci, start in enumerate(range(0, spec.n, CHUNK)):
+        cnt = min(CHUNK, spec.n - start)
+        out[start:start + cnt] = _chunk_values(spec, which, col, ids, ci, cnt)
+
+
+def _worker(args):
+    """Fill one (column, chunk) of a shared-memory graph (process pool)."""
+    shm_name, n, spec, which, ci = args
+    from multiprocessing import shared_memory
+    shm = shared_memory.SharedMemory(name=shm_name)
+    try:
+        g = np.ndarray((n, 3), dtype=np.uint32, buffer=shm.buf)
+        col = (spec.s, spec.p, spec.o)[which]
+        start = ci * CHUNK
         cnt = min(CHUNK, n - start)
-        rng = np.random.Generator(np.random.PCG64(
-            np.random.SeedSequence([spec.seed, which, ci])))
-        if col.dist == "uniform":
-            ranks = rng.integers(1, col.n_ids + 1, size=cnt, dtype=np.int64)
-            vals = ids[ranks - 1]
-        else:
-            counts = _rank_counts(rng, col, cnt)
-            vals = np.repeat(ids, counts)
-            rng.shuffle(vals)
-        out[start:start + cnt] = vals
+        g[start:start + cnt, which] = _chunk_values(spec, which, col, _col_ids(spec, which, col),
+                                                    ci, cnt)
+        del g
+    finally:
+        shm.close()
+    return ci
 
 
-def make_graph(spec: GraphSpec) -> np.ndarray:
-    """Return the (N, 3) uint32 row-major triple array for `spec`."""
-    g = np.empty((spec.n, 3), dtype=np.uint32)
-    for which, col in enumerate((spec.s, spec.p, spec.o)):
-        tmp = np.empty(spec.n, dtype=np.uint32)
-        _draw_column(spec, which, col, tmp)
-        g[:, which] = tmp
-        del tmp
+def _gpu_initialised() -> bool:
+    import sys
+    torch = sys.modules.get("torch")
+    try:
+        return bool(torch is not None and torch.cuda.is_initialized())
+    except Exception:  # noqa: BLE001
+        return True
+
+
+def make_graph(spec: GraphSpec, workers: int | None = None) -> np.ndarray:
+    """Return the (N, 3) uint32 row-major triple array for `spec`.
+
+    Each (column, chunk) is drawn from its own seed, so the result is the
+    same whether chunks are drawn in one process or by a pool of forked
+    workers (used for graphs of more than two chunks).  A process that has
+    already initialised a GPU draws serially, so no GPU state is forked."""
+    nchunks = (spec.n + CHUNK - 1) // CHUNK
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if _gpu_initialised():
+        workers = 1
+    if nchunks <= 2 or workers <= 1:
+        g = np.empty((spec.n, 3), dtype=np.uint32)
+        for which, col in enumerate((spec.s, spec.p, spec.o)):
+            tmp = np.empty(spec.n, dtype=np.uint32)
+            _draw_column(spec, which, col, tmp)
+            g[:, which] = tmp
+            del tmp
+        return g
+    from concurrent.futures import ProcessPoolExecutor
+    from multiprocessing import get_context, shared_memory
+    shm = shared_memory.SharedMemory(create=True, size=spec.n * 12)
+    try:
+        jobs = [(shm.name, spec.n, spec, which, ci) for which in range(3) for ci in range(nchunks)]
+        with ProcessPoolExecutor(max_workers=workers, mp_context=get_context("fork")) as ex:
+            list(ex.map(_worker, jobs))
+        g = np.empty((spec.n, 3), dtype=np.uint32)
+        g[:] = np.ndarray((spec.n, 3), dtype=np.uint32, buffer=shm.buf)
+    finally:
+        shm.close()
+        shm.unlink()
     return g
 
 

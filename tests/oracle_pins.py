@@ -270,6 +270,15 @@ def check_random_plans(O, n=300, seed=99):
         assert got.vars == wv and _rows(got) == want, (i, plan)
 
 
+def check_random_plans_sortmerge(O, n=300, seed=77):
+    """The same plans with every plan join forced onto the sort-merge path."""
+    O.set_nested_join_limit(0.0)
+    try:
+        check_random_plans(O, n, seed)
+    finally:
+        O.set_nested_join_limit(1e8)
+
+
 # ---------------------------------------------------------------------------
 # invariants at size (independent numpy arithmetic)
 # ---------------------------------------------------------------------------
@@ -333,4 +342,4 @@ def check_invariants_tiny_config(O):
 ALL_CHECKS = [check_rule11, check_toy_sec3, check_exhaustive_scan, check_exhaustive_join,
               check_table3_matrix, check_union_listing4, check_scan_multi_bruteforce,
               check_union_bruteforce, check_filter_bruteforce, check_random_plans,
-              check_invariants_tiny_config]
+              check_random_plans_sortmerge, check_invariants_tiny_config]

@@ -162,3 +162,38 @@ def test_query_errors(ctx, graphs):
     with pytest.raises(TidError) as e:
         ctx.query(G, Plan().scan(pat("?a 7 ?b", n)).scan(pat("?c 8 ?d", n)).join(n["?a"]))
     assert e.value.status == -5
+
+
+def test_query_batch_equals_alone(ctx, graphs):
+    """Every plan inside a batch returns exactly what it returns alone, and
+    what the oracle returns (small graph, mixed star/chain/union plans)."""
+    g = graphs("small")
+    G = ctx.load(g)
+    rng = np.random.default_rng(77)
+    plans = []
+    for i in range(40):
+        n = {}
+        k = int(rng.integers(1, 5))
+        preds = rng.integers(1, 51, size=k)
+        p = Plan()
+        if i % 3 == 0:      # star on ?s
+            for j, pid in enumerate(preds):
+                p.scan(pat(f"?s {pid} ?o{j}", n))
+                if j:
+                    p.join(n["?s"])
+        elif i % 3 == 1:    # chain
+            for j, pid in enumerate(preds):
+                p.scan(pat(f"?x{j} {pid} ?x{j + 1}", n))
+                if j:
+                    p.join(n[f"?x{j}"])
+        else:               # union of single patterns, DISTINCT
+            for pid in preds:
+                p.scan(pat(f"?s {pid} ?o", n))
+            p.union(k, True)
+        plans.append(p)
+    batch = ctx.query_batch(G, plans)
+    for p, t in zip(plans, batch):
+        alone = ctx.query(G, p)
+        assert np.array_equal(t.to_numpy(), alone.to_numpy())
+        same(t, oracle.query(g, p))
+    assert ctx.query_batch(G, []) == []

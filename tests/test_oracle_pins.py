@@ -104,3 +104,7 @@ def test_hypothesis_plans(oracle_lib, seed):
 
 def test_scan_multi_bruteforce(oracle_lib):
     P.check_scan_multi_bruteforce(oracle_lib)
+
+
+def test_random_plans_sortmerge_joins(oracle_lib):
+    P.check_random_plans_sortmerge(oracle_lib)
