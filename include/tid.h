@@ -204,6 +204,12 @@ tid_status tid_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan, tid
    output is written.  Synchronises. */
 tid_status tid_query_batch(tid_ctx *ctx, const tid_graph *g, const tid_plan *const *plans,
                            int32_t nq, tid_table **outs);
+/* Upper estimate of the device bytes a plan holds while it runs: the sum of
+   its scans' output buffers (sized from the load-time histograms, Sec. 3's
+   one-pass search) times two for join intermediates.  Host only, no device
+   work; used to admit queries against a memory budget. */
+tid_status tid_plan_estimate(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan,
+                             uint64_t *bytes);
 
 #ifdef __cplusplus
 }

@@ -69,6 +69,7 @@ SIGNATURES = {
     "tid_query": (_S, [_VP, _VP, ctypes.POINTER(tid_plan), _PP]),
     "tid_query_batch": (_S, [_VP, _VP, ctypes.POINTER(ctypes.POINTER(tid_plan)), ctypes.c_int32,
                              _PP]),
+    "tid_plan_estimate": (_S, [_VP, _VP, ctypes.POINTER(tid_plan), _U64P]),
 }
 
 

@@ -44,6 +44,7 @@ std::unique_ptr<tid_table> sort_table(tid_ctx *, const tid_table *, int);
 std::unique_ptr<tid_table> run_query(tid_ctx *, const tid_graph *, const tid_plan *);
 std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *, const tid_graph *,
                                                   const tid_plan *const *, int);
+uint64_t estimate_plan_bytes(const tid_graph *, const tid_plan *);
 std::unique_ptr<tid_table> copy_columns(tid_ctx *, const uint32_t *const *, int32_t,
                                         const int32_t *, uint64_t, int);
 }  // namespace tid
@@ -344,6 +345,15 @@ tid_status tid_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan, tid
     });
     if (st == TID_OK) *out = res.release();
     return st;
+}
+
+tid_status tid_plan_estimate(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan,
+                             uint64_t *bytes) {
+    return guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(g && plan && bytes, TID_E_INVALID_ARG, "null argument");
+        *bytes = tid::estimate_plan_bytes(g, plan);
+    });
 }
 
 tid_status tid_query_batch(tid_ctx *ctx, const tid_graph *g, const tid_plan *const *plans,

@@ -284,6 +284,9 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
 // ---------------------------------------------------------------------------
 
 int device_cus(tid_ctx *ctx);
+// Workgroups of `kernel` (BLOCK threads, `lds` dynamic LDS bytes) resident per
+// CU; cached per (kernel, lds) and safe to call from several host threads.
+int resident_blocks(const void *kernel, int block, size_t lds);
 
 // Launch the compaction of `n` items over the resident-capacity grid.  The
 // caller fills a.out[0..k) (columns, caps, counts, ncols); staging areas are
@@ -294,14 +297,7 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
     auto kern = compact_kernel<Src, BLOCK, IPT, MAXK, MAXC>;
     const size_t lds = (size_t)stage_words * sizeof(uint32_t);
-    static int blocks_per_cu = -1;  // per template instance
-    static size_t blocks_lds = 0;
-    if (blocks_per_cu < 0 || blocks_lds != lds) {
-        int nb = 0;
-        TID_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, BLOCK, lds));
-        blocks_per_cu = std::max(nb, 1);
-        blocks_lds = lds;
-    }
+    const int blocks_per_cu = resident_blocks((const void *)kern, BLOCK, lds);
     const uint64_t n = src.n;
     if (n == 0) return;
     uint64_t cols_total = 0;

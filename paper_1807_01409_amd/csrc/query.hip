@@ -360,6 +360,22 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
     return out;
 }
 
+uint64_t pattern_output_bound(const tid_graph *g, const tid_pattern &p);
+
+// Device bytes the plan's scans will hold (their outputs are sized by the
+// load-time histograms), times two for the intermediate results of joins.
+uint64_t estimate_plan_bytes(const tid_graph *g, const tid_plan *plan) {
+    PlanRun r;
+    compile_plan(plan, r);
+    uint64_t bytes = 0;
+    for (const tid_pattern &p : r.scans) {
+        int32_t vars[3], src[3];
+        const int nc = pattern_schema(p, vars, src);
+        bytes += pattern_output_bound(g, p) * 4ull * (uint64_t)std::max(nc, 1);
+    }
+    return 2 * bytes;
+}
+
 std::unique_ptr<tid_table> run_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan) {
     auto v = run_plans(ctx, g, &plan, 1);
     return std::move(v[0]);

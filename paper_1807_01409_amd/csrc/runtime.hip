@@ -321,7 +321,23 @@ uint64_t tid_graph::count_in(int pos, uint64_t lo, uint64_t hi) const {
     return c[b] - c[a];
 }
 
+#include <mutex>
+
 namespace tid {
+int resident_blocks(const void *kernel, int block, size_t lds) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, size_t>, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(kernel, lds);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int nb = 0;
+    TID_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, block, lds));
+    nb = std::max(nb, 1);
+    cache[key] = nb;
+    return nb;
+}
+
 int device_cus(tid_ctx *ctx) {
     if (ctx->num_cus <= 0) {
         int n = 0;

@@ -365,6 +365,10 @@ static uint64_t pattern_bound(const tid_graph *g, const tid_pattern &p) {
     return b;
 }
 
+uint64_t pattern_output_bound(const tid_graph *g, const tid_pattern &p) {
+    return pattern_bound(g, p);
+}
+
 struct Shape {
     int block, ipt;
 };
@@ -420,14 +424,7 @@ static void launch_multi(tid_ctx *ctx, const tid_graph *g, MultiArgs &a, int k, 
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
     auto kern = scan_multi_kernel<BLOCK, IPT>;
     const size_t lds = (size_t)sw * sizeof(uint32_t);
-    static int blocks_per_cu = -1;
-    static size_t blocks_lds = 0;
-    if (blocks_per_cu < 0 || blocks_lds != lds) {
-        int nb = 0;
-        TID_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kern, BLOCK, lds));
-        blocks_per_cu = std::max(nb, 1);
-        blocks_lds = lds;
-    }
+    const int blocks_per_cu = resident_blocks((const void *)kern, BLOCK, lds);
     uint64_t cols_total = 0;
     for (int j = 0; j < k; ++j) cols_total += (uint64_t)a.out[j].ncols;
     const uint32_t rows_per = (uint32_t)(sw / std::max<uint64_t>(cols_total, 1));

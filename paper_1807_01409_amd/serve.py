@@ -1,0 +1,172 @@
+"""Continuous-batching query server over a graph resident in HBM.
+
+Requests arrive on a clock (open loop).  A dispatcher admits waiting
+requests in arrival order while the estimated device bytes of everything in
+flight stay under a budget (tid_plan_estimate), and hands each admitted group
+to a free worker.  Every worker owns a library context and its own HIP
+stream, so the batches of different workers run on the device at the same
+time; a request that arrives while others are running joins the next group
+as soon as a worker and budget free up.  Each group runs as one
+tid_query_batch call, whose results are exactly those of tid_query alone.
+"""
+from __future__ import annotations
+
+import collections
+import queue
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Callable, List, Optional, Sequence
+
+import numpy as np
+
+from .tid import Context, Graph
+
+
+@dataclass
+class Request:
+    rid: int
+    plan: object
+    arrival: float          # seconds from the start of the run
+    est_bytes: int = 0
+    admitted: float = -1.0
+    done: float = -1.0
+    rows: int = -1
+    result: Optional[np.ndarray] = None
+
+
+@dataclass
+class ServeStats:
+    completed: int
+    wall_s: float
+    qps: float
+    p50_ms: float
+    p99_ms: float
+    mean_batch: float
+    max_inflight_bytes: int
+    max_queue: int
+    latencies_ms: List[float] = field(default_factory=list)
+
+
+class Server:
+    """Workers share one resident graph (read only) loaded by the first context."""
+
+    def __init__(self, triples, workers: int = 2, budget_bytes: int = 64 << 30,
+                 max_batch: int = 256, allocator: str = "pool", device: int = 0):
+        self.ctxs = [Context(device, allocator=allocator) for _ in range(workers)]
+        self.graph: Graph = self.ctxs[0].load(triples)
+        self.budget = int(budget_bytes)
+        self.max_batch = int(max_batch)
+        self._jobs: "queue.Queue" = queue.Queue()
+        self._done: "queue.Queue" = queue.Queue()
+        self._threads = []
+        self._keep = False
+        self._t0 = 0.0
+        for w in range(workers):
+            th = threading.Thread(target=self._worker, args=(w,), daemon=True)
+            th.start()
+            self._threads.append(th)
+
+    # -- workers ------------------------------------------------------------
+    def _worker(self, w: int):
+        ctx = self.ctxs[w]
+        while True:
+            batch = self._jobs.get()
+            if batch is None:
+                return
+            try:
+                tabs = ctx.query_batch(self.graph, [r.plan for r in batch])
+                for r, t in zip(batch, tabs):
+                    if self._keep:
+                        r.result = t.to_numpy()
+                        r.rows = r.result.shape[0]
+                    else:
+                        r.rows = t.nrows
+                    t.free()
+                err = None
+            except Exception as e:  # noqa: BLE001 - reported to the dispatcher
+                err = e
+            now = time.perf_counter() - self._t0
+            for r in batch:
+                r.done = now
+            self._done.put((w, batch, err))
+
+    def close(self):
+        for _ in self._threads:
+            self._jobs.put(None)
+        for th in self._threads:
+            th.join()
+        self.graph.free()
+        for c in self.ctxs:
+            c.close()
+
+    # -- dispatcher ----------------------------------------------------------
+    def run(self, requests: Sequence[Request], keep_results: bool = False,
+            warmup_s: float = 0.0) -> ServeStats:
+        """Serve `requests` (sorted by arrival) in real time; returns latency
+        and throughput over the requests arriving after `warmup_s`."""
+        ctx0 = self.ctxs[0]
+        for r in requests:
+            r.est_bytes = ctx0.plan_estimate(self.graph, r.plan)
+        self._keep = keep_results
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        waiting: "collections.deque[Request]" = collections.deque()
+        free = len(self.ctxs)
+        inflight = 0
+        nxt = 0
+        finished = 0
+        batches = []
+        max_inflight = 0
+        max_queue = 0
+        self._t0 = time.perf_counter()
+        while finished < len(reqs):
+            now = time.perf_counter() - self._t0
+            while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                waiting.append(reqs[nxt])
+                nxt += 1
+            max_queue = max(max_queue, len(waiting))
+            # admit in arrival order while a worker and budget are free; a
+            # request larger than the budget runs alone when nothing else does
+            while free and waiting:
+                group = []
+                while waiting and len(group) < self.max_batch:
+                    r = waiting[0]
+                    if inflight + r.est_bytes > self.budget and (group or inflight):
+                        break
+                    group.append(waiting.popleft())
+                    inflight += r.est_bytes
+                if not group:
+                    break
+                t_adm = time.perf_counter() - self._t0
+                for r in group:
+                    r.admitted = t_adm
+                self._jobs.put(group)
+                batches.append(len(group))
+                free -= 1
+            max_inflight = max(max_inflight, inflight)
+            # wait for a completion or the next arrival
+            timeout = 0.05
+            if nxt < len(reqs):
+                timeout = max(0.0, min(timeout, reqs[nxt].arrival - now))
+            try:
+                w, batch, err = self._done.get(timeout=timeout if timeout > 0 else 1e-4)
+            except queue.Empty:
+                continue
+            if err is not None:
+                raise err
+            free += 1
+            for r in batch:
+                inflight -= r.est_bytes
+            finished += len(batch)
+        wall = time.perf_counter() - self._t0
+        meas = [r for r in reqs if r.arrival >= warmup_s]
+        lat = np.array([(r.done - r.arrival) * 1e3 for r in meas]) if meas else np.zeros(1)
+        span = (max(r.done for r in meas) - warmup_s) if meas else wall
+        return ServeStats(completed=len(meas), wall_s=wall,
+                          qps=len(meas) / span if span > 0 else 0.0,
+                          p50_ms=float(np.percentile(lat, 50)),
+                          p99_ms=float(np.percentile(lat, 99)),
+                          mean_batch=float(np.mean(batches)) if batches else 0.0,
+                          max_inflight_bytes=int(max_inflight), max_queue=int(max_queue),
+                          latencies_ms=lat.tolist())
+

@@ -141,6 +141,9 @@ class Context:
     def query_batch(self, g: "Graph", plans) -> List["Table"]:
         return tid_query_batch(self, g, plans)
 
+    def plan_estimate(self, g: "Graph", plan) -> int:
+        return tid_plan_estimate(self, g, plan)
+
     def table(self, rows: np.ndarray, vars_: Sequence[int]) -> "Table":
         return tid_table_from_columns(self, rows, vars_)
 
@@ -308,6 +311,14 @@ def tid_query_batch(ctx: Context, g: Graph, plans) -> List[Table]:
     outs = (ctypes.c_void_p * max(1, len(cps)))()
     _check(ctx.ptr, ctx._lib.tid_query_batch(ctx.ptr, g._p, arr, len(cps), outs))
     return [Table(ctx, ctypes.c_void_p(outs[i])) for i in range(len(cps))]
+
+
+def tid_plan_estimate(ctx: Context, g: Graph, plan) -> int:
+    keep: list = []
+    cp = _plan(plan, keep)
+    v = ctypes.c_uint64()
+    _check(ctx.ptr, ctx._lib.tid_plan_estimate(ctx.ptr, g._p, ctypes.byref(cp), ctypes.byref(v)))
+    return int(v.value)
 
 
 def tid_query(ctx: Context, g: Graph, plan) -> Table:

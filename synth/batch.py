@@ -202,3 +202,10 @@ def batch_queries(idx: PredIndex, nq: int = 1024, seed: int = 4, max_rows: int =
                       "rows": int(pref[-1]), "prefix_rows": [int(x) for x in pref],
                       "pattern_rows_max": int(max(pat_rows)), "attempts": attempt + 1})
     return plans, infos
+
+
+def poisson_arrivals(n: int, qps: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of an open-loop Poisson process at rate qps
+    (seeded exponential gaps)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0x5E7E])))
+    return np.cumsum(rng.exponential(1.0 / qps, size=n))

@@ -1,0 +1,53 @@
+"""Batched and served queries: every result inside a batch or a served mix
+equals the same query run alone (byte for byte), and the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import CONFIGS, make_graph
+from synth.batch import PredIndex, batch_queries, poisson_arrivals
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mix(graphs):
+    g = graphs("medium", 2_000_000)
+    plans, infos = batch_queries(PredIndex(g), nq=96, seed=4, max_rows=1 << 16)
+    return g, plans, infos
+
+
+def test_batch_mix_equals_alone_and_oracle(ctx, mix):
+    g, plans, infos = mix
+    G = ctx.load(g)
+    batch = ctx.query_batch(G, plans)
+    for p, t, info in zip(plans, batch, infos):
+        alone = ctx.query(G, p).to_numpy()
+        got = t.to_numpy()
+        assert np.array_equal(got, alone)
+        assert got.shape[0] == info["rows"]          # exact count from the generator
+    for p, t in list(zip(plans, batch))[:32]:
+        o = oracle.query(g, p)
+        assert np.array_equal(t.to_numpy(), o.rows)
+
+
+@pytest.mark.parametrize("budget", [64 << 30, 8 << 20])
+def test_served_mix_equals_alone(ctx, mix, budget):
+    from paper_1807_01409_amd.serve import Request, Server
+    g, plans, infos = mix
+    arrivals = poisson_arrivals(240, qps=4000.0, seed=11)
+    reqs = [Request(i, plans[i % len(plans)], float(arrivals[i])) for i in range(240)]
+    srv = Server(g, workers=3, budget_bytes=budget, max_batch=48)
+    try:
+        stats = srv.run(reqs, keep_results=True)
+    finally:
+        srv.close()
+    assert stats.completed == len(reqs)
+    G = ctx.load(g)
+    alone = {}
+    for r in reqs:
+        key = r.rid % len(plans)
+        if key not in alone:
+            alone[key] = ctx.query(G, r.plan).to_numpy()
+        assert np.array_equal(r.result, alone[key]), r.rid
+    assert stats.p99_ms >= stats.p50_ms > 0
