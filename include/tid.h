@@ -77,7 +77,10 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
      "scan_items"         triples per thread in the scan kernel (autotuner)
      "scan_block"         threads per workgroup in the scan kernel (autotuner)
      "stage_words"        LDS words per workgroup for staging compacted rows
-                          (0 = default, at most 16384) */
+                          (0 = default, at most 16384)
+     "wide_min"           a plan batch with at least this many patterns of
+                          constant predicate uses the bucketed wide pass
+                          (0 = default 32) */
 tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value);
 tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value);
 

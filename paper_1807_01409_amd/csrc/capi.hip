@@ -121,6 +121,9 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
             ctx->opt.scan_items = value;
         } else if (k == "scan_block") {
             ctx->opt.scan_block = value;
+        } else if (k == "wide_min") {
+            TID_REQUIRE(value >= 0, TID_E_INVALID_ARG, "wide_min must be >= 0");
+            ctx->opt.wide_min = value;
         } else if (k == "stage_words") {
             TID_REQUIRE(value >= 0 && value <= 16384, TID_E_INVALID_ARG,
                         "stage_words must be in 0..16384");
@@ -141,6 +144,7 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "scan_items") *value = ctx->opt.scan_items;
         else if (k == "scan_block") *value = ctx->opt.scan_block;
         else if (k == "stage_words") *value = ctx->opt.stage_words;
+        else if (k == "wide_min") *value = ctx->opt.wide_min;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });
 }

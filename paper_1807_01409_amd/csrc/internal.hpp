@@ -57,6 +57,7 @@ struct Options {
     int64_t scan_items = 0;   // 0 = built-in default
     int64_t scan_block = 0;
     int64_t stage_words = 0;  // LDS staging words per workgroup (0 = default)
+    int64_t wide_min = 0;     // patterns needed before wide passes are used (0 = 32)
 };
 
 }  // namespace tid
@@ -187,6 +188,9 @@ struct CompiledPattern;  // scan.hip
 // Scan: fill `outs[j]` for k patterns in one pass.  Tables are allocated here.
 void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                 std::unique_ptr<tid_table> *outs);
+// any number of patterns, in as few passes over the graph as the kernels allow
+void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+               std::unique_ptr<tid_table> *outs);
 std::unique_ptr<tid_table> filter_range(tid_ctx *ctx, const tid_table *t, int col, uint32_t lo,
                                         uint32_t hi);
 // columns of L and of R kept, in that order, in a join's output

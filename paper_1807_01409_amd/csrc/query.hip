@@ -324,12 +324,11 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
             all.push_back(runs[i].scans[s]);
             where.emplace_back(i, (int)s);
         }
-    for (size_t s0 = 0; s0 < all.size(); s0 += TID_MAX_MULTI) {
-        const int k = (int)std::min<size_t>(TID_MAX_MULTI, all.size() - s0);
-        std::unique_ptr<tid_table> outs[TID_MAX_MULTI];
-        scan_multi(ctx, g, all.data() + s0, k, outs);
-        for (int j = 0; j < k; ++j)
-            runs[where[s0 + j].first].scanned[where[s0 + j].second] = std::move(outs[j]);
+    if (!all.empty()) {
+        std::vector<std::unique_ptr<tid_table>> outs(all.size());
+        scan_many(ctx, g, all.data(), (int)all.size(), outs.data());
+        for (size_t j = 0; j < all.size(); ++j)
+            runs[where[j].first].scanned[where[j].second] = std::move(outs[j]);
     }
     for (;;) {
         Needs needs;

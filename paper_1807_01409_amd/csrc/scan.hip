@@ -467,6 +467,50 @@ static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pa
     launch_multi<512, 16>(ctx, g, a, k, stage_words(ctx));
 }
 
+bool wide_eligible(const tid_pattern &p);
+void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+              tid_table *const *outs);
+
+// Any number of patterns: those with a constant (bucketable) predicate go
+// through wide passes of up to 1024 patterns when there are at least
+// `wide_min` of them; the rest through passes of up to 16.
+void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+               std::unique_ptr<tid_table> *outs) {
+    const int64_t wide_min = ctx->opt.wide_min > 0 ? ctx->opt.wide_min : 32;
+    std::vector<int> wide, rest;
+    for (int j = 0; j < k; ++j) (wide_eligible(pats[j]) ? wide : rest).push_back(j);
+    if ((int64_t)wide.size() < wide_min || ctx->opt.capacity_override > 0 || g->n == 0) {
+        rest.insert(rest.end(), wide.begin(), wide.end());
+        wide.clear();
+    }
+    // wide passes: tables sized by the histogram bounds, which cannot overflow
+    for (size_t w0 = 0; w0 < wide.size(); w0 += 1024) {
+        const int m = (int)std::min<size_t>(1024, wide.size() - w0);
+        std::vector<tid_pattern> wp(m);
+        std::vector<tid_table *> wt(m);
+        for (int j = 0; j < m; ++j) {
+            const tid_pattern &p = pats[wide[w0 + j]];
+            int32_t vars[3], src[3];
+            const int nc = pattern_schema(p, vars, src);
+            auto t = make_table(ctx, nc, vars, pattern_bound(g, p));
+            for (int c = 0; c < nc; ++c) t->maxv[c] = g->max_id[src[c]];
+            t->maxv_known = true;
+            wp[j] = p;
+            wt[j] = t.get();
+            outs[wide[w0 + j]] = std::move(t);
+        }
+        run_wide(ctx, g, wp.data(), m, wt.data());
+    }
+    for (size_t r0 = 0; r0 < rest.size(); r0 += TID_MAX_MULTI) {
+        const int m = (int)std::min<size_t>(TID_MAX_MULTI, rest.size() - r0);
+        std::vector<tid_pattern> rp(m);
+        std::unique_ptr<tid_table> rt[TID_MAX_MULTI];
+        for (int j = 0; j < m; ++j) rp[j] = pats[rest[r0 + j]];
+        scan_multi(ctx, g, rp.data(), m, rt);
+        for (int j = 0; j < m; ++j) outs[rest[r0 + j]] = std::move(rt[j]);
+    }
+}
+
 void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                 std::unique_ptr<tid_table> *outs) {
     TID_REQUIRE(k >= 1 && k <= TID_MAX_MULTI, TID_E_INVALID_ARG, "scan: 1..16 patterns per pass");

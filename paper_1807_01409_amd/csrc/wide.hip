@@ -1,0 +1,351 @@
+// wide.hip -- one pass over the graph for many patterns at once (Sec. 4.1's
+// keysArray at batch scale: a triple may answer several subqueries, and each
+// subquery gets its own result).  For up to kWideMax patterns with a constant
+// predicate:
+//   - the patterns sit in LDS, bucketed by predicate ID, so a triple is tested
+//     only against the patterns of its own predicate;
+//   - every wave owns one contiguous sub-range of the graph, so the per-pattern
+//     counts and ranks of a sub-range need no workgroup barrier: lanes that
+//     match the same pattern in the same step are grouped with ballots and
+//     their leader advances the wave's LDS counter for that pattern;
+//   - count pass -> column-wise exclusive scan of the (sub-range x pattern)
+//     count matrix -> write pass, which places every match at its pattern's
+//     offset for the sub-range plus its rank: ascending triple position per
+//     pattern, as a single-pattern scan gives.
+// The graph is read twice per pass; the work per triple is the size of its
+// predicate's bucket.
+#include "compact.hpp"
+
+#include <algorithm>
+
+namespace tid {
+
+constexpr int kWideMax = 1024;       // patterns per pass (10-bit ids)
+constexpr int kWideIdBits = 10;
+constexpr uint32_t kWidePreds = 4096;  // predicate IDs 1..4095 can be bucketed
+constexpr int kWideBlock = 256;
+constexpr int kWideNW = kWideBlock / dev::kWave;
+constexpr int kWideIPT = 8;
+
+// A pattern with a constant predicate, compacted for LDS.
+struct WidePat {
+    uint32_t s, o;       // constants (0 = free)
+    uint32_t lo, span;   // range test (x - lo) < span on position rpos
+    uint32_t flags;      // bit0 s bound, bit1 o bound, bit2 s==o, bits 3-4 range pos+1,
+                         // bits 5-6 ncols, bits 8-9/10-11/12-13 source position of col 0/1/2
+};
+
+struct WideOut {
+    uint32_t *col[3];
+    uint64_t cap;
+};
+
+struct WideArgs {
+    const uint32_t *g;
+    uint64_t n;
+    const WidePat *pats;      // k
+    const uint32_t *bucket;   // kWidePreds words: start << 12 | len
+    const uint16_t *ids;      // k pattern ids grouped by predicate
+    const WideOut *outs;      // k
+    uint64_t **counts_out;    // k device row-count words
+    int k;
+    uint64_t sub;             // triples per wave sub-range
+    uint32_t W;               // sub-ranges
+    uint32_t *cnt;            // W x k counts, then offsets in place
+    uint64_t *tot;            // k totals
+};
+
+struct __attribute__((packed, aligned(4))) WTri {
+    uint32_t v[3];
+};
+
+__device__ __forceinline__ bool wide_match(const WidePat &q, const WTri &t) {
+    bool ok = true;
+    if (q.flags & 1u) ok &= t.v[0] == q.s;
+    if (q.flags & 2u) ok &= t.v[2] == q.o;
+    if (q.flags & 4u) ok &= t.v[0] == t.v[2];
+    const uint32_t rp = (q.flags >> 3) & 3u;
+    if (rp) ok &= (t.v[rp - 1] - q.lo) < q.span;
+    return ok;
+}
+
+__device__ __forceinline__ uint64_t match_pid(uint32_t pid, bool m) {
+    uint64_t peers = dev::ballot(m);
+#pragma unroll
+    for (int b = 0; b < kWideIdBits; ++b) {
+        const bool bit = (pid >> b) & 1u;
+        const uint64_t mb = dev::ballot(bit);
+        peers &= bit ? mb : ~mb;
+    }
+    return m ? peers : 0ull;
+}
+
+// load the pattern table and predicate buckets into LDS
+__device__ __forceinline__ void wide_setup(const WideArgs &a, WidePat *s_pat, uint32_t *s_bucket,
+                                           uint16_t *s_ids) {
+    for (int i = threadIdx.x; i < a.k; i += blockDim.x) {
+        s_pat[i] = a.pats[i];
+        s_ids[i] = a.ids[i];
+    }
+    for (uint32_t p = threadIdx.x; p < kWidePreds; p += blockDim.x) s_bucket[p] = a.bucket[p];
+}
+
+// Walk the calling wave's sub-range in triple order.  For every match the
+// wave's running count of that pattern (s_run) advances by the number of
+// lanes matching it in the same step; the write pass (WRITE) also stores the
+// binding at that running count plus the lane's rank among them.
+template <bool WRITE>
+__device__ __forceinline__ void wide_walk(const WideArgs &a, const WidePat *s_pat,
+                                          const uint32_t *s_bucket, const uint16_t *s_ids,
+                                          uint32_t *s_run, uint64_t r0, uint64_t r1,
+                                          uint32_t *flags) {
+    const int lane = dev::lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+    for (uint64_t t0 = r0; t0 < r1; t0 += (uint64_t)dev::kWave * kWideIPT) {
+        WTri t[kWideIPT];
+#pragma unroll
+        for (int it = 0; it < kWideIPT; ++it) {
+            const uint64_t i = t0 + (uint64_t)it * dev::kWave + lane;
+            if (i < r1) t[it] = *reinterpret_cast<const WTri *>(a.g + 3 * i);
+            else t[it].v[0] = t[it].v[1] = t[it].v[2] = 0;
+        }
+#pragma unroll
+        for (int it = 0; it < kWideIPT; ++it) {
+            const uint32_t p = t[it].v[1];
+            const uint32_t b = (p > 0 && p < kWidePreds) ? s_bucket[p] : 0u;
+            const uint32_t start = b >> 12, len = b & 0xFFFu;
+            for (uint32_t c = 0; dev::ballot(c < len); ++c) {
+                const bool has = c < len;
+                const uint32_t pid = has ? s_ids[start + c] : 0u;
+                const bool m = has && wide_match(s_pat[pid], t[it]);
+                const uint64_t peers = match_pid(pid, m);
+                if (!m) continue;
+                const uint32_t before = s_run[pid];
+                if (WRITE) {
+                    const uint64_t pos = (uint64_t)before + (uint32_t)__popcll(peers & lt);
+                    const WidePat &q = s_pat[pid];
+                    const WideOut &o = a.outs[pid];
+                    const int nc = (q.flags >> 5) & 3u;
+                    if (pos < o.cap) {
+                        for (int cc = 0; cc < nc; ++cc) {
+                            const uint32_t src = (q.flags >> (8 + 2 * cc)) & 3u;
+                            o.col[cc][pos] = t[it].v[src];
+                        }
+                    } else {
+                        atomicOr(&flags[1], 1u);
+                    }
+                }
+                if (lane == __builtin_ctzll(peers)) s_run[pid] = before + (uint32_t)__popcll(peers);
+            }
+        }
+    }
+}
+
+// LDS layout: patterns (k), predicate buckets, pattern ids (k, padded to
+// words), then one running counter per (wave, pattern)
+struct WideLds {
+    WidePat *pat;
+    uint32_t *bucket;
+    uint16_t *ids;
+    uint32_t *run;
+};
+
+__device__ __forceinline__ WideLds wide_lds(uint32_t *lds, int k) {
+    WideLds l;
+    l.pat = reinterpret_cast<WidePat *>(lds);
+    l.bucket = reinterpret_cast<uint32_t *>(l.pat + k);
+    l.ids = reinterpret_cast<uint16_t *>(l.bucket + kWidePreds);
+    l.run = reinterpret_cast<uint32_t *>(l.ids + ((k + 1) & ~1));
+    return l;
+}
+
+__global__ __launch_bounds__(kWideBlock) void wide_count(WideArgs a, uint32_t *flags) {
+    extern __shared__ uint32_t lds[];
+    const WideLds l = wide_lds(lds, a.k);
+    WidePat *s_pat = l.pat;
+    uint32_t *s_bucket = l.bucket;
+    uint16_t *s_ids = l.ids;
+    uint32_t *s_cnt = l.run;  // [NW][k]
+    wide_setup(a, s_pat, s_bucket, s_ids);
+    const int wave = threadIdx.x / dev::kWave, lane = dev::lane_id();
+    uint32_t *run = s_cnt + (size_t)wave * a.k;
+    for (int j = lane; j < a.k; j += dev::kWave) run[j] = 0;
+    __syncthreads();
+    const uint32_t gw = blockIdx.x * kWideNW + wave;
+    if (gw < a.W) {
+        const uint64_t r0 = (uint64_t)gw * a.sub, r1 = min(a.n, r0 + a.sub);
+        wide_walk<false>(a, s_pat, s_bucket, s_ids, run, r0, r1, flags);
+        for (int j = lane; j < a.k; j += dev::kWave) a.cnt[(size_t)gw * a.k + j] = run[j];
+    }
+}
+
+// Column-wise exclusive scan of the W x k count matrix, in place; totals to
+// tot[] and to every pattern's table count.  One workgroup per 64 patterns:
+// lane = pattern, wave = a slice of the sub-ranges.
+constexpr int kColBlock = 1024;
+__global__ __launch_bounds__(kColBlock) void wide_offsets(WideArgs a) {
+    constexpr int kParts = kColBlock / dev::kWave;
+    __shared__ uint32_t s_part[kParts][dev::kWave];
+    const int lane = dev::lane_id(), part = threadIdx.x / dev::kWave;
+    const int j = blockIdx.x * dev::kWave + lane;
+    const uint32_t per = (a.W + kParts - 1) / kParts;
+    const uint32_t w0 = min(a.W, part * per), w1 = min(a.W, w0 + per);
+    uint32_t sum = 0;
+    if (j < a.k)
+        for (uint32_t w = w0; w < w1; ++w) sum += a.cnt[(size_t)w * a.k + j];
+    s_part[part][lane] = sum;
+    __syncthreads();
+    uint32_t run = 0;
+    for (int x = 0; x < part; ++x) run += s_part[x][lane];
+    if (j < a.k) {
+        for (uint32_t w = w0; w < w1; ++w) {
+            const uint32_t c = a.cnt[(size_t)w * a.k + j];
+            a.cnt[(size_t)w * a.k + j] = run;
+            run += c;
+        }
+        if (part == kParts - 1) {
+            a.tot[j] = run;
+            *a.counts_out[j] = run;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kWideBlock) void wide_write(WideArgs a, uint32_t *flags) {
+    extern __shared__ uint32_t lds[];
+    const WideLds l = wide_lds(lds, a.k);
+    WidePat *s_pat = l.pat;
+    uint32_t *s_bucket = l.bucket;
+    uint16_t *s_ids = l.ids;
+    uint32_t *s_run = l.run;
+    wide_setup(a, s_pat, s_bucket, s_ids);
+    const int wave = threadIdx.x / dev::kWave, lane = dev::lane_id();
+    uint32_t *run = s_run + (size_t)wave * a.k;
+    const uint32_t gw = blockIdx.x * kWideNW + wave;
+    if (gw < a.W)
+        for (int j = lane; j < a.k; j += dev::kWave) run[j] = a.cnt[(size_t)gw * a.k + j];
+    __syncthreads();
+    if (gw < a.W) {
+        const uint64_t r0 = (uint64_t)gw * a.sub, r1 = min(a.n, r0 + a.sub);
+        wide_walk<true>(a, s_pat, s_bucket, s_ids, run, r0, r1, flags);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+int pattern_schema(const tid_pattern &p, int32_t *vars, int32_t *src);
+
+// Can the pattern go through the wide pass?  Needs a constant predicate
+// that fits the bucket table and no variable repeated on the predicate.
+bool wide_eligible(const tid_pattern &p) {
+    return p.p != 0 && p.p < kWidePreds;
+}
+
+static WidePat compile_wide(const tid_pattern &p) {
+    int32_t vars[3], src[3];
+    const int nc = pattern_schema(p, vars, src);
+    WidePat w{};
+    w.s = p.s;
+    w.o = p.o;
+    if (p.s) w.flags |= 1u;
+    if (p.o) w.flags |= 2u;
+    if (p.vs >= 0 && p.vs == p.vo) w.flags |= 4u;
+    if (p.range_pos >= 0) {
+        w.flags |= (uint32_t)(p.range_pos + 1) << 3;
+        w.lo = p.lo;
+        w.span = p.hi > p.lo ? p.hi - p.lo : 0u;
+    }
+    w.flags |= (uint32_t)nc << 5;
+    for (int c = 0; c < nc; ++c) w.flags |= (uint32_t)src[c] << (8 + 2 * c);
+    return w;
+}
+
+static size_t wide_lds_bytes(int k) {
+    return sizeof(WidePat) * (size_t)k + 4 * kWidePreds + 2 * (size_t)((k + 1) & ~1) +
+           4 * (size_t)kWideNW * (size_t)k;
+}
+
+// One wide pass for k <= kWideMax eligible patterns into preallocated tables.
+void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+              tid_table *const *outs) {
+    TID_REQUIRE(k >= 1 && k <= kWideMax, TID_E_INTERNAL, "wide pass: bad pattern count");
+    std::vector<WidePat> wp(k);
+    std::vector<WideOut> wo(k);
+    std::vector<uint64_t *> wc(k);
+    std::vector<std::vector<uint16_t>> by_pred(kWidePreds);
+    for (int j = 0; j < k; ++j) {
+        TID_REQUIRE(wide_eligible(pats[j]), TID_E_INTERNAL, "wide pass: pattern not eligible");
+        wp[j] = compile_wide(pats[j]);
+        for (int c = 0; c < 3; ++c) wo[j].col[c] = c < outs[j]->ncols ? outs[j]->col[c] : nullptr;
+        wo[j].cap = outs[j]->cap;
+        wc[j] = outs[j]->d_count;
+        by_pred[pats[j].p].push_back((uint16_t)j);
+    }
+    std::vector<uint32_t> bucket(kWidePreds, 0);
+    std::vector<uint16_t> ids;
+    for (uint32_t p = 0; p < kWidePreds; ++p) {
+        if (by_pred[p].empty()) continue;
+        bucket[p] = ((uint32_t)ids.size() << 12) | (uint32_t)by_pred[p].size();
+        ids.insert(ids.end(), by_pred[p].begin(), by_pred[p].end());
+    }
+    // tables of constants, in one device block
+    const size_t b_pats = align_up(sizeof(WidePat) * k), b_bucket = align_up(4 * kWidePreds),
+                 b_ids = align_up(2 * (size_t)k), b_outs = align_up(sizeof(WideOut) * k),
+                 b_cnts = align_up(8 * (size_t)k), b_tot = align_up(8 * (size_t)k);
+    const size_t consts = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot;
+    std::vector<char> host(consts, 0);
+    char *h = host.data();
+    std::memcpy(h, wp.data(), sizeof(WidePat) * k);
+    std::memcpy(h + b_pats, bucket.data(), 4 * kWidePreds);
+    std::memcpy(h + b_pats + b_bucket, ids.data(), 2 * (size_t)k);
+    std::memcpy(h + b_pats + b_bucket + b_ids, wo.data(), sizeof(WideOut) * k);
+    std::memcpy(h + b_pats + b_bucket + b_ids + b_outs, wc.data(), 8 * (size_t)k);
+    DevBuf dconst(ctx, consts);
+    TID_HIP(hipMemcpyAsync(dconst.get(), host.data(), consts, hipMemcpyHostToDevice, ctx->stream));
+    char *d = dconst.get<char>();
+
+    const size_t lds = wide_lds_bytes(k);
+    static bool attr_set = false;
+    if (!attr_set) {  // allow up to 160 KB of dynamic LDS per workgroup
+        TID_HIP(hipFuncSetAttribute((const void *)wide_count,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        TID_HIP(hipFuncSetAttribute((const void *)wide_write,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        attr_set = true;
+    }
+    const int per_cu = resident_blocks((const void *)wide_write, kWideBlock, lds);
+    const uint64_t waves = (uint64_t)per_cu * device_cus(ctx) * kWideNW;
+    const uint64_t unit = (uint64_t)dev::kWave * kWideIPT;
+    const uint64_t units = (g->n + unit - 1) / unit;
+    uint64_t W = std::max<uint64_t>(1, std::min(units, waves));
+    const uint64_t sub = (units + W - 1) / W * unit;
+    W = (g->n + sub - 1) / sub;
+    DevBuf cnt(ctx, (size_t)W * k * 4);
+
+    WideArgs a{};
+    a.g = g->data.get<const uint32_t>();
+    a.n = g->n;
+    a.pats = reinterpret_cast<const WidePat *>(d);
+    a.bucket = reinterpret_cast<const uint32_t *>(d + b_pats);
+    a.ids = reinterpret_cast<const uint16_t *>(d + b_pats + b_bucket);
+    a.outs = reinterpret_cast<const WideOut *>(d + b_pats + b_bucket + b_ids);
+    a.counts_out = reinterpret_cast<uint64_t **>(d + b_pats + b_bucket + b_ids + b_outs);
+    a.tot = reinterpret_cast<uint64_t *>(d + b_pats + b_bucket + b_ids + b_outs + b_cnts);
+    a.k = k;
+    a.sub = sub;
+    a.W = (uint32_t)W;
+    a.cnt = cnt.get<uint32_t>();
+    const unsigned blocks = (unsigned)((W + kWideNW - 1) / kWideNW);
+    hipLaunchKernelGGL(wide_count, dim3(blocks), dim3(kWideBlock), lds, ctx->stream, a,
+                       ctx->d_flags);
+    TID_HIP(hipGetLastError());
+    hipLaunchKernelGGL(wide_offsets, dim3((unsigned)((k + dev::kWave - 1) / dev::kWave)),
+                       dim3(kColBlock), 0, ctx->stream, a);
+    TID_HIP(hipGetLastError());
+    hipLaunchKernelGGL(wide_write, dim3(blocks), dim3(kWideBlock), lds, ctx->stream, a,
+                       ctx->d_flags);
+    TID_HIP(hipGetLastError());
+}
+
+}  // namespace tid
