@@ -76,6 +76,8 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           0: return TID_E_CAPACITY instead
      "scan_items"         triples per thread in the scan kernel (autotuner)
      "scan_block"         threads per workgroup in the scan kernel (autotuner)
+     "scan_prefetch"      1: the scan loads tile t+1 before testing tile t;
+                          0: it does not; -1: built-in default (autotuner)
      "stage_words"        LDS words per workgroup for staging compacted rows
                           (0 = default, at most 16384)
      "wide_min"           a plan batch with at least this many patterns of

@@ -121,6 +121,8 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
             ctx->opt.scan_items = value;
         } else if (k == "scan_block") {
             ctx->opt.scan_block = value;
+        } else if (k == "scan_prefetch") {
+            ctx->opt.scan_prefetch = value < 0 ? -1 : (value ? 1 : 0);
         } else if (k == "wide_min") {
             TID_REQUIRE(value >= 0, TID_E_INVALID_ARG, "wide_min must be >= 0");
             ctx->opt.wide_min = value;
@@ -145,6 +147,7 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "scan_block") *value = ctx->opt.scan_block;
         else if (k == "stage_words") *value = ctx->opt.stage_words;
         else if (k == "wide_min") *value = ctx->opt.wide_min;
+        else if (k == "scan_prefetch") *value = ctx->opt.scan_prefetch;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });
 }

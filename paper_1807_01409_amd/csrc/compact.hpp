@@ -55,17 +55,24 @@ namespace dev {
 // Load one tile of items (striped: item `it` of thread `tid` is
 // t0 + it*BLOCK + tid), test them, and leave per-(item, wave) match counts of
 // every pattern in s_off.  Returns the match bits in mb.
-template <class Src, int BLOCK, int IPT, int MAXK>
-__device__ __forceinline__ void tile_matches(const Src &src, int k, uint64_t t0, uint64_t r1,
-                                             typename Src::Item *item, uint32_t *mb,
-                                             uint32_t (*s_off)[IPT * (BLOCK / kWave)]) {
-    constexpr int NW = BLOCK / kWave;
-    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+template <class Src, int BLOCK, int IPT>
+__device__ __forceinline__ void tile_load(const Src &src, uint64_t t0, uint64_t r1,
+                                          typename Src::Item *item) {
+    const int tid = threadIdx.x;
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
         const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
         item[it] = i < r1 ? src.load(i) : typename Src::Item{};
     }
+}
+
+// Test a loaded tile and leave the per-(item, wave) match counts in s_off.
+template <class Src, int BLOCK, int IPT, int MAXK>
+__device__ __forceinline__ void tile_test(const Src &src, int k, uint64_t t0, uint64_t r1,
+                                          const typename Src::Item *item, uint32_t *mb,
+                                          uint32_t (*s_off)[IPT * (BLOCK / kWave)]) {
+    constexpr int NW = BLOCK / kWave;
+    const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
 #pragma unroll
     for (int j = 0; j < MAXK; ++j) mb[j] = 0;
 #pragma unroll
@@ -84,6 +91,14 @@ __device__ __forceinline__ void tile_matches(const Src &src, int k, uint64_t t0,
             if (lane == 0) s_off[j][it * NW + wave] = (uint32_t)__popcll(b);
         }
     }
+}
+
+template <class Src, int BLOCK, int IPT, int MAXK>
+__device__ __forceinline__ void tile_matches(const Src &src, int k, uint64_t t0, uint64_t r1,
+                                             typename Src::Item *item, uint32_t *mb,
+                                             uint32_t (*s_off)[IPT * (BLOCK / kWave)]) {
+    tile_load<Src, BLOCK, IPT>(src, t0, r1, item);
+    tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, mb, s_off);
 }
 
 // exclusive offsets (in item order) of NV counts, in place; returns the total
@@ -112,7 +127,7 @@ __device__ __forceinline__ uint32_t offsets_in_place(uint32_t *s) {
 
 }  // namespace dev
 
-template <class Src, int BLOCK, int IPT, int MAXK, int MAXC>
+template <class Src, int BLOCK, int IPT, int MAXK, int MAXC, bool PREFETCH = false>
 __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAXK, MAXC> a,
                                                          uint64_t *sync, uint32_t *flags) {
     constexpr int NW = BLOCK / dev::kWave;
@@ -142,11 +157,22 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
     const uint64_t r1 = min(src.n, r0 + a.range);
 
     typename Src::Item item[IPT];
+    typename Src::Item next[PREFETCH ? IPT : 1];
     uint32_t mb[MAXK];
 
     // ---- phase 1: test the range, stage compacted outputs in LDS ----------
+    // With PREFETCH the loads of tile t+1 are issued before tile t is tested,
+    // so the workgroup keeps memory busy through its barriers.
+    if (PREFETCH && r0 < r1) dev::tile_load<Src, BLOCK, IPT>(src, r0, r1, next);
     for (uint64_t t0 = r0; t0 < r1; t0 += TILE) {
-        dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, mb, s_off);
+        if (PREFETCH) {
+#pragma unroll
+            for (int it = 0; it < IPT; ++it) item[it] = next[PREFETCH ? it : 0];
+            if (t0 + TILE < r1) dev::tile_load<Src, BLOCK, IPT>(src, t0 + TILE, r1, next);
+            dev::tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, mb, s_off);
+        } else {
+            dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, mb, s_off);
+        }
         __syncthreads();
         for (int j = wave; j < k; j += NW) {
             const uint32_t tot = dev::offsets_in_place<NV>(s_off[j]);
@@ -291,11 +317,11 @@ int resident_blocks(const void *kernel, int block, size_t lds);
 // Launch the compaction of `n` items over the resident-capacity grid.  The
 // caller fills a.out[0..k) (columns, caps, counts, ncols); staging areas are
 // laid out here over `stage_words` words of LDS.
-template <class Src, int BLOCK, int IPT, int MAXK, int MAXC>
+template <class Src, int BLOCK, int IPT, int MAXK, int MAXC, bool PREFETCH = false>
 void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, int k,
                     uint32_t stage_words) {
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
-    auto kern = compact_kernel<Src, BLOCK, IPT, MAXK, MAXC>;
+    auto kern = compact_kernel<Src, BLOCK, IPT, MAXK, MAXC, PREFETCH>;
     const size_t lds = (size_t)stage_words * sizeof(uint32_t);
     const int blocks_per_cu = resident_blocks((const void *)kern, BLOCK, lds);
     const uint64_t n = src.n;

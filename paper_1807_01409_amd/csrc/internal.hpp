@@ -58,6 +58,7 @@ struct Options {
     int64_t scan_block = 0;
     int64_t stage_words = 0;  // LDS staging words per workgroup (0 = default)
     int64_t wide_min = 0;     // patterns needed before wide passes are used (0 = 32)
+    int64_t scan_prefetch = -1;  // -1 built-in default, 0 off, 1 prefetch the next tile
 };
 
 }  // namespace tid

@@ -371,12 +371,14 @@ uint64_t pattern_output_bound(const tid_graph *g, const tid_pattern &p) {
 
 struct Shape {
     int block, ipt;
+    bool prefetch;
 };
 
 static Shape scan_shape(tid_ctx *ctx) {
-    Shape s{512, 16};
+    Shape s{512, 16, false};
     if (ctx->opt.scan_block) s.block = (int)ctx->opt.scan_block;
     if (ctx->opt.scan_items) s.ipt = (int)ctx->opt.scan_items;
+    if (ctx->opt.scan_prefetch >= 0) s.prefetch = ctx->opt.scan_prefetch > 0;
     return s;
 }
 
@@ -403,7 +405,10 @@ static void run_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, 
     const uint32_t sw = stage_words(ctx);
 #define TID_SCAN_CASE(B, I)                                                         \
     if (sh.block == B && sh.ipt == I) {                                             \
-        launch_compact<ScanSrc<MAXK>, B, I, MAXK, 3>(ctx, src, a, k, sw);          \
+        if (sh.prefetch)                                                            \
+            launch_compact<ScanSrc<MAXK>, B, I, MAXK, 3, true>(ctx, src, a, k, sw); \
+        else                                                                        \
+            launch_compact<ScanSrc<MAXK>, B, I, MAXK, 3, false>(ctx, src, a, k, sw); \
         return;                                                                     \
     }
     TID_SCAN_CASE(256, 16)

@@ -191,3 +191,19 @@ def test_scan_full_medium(ctx, graphs):
         p_id = int(np.argmin(np.abs(np.log(np.maximum(hist, 1) / n) - np.log(sigma))))
         p = Pattern(0, p_id, 0, 0, -1, 1)
         same(ctx.scan(G, p), oracle.scan(g, p))
+
+
+def test_autotune_shapes_agree(ctx, graphs, tmp_path, monkeypatch):
+    """The autotuner's sweep checks every shape against the first: results
+    are byte-identical across launch shapes, prefetch and staging sizes."""
+    from paper_1807_01409_amd import autotune
+    monkeypatch.setenv("TID_TUNE_CACHE", str(tmp_path / "tune.json"))
+    g = graphs("medium", 300_000)
+    G = ctx.load(g)
+    res = autotune.tune_scan(ctx, G, [pat("?s 2 ?o"), pat("?s 14 ?o")], reps=2,
+                             shapes=[(256, 16), (512, 8), (1024, 4)], stage_words=[4096, 16384])
+    assert len(res["table"]) == 12
+    entry = autotune.apply(ctx, G.n)
+    assert entry is not None and entry["options"] == res["options"]
+    for k in autotune.KEYS:
+        ctx.set_option(k, -1 if k == "scan_prefetch" else 0)
