@@ -102,17 +102,17 @@ def cpu_baseline(g, w):
 
 def event_time(torch, stream, fn, reps):
     """Average seconds per call of fn, with HIP events on `stream`, calls
-    queued back to back."""
-    keep = []
+    queued back to back.  Each result is released right after its call (in
+    stream order), so the allocator reuses one block and no allocation falls
+    inside the timed region."""
+    fn().free()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
     for _ in range(reps):
-        keep.append(fn())
+        fn().free()
     ev1.record(stream)
     ev1.synchronize()
-    for t in keep:
-        t.free()
     return ev0.elapsed_time(ev1) / 1e3 / reps
 
 
@@ -191,6 +191,34 @@ def batched(args):
     ctx.close()
 
 
+def scan_profile(args):
+    """Short run for rocprofv3 counter collection: each of the benchmark's
+    four single-pattern scans `--steps` times, then a plain device copy of a
+    graph-sized buffer (the calibration kernel for the byte counters)."""
+    import torch
+    from paper_1807_01409_amd import Context
+    from synth import CONFIGS, make_graph
+
+    spec = CONFIGS["medium"] if args.n is None else CONFIGS["medium"].with_n(args.n)
+    g = make_graph(spec)
+    w = build_workload(g)
+    ctx = Context(0)
+    G = ctx.load(g)
+    for p in w["scans"] + [w["range"]]:
+        for _ in range(args.steps):
+            ctx.scan(G, p).free()
+    ctx.synchronize()
+    src = torch.empty(spec.n * 3, dtype=torch.int32, device="cuda")
+    with torch.cuda.stream(ctx.stream):
+        for _ in range(args.steps):
+            dst = src.clone()
+            del dst
+    torch.cuda.synchronize()
+    log(f"scan-profile done: {len(w['scans']) + 1} scans x {args.steps}, copy of "
+        f"{spec.n * 12} bytes x {args.steps}")
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,7 +226,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=None, help="override graph size (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["medium", "batched"], default="medium")
+    ap.add_argument("--workload", choices=["medium", "batched", "scan-profile"],
+                    default="medium")
     ap.add_argument("--queries", type=int, default=1024)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -206,6 +235,9 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         batched(args)
+        return
+    if args.workload == "scan-profile":
+        scan_profile(args)
         return
 
     import torch
@@ -297,7 +329,7 @@ def main():
                    "star": w["star_info"], "union": w["union_info"], "range": w["range_info"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(khash),
-                     "kernel": "compact_kernel<ScanSrc<1>,512,16,1,3> (single-pattern scan)",
+                     "kernel": "compact_kernel<ScanSrc<1>,512,8,1,3,prefetch> (single-pattern scan)",
                      "per_launch": per_launch},
         "breakdown": breakdown,
         "cpu_baseline": cpu,

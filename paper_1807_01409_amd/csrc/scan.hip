@@ -375,7 +375,7 @@ struct Shape {
 };
 
 static Shape scan_shape(tid_ctx *ctx) {
-    Shape s{512, 16, false};
+    Shape s{512, 8, true};  // the autotuner's choice on the 50M-triple medium graph
     if (ctx->opt.scan_block) s.block = (int)ctx->opt.scan_block;
     if (ctx->opt.scan_items) s.ipt = (int)ctx->opt.scan_items;
     if (ctx->opt.scan_prefetch >= 0) s.prefetch = ctx->opt.scan_prefetch > 0;

@@ -7,7 +7,9 @@ callbacks) and the stream.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -31,6 +33,20 @@ def _check(ctx_ptr, st: int):
 def _pattern(p) -> L.tid_pattern:
     return L.tid_pattern(int(p.s), int(p.p), int(p.o), int(p.vs), int(p.vp), int(p.vo),
                          int(p.range_pos), int(p.lo), int(p.hi))
+
+
+_LIVE: "weakref.WeakSet" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    """Close contexts before the interpreter tears torch down (their free
+    callbacks call into torch)."""
+    for c in list(_LIVE):
+        try:
+            c.close()
+        except Exception:  # noqa: BLE001
+            pass
 
 
 class Context:
@@ -61,7 +77,8 @@ class Context:
                     return None
 
             def _free(user, ptr, nbytes, stream):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                if torch.cuda is not None:
+                    torch.cuda.caching_allocator_delete(int(ptr))
 
             self._cb = (L.ALLOC_FN(_alloc), L.FREE_FN(_free))
         elif allocator == "pool":
@@ -75,7 +92,7 @@ class Context:
             raise TidError(st, "tid_ctx_create failed")
         self._p = out
         self._lib = lib
-        self._children: list = []
+        _LIVE.add(self)
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
