@@ -80,6 +80,9 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           0: it does not; -1: built-in default (autotuner)
      "stage_words"        LDS words per workgroup for staging compacted rows
                           (0 = default, at most 16384)
+     "multi_kernel"       multi-pattern pass: 0 auto, 1 LDS pattern loop,
+                          2 unrolled (up to 8 patterns)   (autotuner)
+     "multi_shape"        launch shape index 0..3 of that kernel (autotuner)
      "wide_min"           a plan batch with at least this many patterns of
                           constant predicate uses the bucketed wide pass
                           (0 = default 32) */

@@ -121,6 +121,12 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
             ctx->opt.scan_items = value;
         } else if (k == "scan_block") {
             ctx->opt.scan_block = value;
+        } else if (k == "multi_kernel") {
+            TID_REQUIRE(value >= 0 && value <= 2, TID_E_INVALID_ARG, "multi_kernel is 0, 1 or 2");
+            ctx->opt.multi_kernel = value;
+        } else if (k == "multi_shape") {
+            TID_REQUIRE(value >= 0 && value <= 3, TID_E_INVALID_ARG, "multi_shape is 0..3");
+            ctx->opt.multi_shape = value;
         } else if (k == "scan_prefetch") {
             ctx->opt.scan_prefetch = value < 0 ? -1 : (value ? 1 : 0);
         } else if (k == "wide_min") {
@@ -148,6 +154,8 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "stage_words") *value = ctx->opt.stage_words;
         else if (k == "wide_min") *value = ctx->opt.wide_min;
         else if (k == "scan_prefetch") *value = ctx->opt.scan_prefetch;
+        else if (k == "multi_kernel") *value = ctx->opt.multi_kernel;
+        else if (k == "multi_shape") *value = ctx->opt.multi_shape;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });
 }

@@ -455,10 +455,54 @@ static void launch_multi(tid_ctx *ctx, const tid_graph *g, MultiArgs &a, int k, 
     TID_HIP(hipGetLastError());
 }
 
+// Up to MAXK patterns in the generic compaction kernel, fully unrolled.
+template <int MAXK, int B, int I>
+static void run_unrolled(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+                         tid_table *const *outs) {
+    ScanSrc<MAXK> src{};
+    src.g = g->data.get<const uint32_t>();
+    src.n = g->n;
+    CompactArgs<MAXK, 3> a{};
+    for (int j = 0; j < k; ++j) {
+        src.pat[j] = compile_pattern(pats[j]);
+        for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
+        a.out[j].cap = outs[j]->cap;
+        a.out[j].count = outs[j]->d_count;
+        a.out[j].ncols = outs[j]->ncols;
+    }
+    launch_compact<ScanSrc<MAXK>, B, I, MAXK, 3, true>(ctx, src, a, k, stage_words(ctx));
+}
+
+template <int MAXK>
+static void run_unrolled_shape(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+                               tid_table *const *outs, int shape) {
+    if (shape == 1)
+        run_unrolled<MAXK, 256, 8>(ctx, g, pats, k, outs);
+    else if (shape == 2)
+        run_unrolled<MAXK, 256, 16>(ctx, g, pats, k, outs);
+    else
+        run_unrolled<MAXK, 512, 8>(ctx, g, pats, k, outs);
+}
+
+// multi_kernel option: 1 the LDS pattern-loop kernel, 2 the unrolled kernel
+// (k <= 8); 0 picks the unrolled kernel up to 4 patterns and the loop kernel
+// above that (the 8-pattern unrolled instance spills to scratch and runs 3x
+// slower than the loop).  multi_shape 0 is 512 threads x 8 triples for both.
 static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                          tid_table *const *outs) {
     if (k == 1) {
         run_scan<1>(ctx, g, pats, k, outs);
+        return;
+    }
+    const int which = (int)ctx->opt.multi_kernel;
+    const int shape = (int)ctx->opt.multi_shape;
+    if ((which == 0 && k <= 4) || (which == 2 && k <= 8)) {
+        if (k == 2)
+            run_unrolled_shape<2>(ctx, g, pats, k, outs, shape);
+        else if (k <= 4)
+            run_unrolled_shape<4>(ctx, g, pats, k, outs, shape);
+        else
+            run_unrolled_shape<8>(ctx, g, pats, k, outs, shape);
         return;
     }
     MultiArgs a{};
@@ -469,7 +513,15 @@ static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pa
         a.out[j].count = outs[j]->d_count;
         a.out[j].ncols = outs[j]->ncols;
     }
-    launch_multi<512, 16>(ctx, g, a, k, stage_words(ctx));
+    const uint32_t sw = stage_words(ctx);
+    if (shape == 1)
+        launch_multi<512, 16>(ctx, g, a, k, sw);
+    else if (shape == 2)
+        launch_multi<256, 16>(ctx, g, a, k, sw);
+    else if (shape == 3)
+        launch_multi<1024, 8>(ctx, g, a, k, sw);
+    else
+        launch_multi<512, 8>(ctx, g, a, k, sw);
 }
 
 bool wide_eligible(const tid_pattern &p);
