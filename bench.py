@@ -191,6 +191,72 @@ def batched(args):
     ctx.close()
 
 
+def serving(args):
+    """Continuous-batching server on the 1B-triple serving graph resident in
+    HBM: Poisson arrivals at --qps drawn from a pool of --queries queries of
+    the batched mix (1-6 patterns, star/chain, selectivity log-U[1e-6,1e-1]),
+    admitted by estimated result bytes against --budget-gb.  Reports p50/p99
+    latency and sustained queries/s, and checks that sampled requests return
+    the same rows as the same query run alone."""
+    from paper_1807_01409_amd.serve import Request, Server
+    from synth import CONFIGS, make_graph
+    from synth.batch import PredIndex, batch_queries, poisson_arrivals
+
+    spec = CONFIGS["serving"] if args.n is None else CONFIGS["serving"].with_n(args.n)
+    t0 = time.time()
+    g = make_graph(spec)
+    log(f"generated {spec.n} triples in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    idx = PredIndex(g)
+    log(f"index in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    plans, infos = batch_queries(idx, nq=args.queries, seed=spec.seed)
+    del idx
+    log(f"{len(plans)} queries in {time.time() - t0:.1f}s")
+    n_req = int(args.qps * args.duration)
+    arrivals = poisson_arrivals(n_req, args.qps, spec.seed)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([spec.seed, 0x5E7F])))
+    pick = rng.integers(0, len(plans), size=n_req)
+    reqs = [Request(i, plans[int(pick[i])], float(arrivals[i])) for i in range(n_req)]
+    srv = Server(g, workers=args.serve_workers, budget_bytes=int(args.budget_gb * (1 << 30)),
+                 max_batch=args.max_batch)
+    log("graph resident; warm-up burst")
+    srv.run([Request(-1 - i, plans[i % len(plans)], 0.0) for i in range(2 * args.max_batch)])
+    check = set(range(0, n_req, max(1, n_req // 64)))
+    st = srv.run(reqs, keep_results=check, warmup_s=args.warmup_s)
+    log(f"served {n_req} requests in {st.wall_s:.2f}s: p50 {st.p50_ms:.2f} ms p99 "
+        f"{st.p99_ms:.2f} ms, {st.qps:.0f} q/s, mean batch {st.mean_batch:.1f}")
+    ctx = srv.ctxs[0]
+    mism = 0
+    for r in reqs:
+        if r.rid in check:
+            t = ctx.query(srv.graph, r.plan)
+            if not np.array_equal(t.to_numpy(), r.result):
+                mism += 1
+            t.free()
+    rows = np.array([i["rows"] for i in infos])
+    out = {
+        "metric": "serving p50/p99 latency and sustained queries/s",
+        "value": st.qps, "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": st.wall_s * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
+        "config": {"workload": f"serving graph {spec.n} triples resident in HBM; Poisson "
+                               f"arrivals at {args.qps:g} q/s for {args.duration:g}s from a pool "
+                               f"of {len(plans)} batched-mix queries; result budget "
+                               f"{args.budget_gb:g} GiB",
+                   "n_triples": spec.n, "requests": n_req, "offered_qps": args.qps,
+                   "workers": args.serve_workers, "max_batch": args.max_batch,
+                   "warmup_s": args.warmup_s,
+                   "pool_rows_quantiles": [int(x) for x in np.quantile(rows, [0.5, 0.9, 0.99, 1.0])]},
+        "completed_after_warmup": st.completed, "mean_batch": st.mean_batch,
+        "max_queue": st.max_queue, "max_inflight_bytes": st.max_inflight_bytes,
+        "mix_equals_alone_checked": len(check), "mix_equals_alone_mismatches": mism,
+    }
+    print(json.dumps(out), flush=True)
+    srv.close()
+
+
 def scan_profile(args):
     """Short run for rocprofv3 counter collection: each of the benchmark's
     four single-pattern scans `--steps` times, then a plain device copy of a
@@ -226,15 +292,24 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=None, help="override graph size (testing)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["medium", "batched", "scan-profile"],
+    ap.add_argument("--workload", choices=["medium", "batched", "serving", "scan-profile"],
                     default="medium")
     ap.add_argument("--queries", type=int, default=1024)
+    ap.add_argument("--qps", type=float, default=2000.0, help="serving: offered load")
+    ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")
+    ap.add_argument("--warmup-s", type=float, default=1.0, help="serving: arrivals not measured")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: result budget")
+    ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--max-batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "batched":
         batched(args)
+        return
+    if args.workload == "serving":
+        serving(args)
         return
     if args.workload == "scan-profile":
         scan_profile(args)

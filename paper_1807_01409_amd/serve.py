@@ -77,7 +77,7 @@ class Server:
             try:
                 tabs = ctx.query_batch(self.graph, [r.plan for r in batch])
                 for r, t in zip(batch, tabs):
-                    if self._keep:
+                    if self._keep is True or (self._keep and r.rid in self._keep):
                         r.result = t.to_numpy()
                         r.rows = r.result.shape[0]
                     else:
@@ -101,10 +101,12 @@ class Server:
             c.close()
 
     # -- dispatcher ----------------------------------------------------------
-    def run(self, requests: Sequence[Request], keep_results: bool = False,
+    def run(self, requests: Sequence[Request], keep_results=False,
             warmup_s: float = 0.0) -> ServeStats:
         """Serve `requests` (sorted by arrival) in real time; returns latency
-        and throughput over the requests arriving after `warmup_s`."""
+        and throughput over the requests arriving after `warmup_s`.
+        keep_results: True keeps every result on the host (Request.result), a
+        set of request ids keeps those only, False keeps row counts alone."""
         ctx0 = self.ctxs[0]
         for r in requests:
             r.est_bytes = ctx0.plan_estimate(self.graph, r.plan)

@@ -11,11 +11,13 @@ exceed `max_rows` rows is drawn again.  Sizes are counted from a
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass
 from typing import Dict, List, Tuple
 
 import numpy as np
 
+from .graph import _gpu_initialised
 from .plan import Pattern, Plan
 
 
@@ -23,16 +25,24 @@ class PredIndex:
     """Triples ordered by (predicate, subject); per predicate the slice bounds."""
 
     def __init__(self, g: np.ndarray):
-        key = (g[:, 1].astype(np.uint64) << np.uint64(32)) | g[:, 0].astype(np.uint64)
+        # Bucket by predicate (a radix argsort when IDs fit 16 bits), then
+        # sort each bucket's packed (subject, object) words in place: within
+        # a predicate the order is (s, o), which is a (p, s) order.
+        self.n = g.shape[0]
+        pcol = g[:, 1]
+        hist = np.bincount(pcol)
+        self.start = np.concatenate([[0], np.cumsum(hist)]).astype(np.int64)
+        key = pcol.astype(np.uint16) if hist.size <= 1 << 16 else pcol
         order = np.argsort(key, kind="stable")
         del key
-        self.s = g[order, 0]
-        self.o = g[order, 2]
-        p = g[order, 1]
+        packed = g[order, 0].astype(np.uint64) << np.uint64(32)
+        packed |= g[order, 2]
         del order
-        self.n = g.shape[0]
-        hist = np.bincount(p)
-        self.start = np.concatenate([[0], np.cumsum(hist)]).astype(np.int64)
+        for p in np.nonzero(hist > 1)[0]:
+            packed[self.start[p]:self.start[p + 1]].sort()
+        self.s = (packed >> np.uint64(32)).astype(np.uint32)
+        self.o = packed.astype(np.uint32)
+        del packed
         self.share = hist / self.n
         self.preds = np.nonzero(hist)[0]
         self._obj_counts: Dict[int, Tuple[np.ndarray, np.ndarray]] = {}
@@ -178,30 +188,60 @@ def _plan(shape: str, terms: List[Term]) -> Plan:
     return plan
 
 
+def _one_query(idx: PredIndex, q: int, seed: int, lo: float, hi: float, max_rows: int,
+               max_patterns: int) -> Tuple[Plan, Dict]:
+    """Query q of the mix, drawn from its own seeded stream (so queries can be
+    drawn in any order or process and come out the same)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0xBA7C, q])))
+    for attempt in range(1000):
+        k = int(rng.integers(1, max_patterns + 1))
+        shape = "star" if rng.random() < 0.5 else "chain"
+        sig = 10.0 ** rng.uniform(lo, hi, size=k)
+        terms = [_realise(idx, float(s), rng, shape == "star" or i == k - 1)
+                 for i, s in enumerate(sig)]
+        if shape == "star":
+            pref = _star_prefix_counts(idx, terms)
+        else:
+            pref = _chain_prefix_counts(idx, terms, max_rows)
+        pat_rows = [float(idx.start[t.p + 1] - idx.start[t.p]) for t in terms]
+        if max(pref) <= max_rows:
+            break
+    info = {"shape": shape, "k": k, "sigma": [float(s) for s in sig],
+            "rows": int(pref[-1]), "prefix_rows": [int(x) for x in pref],
+            "pattern_rows_max": int(max(pat_rows)), "attempts": attempt + 1}
+    return _plan(shape, terms), info
+
+
+_POOL_IDX = None   # the index forked workers read (copy-on-write)
+
+
+def _pool_query(args):
+    return _one_query(_POOL_IDX, *args)
+
+
 def batch_queries(idx: PredIndex, nq: int = 1024, seed: int = 4, max_rows: int = 1 << 22,
-                  sigma_range=(1e-6, 1e-1), max_patterns: int = 6) -> Tuple[List[Plan], List[Dict]]:
-    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0xBA7C])))
+                  sigma_range=(1e-6, 1e-1), max_patterns: int = 6,
+                  workers: int | None = None) -> Tuple[List[Plan], List[Dict]]:
+    """nq queries of the mix.  Large mixes are drawn by forked workers unless
+    this process has initialised a GPU (then serially); the result does not
+    depend on the number of workers."""
+    global _POOL_IDX
     lo, hi = np.log10(sigma_range[0]), np.log10(sigma_range[1])
-    plans, infos = [], []
-    for q in range(nq):
-        for attempt in range(1000):
-            k = int(rng.integers(1, max_patterns + 1))
-            shape = "star" if rng.random() < 0.5 else "chain"
-            sig = 10.0 ** rng.uniform(lo, hi, size=k)
-            terms = [_realise(idx, float(s), rng, shape == "star" or i == k - 1)
-                     for i, s in enumerate(sig)]
-            if shape == "star":
-                pref = _star_prefix_counts(idx, terms)
-            else:
-                pref = _chain_prefix_counts(idx, terms, max_rows)
-            pat_rows = [float(idx.start[t.p + 1] - idx.start[t.p]) for t in terms]
-            if max(pref) <= max_rows:
-                break
-        plans.append(_plan(shape, terms))
-        infos.append({"shape": shape, "k": k, "sigma": [float(s) for s in sig],
-                      "rows": int(pref[-1]), "prefix_rows": [int(x) for x in pref],
-                      "pattern_rows_max": int(max(pat_rows)), "attempts": attempt + 1})
-    return plans, infos
+    jobs = [(q, seed, lo, hi, max_rows, max_patterns) for q in range(nq)]
+    if workers is None:
+        workers = min(16, os.cpu_count() or 1)
+    if workers <= 1 or nq < 64 or _gpu_initialised():
+        res = [_one_query(idx, *j) for j in jobs]
+    else:
+        from concurrent.futures import ProcessPoolExecutor
+        from multiprocessing import get_context
+        _POOL_IDX = idx
+        try:
+            with ProcessPoolExecutor(max_workers=workers, mp_context=get_context("fork")) as ex:
+                res = list(ex.map(_pool_query, jobs, chunksize=4))
+        finally:
+            _POOL_IDX = None
+    return [r[0] for r in res], [r[1] for r in res]
 
 
 def poisson_arrivals(n: int, qps: float, seed: int) -> np.ndarray:
