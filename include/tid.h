@@ -83,6 +83,14 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
      "multi_kernel"       multi-pattern pass: 0 auto, 1 LDS pattern loop,
                           2 unrolled (up to 8 patterns)   (autotuner)
      "multi_shape"        launch shape index 0..3 of that kernel (autotuner)
+     "compact_kernel"     0: chunked compaction (workgroups take chunks of
+                          the input from a ticket and place each chunk one
+                          chunk later); 1: block-ranged (one fixed range per
+                          workgroup, placed after all ranges are counted)
+     "chunk_epoch"        stamp of the last chunked launch; the next launch
+                          uses stamp + 1 and, past 2^23 - 1, clears the
+                          context's count slots and restarts at 1 (settable
+                          so that tests can reach the wrap)
      "wide_min"           a plan batch with at least this many patterns of
                           constant predicate uses the bucketed wide pass
                           (0 = default 32) */

@@ -89,6 +89,7 @@ void tid_ctx_destroy(tid_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->lb_state) ctx->free(ctx->lb_state, ctx->lb_bytes);
+    if (ctx->ep_state) ctx->free(ctx->ep_state, ctx->ep_bytes);
     if (ctx->d_flags) ctx->free(ctx->d_flags, 2 * sizeof(uint32_t));
     if (ctx->rw_dev) ctx->free(ctx->rw_dev, ctx->rw_cap * 16);
     if (ctx->rw_host_ptrs) (void)hipHostFree(ctx->rw_host_ptrs);
@@ -127,6 +128,13 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
         } else if (k == "multi_shape") {
             TID_REQUIRE(value >= 0 && value <= 3, TID_E_INVALID_ARG, "multi_shape is 0..3");
             ctx->opt.multi_shape = value;
+        } else if (k == "chunk_epoch") {
+            TID_REQUIRE(value >= 0 && value <= (int64_t)tid::kEpochMax, TID_E_INVALID_ARG,
+                        "chunk_epoch is 0..2^23-1");
+            ctx->epoch = (uint32_t)value;
+        } else if (k == "compact_kernel") {
+            TID_REQUIRE(value == 0 || value == 1, TID_E_INVALID_ARG, "compact_kernel is 0 or 1");
+            ctx->opt.compact_kernel = value;
         } else if (k == "scan_prefetch") {
             ctx->opt.scan_prefetch = value < 0 ? -1 : (value ? 1 : 0);
         } else if (k == "wide_min") {
@@ -156,6 +164,8 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "scan_prefetch") *value = ctx->opt.scan_prefetch;
         else if (k == "multi_kernel") *value = ctx->opt.multi_kernel;
         else if (k == "multi_shape") *value = ctx->opt.multi_shape;
+        else if (k == "compact_kernel") *value = ctx->opt.compact_kernel;
+        else if (k == "chunk_epoch") *value = ctx->epoch;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });
 }

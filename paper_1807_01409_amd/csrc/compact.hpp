@@ -41,14 +41,22 @@ template <int MAXK, int MAXC>
 struct CompactArgs {
     OutDesc<MAXC> out[MAXK];
     int32_t k;
-    uint32_t P;       // number of ranges (= workgroups)
-    uint64_t range;   // items per range, a multiple of the tile
+    uint32_t P;          // number of ranges (= workgroups)
+    uint64_t range;      // block-ranged kernel: items per range, a multiple of the tile
+    // chunked kernel: chunk t < q_big holds big_tiles tiles, later chunks one
+    // tile; q chunks in all; two staging buffers of buf_words LDS words
+    uint64_t q_big, q;
+    uint32_t big_tiles;
+    uint32_t buf_words;
+    uint32_t epoch;      // stamp of this launch's count slots
 };
 
 constexpr uint64_t kNoTile = ~0ull;
 constexpr uint64_t kPublished = 1ull << 63;
 constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kPrefixPer = 8;  // ranges per thread in the prefix read: P <= BLOCK * 8
+constexpr int kEpochShift = 40;                  // count slot: epoch << 40 | rows
+constexpr uint64_t kRowsMask = (1ull << kEpochShift) - 1;
 
 namespace dev {
 
@@ -305,6 +313,296 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
     dev::release_state(sync, (size_t)k * P, counters, P);
 }
 
+
+// ---------------------------------------------------------------------------
+// Chunked compaction with dynamic work distribution.  The input is cut into
+// q chunks (big ones first, single tiles at the end so the tail is short);
+// workgroups take chunks from an atomic ticket, in input order.  A workgroup
+// streams its chunk tile by tile, staging the compacted rows in one of two LDS
+// buffers, publishes the chunk's row count (publishing never waits, so every
+// wait below ends), and then places its PREVIOUS chunk: by that time the chunks before it have been counted by their owners,
+// so the offset (the sum of the counts between the workgroup's frontier and
+// that chunk) is read in one round trip with little or no waiting, and the
+// rows are written while the chunk just streamed waits its turn.  Fast
+// workgroups simply take more chunks, so the kernel ends when the bytes are
+// read, not when the slowest fixed share is.  Rows past a full staging buffer
+// are found again by re-reading the rest of their chunk when it is placed.
+//
+// Chunks are handed out by one counter in increasing order and only to
+// running workgroups, and each workgroup's chunks increase, so a workgroup
+// never waits for a chunk that is not handed out or that a waiting workgroup
+// holds: every wait ends.  Count slots carry the launch's epoch in their upper
+// bits, so they never need clearing; the ticket and done counters are touched
+// only by atomics whose results are consumed, and the last workgroup resets
+// them without a cache write-back.
+// ---------------------------------------------------------------------------
+namespace dev {
+template <class A>
+__device__ __forceinline__ void chunk_bounds(const A &a, uint64_t t, uint64_t n,
+                                             uint64_t tile, uint64_t &c0, uint64_t &c1) {
+    const uint64_t big = tile * a.big_tiles;
+    c0 = t < a.q_big ? t * big : a.q_big * big + (t - a.q_big) * tile;
+    c1 = min(n, c0 + (t < a.q_big ? big : tile));
+}
+}  // namespace dev
+
+template <class Src, int BLOCK, int IPT, int MAXK, int MAXC>
+__global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactArgs<MAXK, MAXC> a,
+                                                               uint64_t *slots, uint32_t *counters,
+                                                               uint32_t *flags) {
+    constexpr int NW = BLOCK / dev::kWave;
+    constexpr int NV = IPT * NW;
+    constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
+    static_assert(IPT <= 32, "match bits live in one 32-bit word per pattern");
+    extern __shared__ uint32_t stage[];
+    __shared__ uint32_t s_off[MAXK][NV];
+    __shared__ uint32_t s_tot[MAXK];
+    __shared__ uint64_t s_cnt[MAXK], s_stg[MAXK], s_ovf[MAXK];     // chunk being streamed
+    __shared__ uint64_t s_pcnt[MAXK], s_pstg[MAXK], s_povf[MAXK];  // chunk waiting for placement
+    __shared__ uint64_t s_fsum[MAXK];  // rows of all chunks before s_front
+    __shared__ uint64_t s_pre[MAXK], s_run[MAXK];
+    __shared__ uint64_t s_red[MAXK][NW];
+    __shared__ uint64_t s_tk, s_front, s_pend;
+
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const int k = MAXK == 1 ? 1 : a.k;
+    const uint64_t Q = a.q;
+    const uint64_t stamp = (uint64_t)a.epoch << kEpochShift;
+    constexpr uint64_t kNone = ~0ull;
+
+    if (tid == 0) {
+        s_tk = atomicAdd(&counters[0], 1u);
+        s_front = 0;
+        s_pend = kNone;
+    }
+    if (tid < k) s_fsum[tid] = 0;
+    __syncthreads();
+
+    typename Src::Item item[IPT], next[IPT];
+    uint32_t mb[MAXK];
+
+    // Count slots of output 0 in the first window between the frontier and
+    // the pending chunk, requested before the next tile's loads so that
+    // reading them does not wait for that tile.
+    auto request_slots = [&](uint64_t *w) {
+        const uint64_t p = s_pend, f = s_front;
+#pragma unroll
+        for (int u = 0; u < kPrefixPer; ++u) {
+            const uint64_t i = f + tid + (uint64_t)u * BLOCK;
+            w[u] = i < p ? dev::peek(&slots[i]) : stamp;
+        }
+    };
+    // Place the pending chunk (staged in buffer `pb`): offset from the count
+    // slots, staged rows out, overflow re-read, frontier advanced.
+    auto place = [&](const uint32_t *pb, const uint64_t *w0) {
+        const uint64_t p = s_pend, f = s_front;
+        uint64_t c0, c1;
+        dev::chunk_bounds(a, p, src.n, TILE, c0, c1);
+        for (int j = 0; j < k; ++j) {
+            uint64_t part = 0;
+            for (uint64_t base = f; base < p; base += (uint64_t)BLOCK * kPrefixPer) {
+                uint64_t w[kPrefixPer];
+#pragma unroll
+                for (int u = 0; u < kPrefixPer; ++u) {
+                    const uint64_t i = base + tid + (uint64_t)u * BLOCK;
+                    w[u] = j == 0 && base == f ? w0[u]
+                                               : (i < p ? dev::peek(&slots[(size_t)j * Q + i]) : stamp);
+                }
+#pragma unroll
+                for (int u = 0; u < kPrefixPer; ++u) {
+                    const uint64_t i = base + tid + (uint64_t)u * BLOCK;
+                    uint32_t spins = 0;
+                    while ((w[u] >> kEpochShift) != a.epoch) {
+                        if (++spins > kSpinLimit) {
+                            atomicOr(&flags[0], 1u);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(2);
+                        w[u] = dev::peek(&slots[(size_t)j * Q + i]);
+                    }
+                    part += w[u] & kRowsMask;
+                }
+            }
+            part = dev::wave_sum(part);
+            if (lane == 0) s_red[j][wave] = part;
+        }
+        __syncthreads();
+        if (tid < k) {
+            uint64_t s = s_fsum[tid];
+            for (int w = 0; w < NW; ++w) s += s_red[tid][w];
+            s_pre[tid] = s;
+            s_run[tid] = s_pstg[tid];
+        }
+        __syncthreads();
+        for (int j = 0; j < k; ++j) {
+            const OutDesc<MAXC> &o = a.out[j];
+            if (o.ncols == 0) continue;
+            const uint64_t pre = s_pre[j];
+            const uint32_t stg = (uint32_t)s_pstg[j];
+            for (uint32_t r = tid; r < stg; r += BLOCK) {
+                const uint64_t dst = pre + r;
+                if (dst < o.cap) {
+                    for (int c = 0; c < o.ncols; ++c)
+                        o.col[c][dst] = pb[o.stage_off + (uint32_t)c * o.stage_cap + r];
+                } else {
+                    atomicOr(&flags[1], 1u);
+                }
+            }
+        }
+        uint64_t first = kNoTile;
+        for (int j = 0; j < k; ++j) first = min(first, s_povf[j]);
+        for (uint64_t t0 = first; t0 < c1; t0 += TILE) {
+            dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, c1, item, mb, s_off);
+            __syncthreads();
+            for (int j = wave; j < k; j += NW) {
+                const uint32_t tot = dev::offsets_in_place<NV>(s_off[j]);
+                if (lane == 0) s_tot[j] = tot;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < MAXK; ++j) {
+                if (j >= k) break;
+                if (s_povf[j] > t0) continue;
+                const OutDesc<MAXC> &o = a.out[j];
+                const uint64_t base = s_pre[j] + s_run[j];
+#pragma unroll
+                for (int it = 0; it < IPT; ++it) {
+                    const bool bit = (mb[j] >> it) & 1u;
+                    const uint64_t b = dev::ballot(bit);
+                    if (bit) {
+                        const uint64_t dst =
+                            base + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
+                        const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
+                        if (dst < o.cap) {
+                            for (int c = 0; c < o.ncols; ++c)
+                                o.col[c][dst] = src.value(j, c, item[it], i);
+                        } else {
+                            atomicOr(&flags[1], 1u);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < k && s_povf[tid] <= t0) s_run[tid] += s_tot[tid];
+        }
+        if (tid < k) {
+            s_fsum[tid] = s_pre[tid] + s_pcnt[tid];
+            if (p == Q - 1) *a.out[tid].count = s_pre[tid] + s_pcnt[tid];
+        }
+        if (tid == 0) s_front = p + 1;
+        __syncthreads();
+    };
+
+    // The next chunk's ticket is taken while the last tile of the current one
+    // is tested (its result is not waited for until the tile is done), and its
+    // first tile is loaded before the previous chunk is placed, so the
+    // placement round trip overlaps loads in flight.
+    int buf = 0;
+    uint32_t ticket = 0;
+    if (s_tk < Q) {
+        uint64_t c0, c1;
+        dev::chunk_bounds(a, s_tk, src.n, TILE, c0, c1);
+        dev::tile_load<Src, BLOCK, IPT>(src, c0, c1, next);
+    }
+    for (;;) {
+        const uint64_t t = s_tk;
+        if (t >= Q) break;
+        uint64_t c0, c1;
+        dev::chunk_bounds(a, t, src.n, TILE, c0, c1);
+        uint32_t *st = stage + (uint32_t)buf * a.buf_words;
+        if (tid < k) {
+            s_cnt[tid] = 0;
+            s_stg[tid] = 0;
+            s_ovf[tid] = kNoTile;
+        }
+        __syncthreads();
+        for (uint64_t t0 = c0; t0 < c1; t0 += TILE) {
+#pragma unroll
+            for (int it = 0; it < IPT; ++it) item[it] = next[it];
+            if (t0 + TILE < c1)
+                dev::tile_load<Src, BLOCK, IPT>(src, t0 + TILE, c1, next);
+            else if (tid == 0)
+                ticket = atomicAdd(&counters[0], 1u);  // result first used after the loop
+            dev::tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, c1, item, mb, s_off);
+            __syncthreads();
+            for (int j = wave; j < k; j += NW) {
+                const uint32_t tot = dev::offsets_in_place<NV>(s_off[j]);
+                if (lane == 0) s_tot[j] = tot;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < MAXK; ++j) {
+                if (j >= k) break;
+                const OutDesc<MAXC> &o = a.out[j];
+                const uint64_t cnt = s_cnt[j];
+                if (s_ovf[j] != kNoTile || cnt + s_tot[j] > o.stage_cap) continue;
+#pragma unroll
+                for (int it = 0; it < IPT; ++it) {
+                    const bool bit = (mb[j] >> it) & 1u;
+                    const uint64_t b = dev::ballot(bit);
+                    if (bit) {
+                        const uint32_t r =
+                            (uint32_t)cnt + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
+                        const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
+                        for (int c = 0; c < o.ncols; ++c)
+                            st[o.stage_off + (uint32_t)c * o.stage_cap + r] =
+                                src.value(j, c, item[it], i);
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < k) {
+                if (s_ovf[tid] == kNoTile && s_cnt[tid] + s_tot[tid] > a.out[tid].stage_cap) {
+                    s_ovf[tid] = t0;
+                    s_stg[tid] = s_cnt[tid];
+                }
+                s_cnt[tid] += s_tot[tid];
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_tk = ticket;
+        if (tid < k) {
+            if (s_ovf[tid] == kNoTile) s_stg[tid] = s_cnt[tid];
+            dev::publish(&slots[(size_t)tid * Q + t], stamp | s_cnt[tid]);
+        }
+        __syncthreads();
+        const bool pending = s_pend != kNone;
+        uint64_t w0[kPrefixPer];
+        if (pending) request_slots(w0);
+        const uint64_t tn = s_tk;  // next chunk (taken during the last tile)
+        if (tn < Q) {
+            uint64_t n0, n1;
+            dev::chunk_bounds(a, tn, src.n, TILE, n0, n1);
+            dev::tile_load<Src, BLOCK, IPT>(src, n0, n1, next);
+        }
+        if (pending) place(stage + (uint32_t)(buf ^ 1) * a.buf_words, w0);
+        if (tid < k) {
+            s_pcnt[tid] = s_cnt[tid];
+            s_pstg[tid] = s_stg[tid];
+            s_povf[tid] = s_ovf[tid];
+        }
+        if (tid == 0) s_pend = t;
+        buf ^= 1;
+        __syncthreads();
+    }
+    if (s_pend != kNone) {
+        uint64_t w0[kPrefixPer];
+        request_slots(w0);
+        place(stage + (uint32_t)(buf ^ 1) * a.buf_words, w0);
+    }
+
+    // the last workgroup out resets the ticket and done counters
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t d = __hip_atomic_fetch_add(&counters[1], 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (d == gridDim.x - 1) {
+            __hip_atomic_store(&counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
@@ -314,13 +612,70 @@ int device_cus(tid_ctx *ctx);
 // CU; cached per (kernel, lds) and safe to call from several host threads.
 int resident_blocks(const void *kernel, int block, size_t lds);
 
+constexpr uint32_t kMaxBigTiles = 4;  // tiles per chunk before the single-tile tail
+
+template <class Src, int BLOCK, int IPT, int MAXK, int MAXC>
+void launch_chunked(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, int k,
+                    uint32_t stage_words) {
+    constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
+    auto kern = chunk_compact_kernel<Src, BLOCK, IPT, MAXK, MAXC>;
+    const size_t lds = (size_t)stage_words * sizeof(uint32_t);
+    const int blocks_per_cu = resident_blocks((const void *)kern, BLOCK, lds);
+    const uint64_t n = src.n;
+    if (n == 0) return;
+    uint64_t cols_total = 0;
+    for (int j = 0; j < k; ++j) cols_total += (uint64_t)a.out[j].ncols;
+    a.buf_words = stage_words / 2;
+    const uint32_t rows_per = (uint32_t)(a.buf_words / std::max<uint64_t>(cols_total, 1));
+    uint32_t off = 0;
+    for (int j = 0; j < k; ++j) {
+        a.out[j].stage_off = off;
+        a.out[j].stage_cap = a.out[j].ncols ? rows_per : 0xFFFFFFFFu;
+        off += rows_per * (uint32_t)a.out[j].ncols;
+    }
+    const uint64_t resident = (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx);
+    const uint64_t tiles = (n + TILE - 1) / TILE;
+    const uint64_t tail = std::min<uint64_t>(tiles, 2 * resident);
+    // Big chunks as long as the rows the output bounds allow per chunk fit
+    // 80% of a staging buffer: fewer placements for sparse outputs, no
+    // overflow re-reads for dense ones.
+    uint64_t big = kMaxBigTiles;
+    for (int j = 0; j < k; ++j) {
+        const OutDesc<MAXC> &o = a.out[j];
+        if (o.ncols == 0 || o.cap == 0) continue;
+        const double rows_per_tile = (double)std::min<uint64_t>(o.cap, n) * TILE / (double)n;
+        big = std::min<uint64_t>(big, (uint64_t)(0.8 * o.stage_cap / rows_per_tile));
+    }
+    big = std::max<uint64_t>(big, 1);
+    a.big_tiles = (uint32_t)big;
+    a.q_big = (tiles - tail) / big;
+    a.q = a.q_big + (tiles - a.q_big * big);
+    TID_REQUIRE(a.q + resident < (1ull << 32), TID_E_UNSUPPORTED, "compaction: input too large");
+    a.k = k;
+    const uint64_t P = std::max<uint64_t>(1, std::min<uint64_t>(resident, a.q));
+    a.P = (uint32_t)P;
+    // state: the ticket and done counters (one u64 word), then k * q count slots
+    constexpr size_t kCounterWords = 1;
+    uint64_t *state = nullptr;
+    a.epoch = ctx->next_epoch(((size_t)k * a.q + kCounterWords) * sizeof(uint64_t), &state);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)P), dim3(BLOCK), lds, ctx->stream, src, a,
+                       state + kCounterWords, reinterpret_cast<uint32_t *>(state), ctx->d_flags);
+    TID_HIP(hipGetLastError());
+}
+
 // Launch the compaction of `n` items over the resident-capacity grid.  The
 // caller fills a.out[0..k) (columns, caps, counts, ncols); staging areas are
-// laid out here over `stage_words` words of LDS.
+// laid out here over `stage_words` words of LDS.  The context's
+// compact_kernel option picks the kernel: 0 chunked (default), 1
+// block-ranged (PREFETCH picks its prefetching variant).
 template <class Src, int BLOCK, int IPT, int MAXK, int MAXC, bool PREFETCH = false>
 void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, int k,
                     uint32_t stage_words) {
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
+    if (ctx->opt.compact_kernel == 0) {
+        launch_chunked<Src, BLOCK, IPT, MAXK, MAXC>(ctx, src, a, k, stage_words);
+        return;
+    }
     auto kern = compact_kernel<Src, BLOCK, IPT, MAXK, MAXC, PREFETCH>;
     const size_t lds = (size_t)stage_words * sizeof(uint32_t);
     const int blocks_per_cu = resident_blocks((const void *)kern, BLOCK, lds);
@@ -344,8 +699,8 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
     a.k = k;
     a.P = (uint32_t)P;
     a.range = range;
-    uint64_t *sync =
-        static_cast<uint64_t *>(ctx->lookback_state(((size_t)k * P + 1) * sizeof(uint64_t)));
+    uint64_t *sync = static_cast<uint64_t *>(
+        ctx->lookback_state(((size_t)k * P + 1) * sizeof(uint64_t)));
     hipLaunchKernelGGL(kern, dim3((uint32_t)P), dim3(BLOCK), lds, ctx->stream, src, a, sync,
                        ctx->d_flags);
     TID_HIP(hipGetLastError());

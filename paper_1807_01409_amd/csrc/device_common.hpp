@@ -55,10 +55,11 @@ __device__ __forceinline__ uint64_t peek(const uint64_t *word) {
 // End of a kernel that uses sync words, called by every thread of every
 // workgroup.  The sync words are all zero when a kernel starts: the workgroup
 // that finishes last (counted on counters[1]) clears the `nwords` words and
-// both counters for the next launch.  Every other workgroup has made its last state access
+// the `ncounters` counter words for the next launch.  Every other workgroup has made its last state access
 // before its increment of done.
 __device__ __forceinline__ void release_state(uint64_t *state, size_t nwords,
-                                              uint32_t *counters, uint32_t num_tiles) {
+                                              uint32_t *counters, uint32_t num_tiles,
+                                              int ncounters = 2) {
     __shared__ int s_last;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -71,10 +72,7 @@ __device__ __forceinline__ void release_state(uint64_t *state, size_t nwords,
     if (s_last) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         for (size_t i = threadIdx.x; i < nwords; i += blockDim.x) state[i] = 0;
-        if (threadIdx.x == 0) {
-            counters[0] = 0;
-            counters[1] = 0;
-        }
+        for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0;
     }
 }
 

@@ -61,6 +61,7 @@ struct Options {
     int64_t scan_prefetch = -1;  // -1 built-in default, 0 off, 1 prefetch the next tile
     int64_t multi_kernel = 0;    // 0 auto, 1 LDS pattern loop, 2 unrolled (<= 8 patterns)
     int64_t multi_shape = 0;     // launch shape index of the chosen multi-pattern kernel
+    int64_t compact_kernel = 0;  // 0 chunked, 1 block-ranged compaction
 };
 
 }  // namespace tid
@@ -79,6 +80,11 @@ struct tid_ctx {
     // scratch for look-back state: grown on demand, owned by the context
     void *lb_state = nullptr;
     size_t lb_bytes = 0;
+    // epoch-stamped count slots of the chunked compaction (two counter words
+    // first); zeroed when grown and when the epoch wraps
+    void *ep_state = nullptr;
+    size_t ep_bytes = 0;
+    uint32_t epoch = 0;
     uint32_t *d_flags = nullptr;      // device error/overflow flags (2 words)
     // staging for read_words: pinned pointer list and values, device copies
     const uint64_t **rw_host_ptrs = nullptr;
@@ -89,6 +95,8 @@ struct tid_ctx {
     void *alloc(size_t bytes);
     void free(void *p, size_t bytes);
     void *lookback_state(size_t bytes);  // all zero between kernels
+    // stamp for the next chunked launch; *state gets the slot area of `bytes`
+    uint32_t next_epoch(size_t bytes, uint64_t **state);
     void sync();
 };
 
@@ -135,6 +143,8 @@ class DevBuf {
 };
 
 constexpr size_t kAlign = 256;
+// Chunked-compaction launch stamps run 1..kEpochMax; then the slots are zeroed.
+constexpr uint32_t kEpochMax = (1u << 23) - 1;
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 
 }  // namespace tid

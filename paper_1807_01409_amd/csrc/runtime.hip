@@ -310,6 +310,26 @@ void *tid_ctx::lookback_state(size_t bytes) {
     return lb_state;
 }
 
+uint32_t tid_ctx::next_epoch(size_t bytes, uint64_t **state) {
+    bool zero = false;
+    if (ep_bytes < bytes) {
+        const size_t want = tid::align_up(std::max(bytes, ep_bytes + ep_bytes / 2), 1 << 16);
+        if (ep_state) free(ep_state, ep_bytes);
+        ep_state = nullptr;
+        ep_bytes = 0;
+        ep_state = alloc(want);
+        ep_bytes = want;
+        zero = true;
+    }
+    if (++epoch > tid::kEpochMax) {
+        epoch = 1;
+        zero = true;
+    }
+    if (zero) TID_HIP(hipMemsetAsync(ep_state, 0, ep_bytes, stream));
+    *state = static_cast<uint64_t *>(ep_state);
+    return epoch;
+}
+
 void tid_ctx::sync() { TID_HIP(hipStreamSynchronize(stream)); }
 
 uint64_t tid_graph::count_in(int pos, uint64_t lo, uint64_t hi) const {

@@ -207,3 +207,44 @@ def test_autotune_shapes_agree(ctx, graphs, tmp_path, monkeypatch):
     assert entry is not None and entry["options"] == res["options"]
     for k in autotune.KEYS:
         ctx.set_option(k, -1 if k == "scan_prefetch" else 0)
+
+
+def _clustered(g):
+    """The same triples ordered by predicate: a predicate's matches are then
+    contiguous, so whole chunks match and staging areas overflow."""
+    return g[np.argsort(g[:, 1], kind="stable")]
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_compact_kernels_big_chunks(ctx, graphs, kernel):
+    """Both compaction kernels on 6M triples (big chunks, a single-tile tail,
+    many workgroups), at sparse and dense selectivities, on the graph in
+    generation order and ordered by predicate."""
+    from synth.queries import predicate_for_selectivity
+    g0 = graphs("medium", 6_000_000)
+    ctx.set_option("compact_kernel", kernel)
+    try:
+        for g in (g0, _clustered(g0)):
+            G = ctx.load(g)
+            pats = [Pattern(0, predicate_for_selectivity(g, s)[0], 0, 0, -1, 1)
+                    for s in (1e-4, 1e-2, 0.1, 0.3)]
+            pats.append(Pattern(0, 0, 0, 0, 1, 2, range_pos=1, lo=1, hi=40))
+            for p in pats:
+                same(ctx.scan(G, p), oracle.scan(g, p))
+            G.free()
+    finally:
+        ctx.set_option("compact_kernel", 0)
+
+
+def test_chunk_epoch_wrap(ctx, graphs):
+    """Launch stamps past the largest epoch restart at 1 after the slots are
+    cleared; results stay exact on both sides of the wrap."""
+    g = graphs("medium", 6_000_000)
+    G = ctx.load(g)
+    p = pat("?s 3 ?o")
+    want = oracle.scan(g, p)
+    top = (1 << 23) - 1
+    ctx.set_option("chunk_epoch", top - 2)
+    for _ in range(5):
+        same(ctx.scan(G, p), want)
+    assert 1 <= ctx.get_option("chunk_epoch") <= 3
