@@ -404,7 +404,9 @@ def main():
                    "star": w["star_info"], "union": w["union_info"], "range": w["range_info"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(khash),
-                     "kernel": "compact_kernel<ScanSrc<1>,512,8,1,3,prefetch> (single-pattern scan)",
+                     "kernel": "single-pattern scan, ScanSrc<1> 512x8: compact_kernel "
+                               "(block-ranged) for sparse outputs, chunk_compact_kernel for "
+                               "dense ones",
                      "per_launch": per_launch},
         "breakdown": breakdown,
         "cpu_baseline": cpu,

@@ -83,10 +83,12 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
      "multi_kernel"       multi-pattern pass: 0 auto, 1 LDS pattern loop,
                           2 unrolled (up to 8 patterns)   (autotuner)
      "multi_shape"        launch shape index 0..3 of that kernel (autotuner)
-     "compact_kernel"     0: chunked compaction (workgroups take chunks of
-                          the input from a ticket and place each chunk one
-                          chunk later); 1: block-ranged (one fixed range per
-                          workgroup, placed after all ranges are counted)
+     "compact_kernel"     1: block-ranged compaction (one fixed range per
+                          workgroup, placed after all ranges are counted);
+                          2: chunked (workgroups take chunks of the input
+                          from a ticket and place each chunk one chunk
+                          later); 0 (default): block-ranged when the output
+                          bound per range is small, chunked otherwise
      "chunk_epoch"        stamp of the last chunked launch; the next launch
                           uses stamp + 1 and, past 2^23 - 1, clears the
                           context's count slots and restarts at 1 (settable

@@ -133,7 +133,7 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
                         "chunk_epoch is 0..2^23-1");
             ctx->epoch = (uint32_t)value;
         } else if (k == "compact_kernel") {
-            TID_REQUIRE(value == 0 || value == 1, TID_E_INVALID_ARG, "compact_kernel is 0 or 1");
+            TID_REQUIRE(value >= 0 && value <= 2, TID_E_INVALID_ARG, "compact_kernel is 0, 1 or 2");
             ctx->opt.compact_kernel = value;
         } else if (k == "scan_prefetch") {
             ctx->opt.scan_prefetch = value < 0 ? -1 : (value ? 1 : 0);

@@ -666,16 +666,15 @@ void launch_chunked(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
 // Launch the compaction of `n` items over the resident-capacity grid.  The
 // caller fills a.out[0..k) (columns, caps, counts, ncols); staging areas are
 // laid out here over `stage_words` words of LDS.  The context's
-// compact_kernel option picks the kernel: 0 chunked (default), 1
-// block-ranged (PREFETCH picks its prefetching variant).
+// compact_kernel option picks the kernel: 1 block-ranged (PREFETCH picks its
+// prefetching variant), 2 chunked, 0 (default) block-ranged when every
+// output's row bound per range is under an eighth of its staging area (its
+// writes at the end are then short, and it has no per-chunk placement), else
+// chunked.
 template <class Src, int BLOCK, int IPT, int MAXK, int MAXC, bool PREFETCH = false>
 void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, int k,
                     uint32_t stage_words) {
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
-    if (ctx->opt.compact_kernel == 0) {
-        launch_chunked<Src, BLOCK, IPT, MAXK, MAXC>(ctx, src, a, k, stage_words);
-        return;
-    }
     auto kern = compact_kernel<Src, BLOCK, IPT, MAXK, MAXC, PREFETCH>;
     const size_t lds = (size_t)stage_words * sizeof(uint32_t);
     const int blocks_per_cu = resident_blocks((const void *)kern, BLOCK, lds);
@@ -684,6 +683,20 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
     uint64_t cols_total = 0;
     for (int j = 0; j < k; ++j) cols_total += (uint64_t)a.out[j].ncols;
     const uint32_t rows_per = (uint32_t)(stage_words / std::max<uint64_t>(cols_total, 1));
+    int kind = (int)ctx->opt.compact_kernel;
+    if (kind == 0) {
+        const uint64_t ranges = std::max<uint64_t>(
+            1, std::min<uint64_t>({(n + TILE - 1) / TILE,
+                                   (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx),
+                                   (uint64_t)BLOCK * kPrefixPer}));
+        kind = 1;
+        for (int j = 0; j < k; ++j)
+            if (a.out[j].ncols && a.out[j].cap / ranges > rows_per / 8) kind = 2;
+    }
+    if (kind == 2) {
+        launch_chunked<Src, BLOCK, IPT, MAXK, MAXC>(ctx, src, a, k, stage_words);
+        return;
+    }
     uint32_t off = 0;
     for (int j = 0; j < k; ++j) {
         a.out[j].stage_off = off;
