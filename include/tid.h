@@ -80,8 +80,9 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           0: it does not; -1: built-in default (autotuner)
      "stage_words"        LDS words per workgroup for staging compacted rows
                           (0 = default, at most 16384)
-     "multi_kernel"       multi-pattern pass: 0 auto, 1 LDS pattern loop,
-                          2 unrolled (up to 8 patterns)   (autotuner)
+     "multi_kernel"       multi-pattern scans: 0 passes of at most 4
+                          patterns (unrolled), 1 one pass of up to 16
+                          patterns (LDS pattern loop)      (autotuner)
      "multi_shape"        launch shape index 0..3 of that kernel (autotuner)
      "compact_kernel"     1: block-ranged compaction (one fixed range per
                           workgroup, placed after all ranges are counted);

@@ -123,7 +123,7 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
         } else if (k == "scan_block") {
             ctx->opt.scan_block = value;
         } else if (k == "multi_kernel") {
-            TID_REQUIRE(value >= 0 && value <= 2, TID_E_INVALID_ARG, "multi_kernel is 0, 1 or 2");
+            TID_REQUIRE(value == 0 || value == 1, TID_E_INVALID_ARG, "multi_kernel is 0 or 1");
             ctx->opt.multi_kernel = value;
         } else if (k == "multi_shape") {
             TID_REQUIRE(value >= 0 && value <= 3, TID_E_INVALID_ARG, "multi_shape is 0..3");

@@ -381,50 +381,65 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
     typename Src::Item item[IPT], next[IPT];
     uint32_t mb[MAXK];
 
-    // Count slots of output 0 in the first window between the frontier and
-    // the pending chunk, requested before the next tile's loads so that
-    // reading them does not wait for that tile.
-    auto request_slots = [&](uint64_t *w) {
+    // Count slots are chunk-major (the k counts of chunk i at slots[i*k ..]),
+    // so one round trip fetches every output's counts of a window of
+    // kSlotsPer * BLOCK chunks.  The first window between the frontier and
+    // the pending chunk is requested before the next tile's loads, so that
+    // reading it does not wait for that tile.
+    constexpr int kSlotsPer = MAXK == 1 ? 2 : 1;
+    auto request_slots = [&](uint64_t (*w)[kSlotsPer]) {
         const uint64_t p = s_pend, f = s_front;
 #pragma unroll
-        for (int u = 0; u < kPrefixPer; ++u) {
+        for (int u = 0; u < kSlotsPer; ++u) {
             const uint64_t i = f + tid + (uint64_t)u * BLOCK;
-            w[u] = i < p ? dev::peek(&slots[i]) : stamp;
+#pragma unroll
+            for (int j = 0; j < MAXK; ++j)
+                if (j < k) w[j][u] = i < p ? dev::peek(&slots[i * k + j]) : stamp;
         }
     };
     // Place the pending chunk (staged in buffer `pb`): offset from the count
     // slots, staged rows out, overflow re-read, frontier advanced.
-    auto place = [&](const uint32_t *pb, const uint64_t *w0) {
+    auto place = [&](const uint32_t *pb, uint64_t (*w)[kSlotsPer]) {
         const uint64_t p = s_pend, f = s_front;
         uint64_t c0, c1;
         dev::chunk_bounds(a, p, src.n, TILE, c0, c1);
-        for (int j = 0; j < k; ++j) {
-            uint64_t part = 0;
-            for (uint64_t base = f; base < p; base += (uint64_t)BLOCK * kPrefixPer) {
-                uint64_t w[kPrefixPer];
+        uint64_t part[MAXK];
 #pragma unroll
-                for (int u = 0; u < kPrefixPer; ++u) {
+        for (int j = 0; j < MAXK; ++j) part[j] = 0;
+        for (uint64_t base = f; base < p; base += (uint64_t)BLOCK * kSlotsPer) {
+            if (base != f) {
+#pragma unroll
+                for (int u = 0; u < kSlotsPer; ++u) {
                     const uint64_t i = base + tid + (uint64_t)u * BLOCK;
-                    w[u] = j == 0 && base == f ? w0[u]
-                                               : (i < p ? dev::peek(&slots[(size_t)j * Q + i]) : stamp);
+#pragma unroll
+                    for (int j = 0; j < MAXK; ++j)
+                        if (j < k) w[j][u] = i < p ? dev::peek(&slots[i * k + j]) : stamp;
                 }
+            }
 #pragma unroll
-                for (int u = 0; u < kPrefixPer; ++u) {
-                    const uint64_t i = base + tid + (uint64_t)u * BLOCK;
+            for (int u = 0; u < kSlotsPer; ++u) {
+                const uint64_t i = base + tid + (uint64_t)u * BLOCK;
+#pragma unroll
+                for (int j = 0; j < MAXK; ++j) {
+                    if (j >= k) break;
                     uint32_t spins = 0;
-                    while ((w[u] >> kEpochShift) != a.epoch) {
+                    while ((w[j][u] >> kEpochShift) != a.epoch) {
                         if (++spins > kSpinLimit) {
                             atomicOr(&flags[0], 1u);
                             break;
                         }
                         __builtin_amdgcn_s_sleep(2);
-                        w[u] = dev::peek(&slots[(size_t)j * Q + i]);
+                        w[j][u] = dev::peek(&slots[i * k + j]);
                     }
-                    part += w[u] & kRowsMask;
+                    part[j] += w[j][u] & kRowsMask;
                 }
             }
-            part = dev::wave_sum(part);
-            if (lane == 0) s_red[j][wave] = part;
+        }
+#pragma unroll
+        for (int j = 0; j < MAXK; ++j) {
+            if (j >= k) break;
+            const uint64_t v = dev::wave_sum(part[j]);
+            if (lane == 0) s_red[j][wave] = v;
         }
         __syncthreads();
         if (tid < k) {
@@ -563,11 +578,11 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
         if (tid == 0) s_tk = ticket;
         if (tid < k) {
             if (s_ovf[tid] == kNoTile) s_stg[tid] = s_cnt[tid];
-            dev::publish(&slots[(size_t)tid * Q + t], stamp | s_cnt[tid]);
+            dev::publish(&slots[t * k + tid], stamp | s_cnt[tid]);
         }
         __syncthreads();
         const bool pending = s_pend != kNone;
-        uint64_t w0[kPrefixPer];
+        uint64_t w0[MAXK][kSlotsPer];
         if (pending) request_slots(w0);
         const uint64_t tn = s_tk;  // next chunk (taken during the last tile)
         if (tn < Q) {
@@ -586,7 +601,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
         __syncthreads();
     }
     if (s_pend != kNone) {
-        uint64_t w0[kPrefixPer];
+        uint64_t w0[MAXK][kSlotsPer];
         request_slots(w0);
         place(stage + (uint32_t)(buf ^ 1) * a.buf_words, w0);
     }

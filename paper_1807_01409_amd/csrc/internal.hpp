@@ -59,7 +59,7 @@ struct Options {
     int64_t stage_words = 0;  // LDS staging words per workgroup (0 = default)
     int64_t wide_min = 0;     // patterns needed before wide passes are used (0 = 32)
     int64_t scan_prefetch = -1;  // -1 built-in default, 0 off, 1 prefetch the next tile
-    int64_t multi_kernel = 0;    // 0 auto, 1 LDS pattern loop, 2 unrolled (<= 8 patterns)
+    int64_t multi_kernel = 0;    // 0 passes of <= 4 unrolled patterns, 1 LDS pattern loop
     int64_t multi_shape = 0;     // launch shape index of the chosen multi-pattern kernel
     int64_t compact_kernel = 0;  // 0 auto, 1 block-ranged, 2 chunked compaction
 };

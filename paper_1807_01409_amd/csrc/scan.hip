@@ -484,25 +484,33 @@ static void run_unrolled_shape(tid_ctx *ctx, const tid_graph *g, const tid_patte
         run_unrolled<MAXK, 512, 8>(ctx, g, pats, k, outs);
 }
 
-// multi_kernel option: 1 the LDS pattern-loop kernel, 2 the unrolled kernel
-// (k <= 8); 0 picks the unrolled kernel up to 4 patterns and the loop kernel
-// above that (the 8-pattern unrolled instance spills to scratch and runs 3x
-// slower than the loop).  multi_shape 0 is 512 threads x 8 triples for both.
+// multi_kernel option: 0 (default) the unrolled kernel for up to 4 patterns,
+// and more patterns as several passes of at most 4 (balanced); 1 the LDS
+// pattern-loop kernel (one pass for up to 16).  Per pattern, the loop kernel
+// stages a sixteenth of the LDS and falls back to re-reading the graph once
+// the outputs are dense; four-pattern passes keep the automatic choice
+// between block-ranged and chunked placement, and measure 2.5x faster for
+// eight patterns of ~1% selectivity.  multi_shape 0 is 512 threads x 8
+// triples for both.
 static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                          tid_table *const *outs) {
     if (k == 1) {
         run_scan<1>(ctx, g, pats, k, outs);
         return;
     }
-    const int which = (int)ctx->opt.multi_kernel;
     const int shape = (int)ctx->opt.multi_shape;
-    if ((which == 0 && k <= 4) || (which == 2 && k <= 8)) {
-        if (k == 2)
-            run_unrolled_shape<2>(ctx, g, pats, k, outs, shape);
-        else if (k <= 4)
-            run_unrolled_shape<4>(ctx, g, pats, k, outs, shape);
-        else
-            run_unrolled_shape<8>(ctx, g, pats, k, outs, shape);
+    if (ctx->opt.multi_kernel == 0) {
+        const int passes = (k + 3) / 4;
+        for (int p0 = 0, p = 0; p < passes; ++p) {
+            const int m = (k - p0) / (passes - p);
+            if (m == 1)
+                run_scan<1>(ctx, g, pats + p0, 1, outs + p0);
+            else if (m == 2)
+                run_unrolled_shape<2>(ctx, g, pats + p0, m, outs + p0, shape);
+            else
+                run_unrolled_shape<4>(ctx, g, pats + p0, m, outs + p0, shape);
+            p0 += m;
+        }
         return;
     }
     MultiArgs a{};
