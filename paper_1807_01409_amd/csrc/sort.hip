@@ -7,8 +7,10 @@
 //   hist     each workgroup owns one contiguous range of the input and counts
 //            the digits of its range (wave-private LDS histograms, updated
 //            by the leader lane of each group of lanes holding one digit);
-//   offsets  one workgroup turns the range-major count matrix into, for every
-//            (range, digit), the place where its first element goes;
+//   offsets  one workgroup per digit scans that digit's counts over the
+//            ranges; the scatter kernel adds the bases of the smaller digits
+//            (a scan of the 256 digit totals) to find, for every (range,
+//            digit), the place where its first element goes;
 //   scatter  each workgroup walks its range tile by tile and writes every
 //            element at its digit's running offset plus its stable rank,
 //            found with ballots that group the lanes holding equal digits.
@@ -78,52 +80,62 @@ __global__ __launch_bounds__(kSortBlock) void radix_hist(const uint64_t *__restr
     }
 }
 
-// Where each (range, digit) goes: offs[w][d] = sum of all counts of digits
-// below d, plus the counts of digit d in ranges before w.  One workgroup:
-// thread t takes digit t % 256 over one quarter of the ranges, so every load
-// of the range-major count matrix is coalesced across digits.
-constexpr int kOffThreads = 1024;
-constexpr int kOffParts = kOffThreads / (int)kRadix;
-__global__ __launch_bounds__(kOffThreads) void digit_offsets(const uint32_t *__restrict__ counts,
-                                                              uint32_t *__restrict__ offs,
-                                                              uint32_t P) {
-    __shared__ uint32_t s_part[kOffParts][kRadix];
-    __shared__ uint32_t s_base[kRadix];
-    __shared__ uint32_t s_w[kRadix / dev::kWave];
-    const int tid = threadIdx.x;
-    const uint32_t d = tid % kRadix, q = tid / kRadix;
-    const uint32_t per = (P + kOffParts - 1) / kOffParts;
-    const uint32_t w0 = min(P, q * per), w1 = min(P, w0 + per);
+// Where each (range, digit) goes is offs[w][d] = base[d] + scan[w][d]: base[d]
+// counts every element of a smaller digit, scan[w][d] the elements of digit d
+// in ranges before w.  One workgroup per digit scans its column of the
+// range-major count matrix and writes the digit's total; the scatter kernel
+// turns the 256 totals into bases itself.
+constexpr int kColThreads = 256;
+__global__ __launch_bounds__(kColThreads) void digit_scan(const uint32_t *__restrict__ counts,
+                                                           uint32_t *__restrict__ scan,
+                                                           uint32_t *__restrict__ totals,
+                                                           uint32_t P) {
+    __shared__ uint32_t s_w[kColThreads / dev::kWave];
+    const uint32_t d = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const uint32_t per = (P + kColThreads - 1) / kColThreads;
+    const uint32_t w0 = min(P, (uint32_t)tid * per), w1 = min(P, w0 + per);
     uint32_t sum = 0;
     for (uint32_t w = w0; w < w1; ++w) sum += counts[(size_t)w * kRadix + d];
-    s_part[q][d] = sum;
+    const uint32_t incl = dev::wave_inclusive_sum(sum);
+    if (lane == dev::kWave - 1) s_w[wave] = incl;
     __syncthreads();
-    if (tid < (int)kRadix) {
-        uint32_t tot = 0;
-        for (int x = 0; x < kOffParts; ++x) tot += s_part[x][d];
-        const uint32_t incl = dev::wave_inclusive_sum(tot);
-        if (dev::lane_id() == dev::kWave - 1) s_w[tid / dev::kWave] = incl;
-        s_base[d] = incl - tot;  // exclusive within the wave for now
-    }
-    __syncthreads();
-    uint32_t run = s_base[d];
-    for (uint32_t x = 0; x < d / dev::kWave; ++x) run += s_w[x];
-    for (uint32_t x = 0; x < q; ++x) run += s_part[x][d];
+    uint32_t run = incl - sum;
+    for (int x = 0; x < wave; ++x) run += s_w[x];
     for (uint32_t w = w0; w < w1; ++w) {
         const uint32_t c = counts[(size_t)w * kRadix + d];
-        offs[(size_t)w * kRadix + d] = run;
+        scan[(size_t)w * kRadix + d] = run;
         run += c;
     }
+    if (tid == kColThreads - 1) totals[d] = run;
 }
 
 __global__ __launch_bounds__(kSortBlock) void radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin, uint64_t *__restrict__ kout,
-    uint32_t *__restrict__ vout, uint64_t n, uint64_t range, int shift, const uint32_t *offs) {
+    uint32_t *__restrict__ vout, uint64_t n, uint64_t range, int shift, const uint32_t *scan,
+    const uint32_t *totals) {
+    constexpr int kPer = kRadix / dev::kWave;  // digits per lane in the base scan
     __shared__ uint32_t s_run[kRadix];
     __shared__ uint32_t s_wh[kSortNW][kRadix];
     const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
     const uint32_t w = blockIdx.x;
-    for (uint32_t d = tid; d < kRadix; d += kSortBlock) s_run[d] = offs[(size_t)w * kRadix + d];
+    // digit bases: exclusive scan of the digit totals (wave 0, kPer digits a lane)
+    if (wave == 0) {
+        uint32_t v[kPer], loc = 0;
+#pragma unroll
+        for (int x = 0; x < kPer; ++x) {
+            v[x] = totals[lane * kPer + x];
+            loc += v[x];
+        }
+        uint32_t run = dev::wave_inclusive_sum(loc) - loc;
+#pragma unroll
+        for (int x = 0; x < kPer; ++x) {
+            s_run[lane * kPer + x] = run;
+            run += v[x];
+        }
+    }
+    __syncthreads();
+    for (uint32_t d = tid; d < kRadix; d += kSortBlock) s_run[d] += scan[(size_t)w * kRadix + d];
     const uint64_t r0 = (uint64_t)w * range, r1 = min(n, r0 + range);
     const uint64_t lt = (1ull << lane) - 1ull;
     for (uint64_t t0 = r0; t0 < r1; t0 += kSortTile) {
@@ -276,7 +288,8 @@ bool radix_sort_pairs(tid_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
     const uint64_t range = (tiles + P - 1) / P * kSortTile;
     P = (n + range - 1) / range;
     DevBuf counts(ctx, (size_t)kRadix * P * sizeof(uint32_t));
-    DevBuf offs(ctx, (size_t)kRadix * P * sizeof(uint32_t));
+    DevBuf scan(ctx, (size_t)kRadix * (P + 1) * sizeof(uint32_t));  // then the digit totals
+    uint32_t *totals = scan.get<uint32_t>() + (size_t)kRadix * P;
     bool flip = false;
     for (int shift = 0; shift < bits; shift += kRadixBits) {
         const uint64_t *ki = flip ? k1 : k0;
@@ -286,11 +299,11 @@ bool radix_sort_pairs(tid_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
         hipLaunchKernelGGL(radix_hist, dim3((uint32_t)P), dim3(kSortBlock), 0, ctx->stream, ki, n,
                            range, shift, counts.get<uint32_t>());
         TID_HIP(hipGetLastError());
-        hipLaunchKernelGGL(digit_offsets, dim3(1), dim3(kOffThreads), 0, ctx->stream,
-                           counts.get<const uint32_t>(), offs.get<uint32_t>(), (uint32_t)P);
+        hipLaunchKernelGGL(digit_scan, dim3(kRadix), dim3(kColThreads), 0, ctx->stream,
+                           counts.get<const uint32_t>(), scan.get<uint32_t>(), totals, (uint32_t)P);
         TID_HIP(hipGetLastError());
         hipLaunchKernelGGL(radix_scatter, dim3((uint32_t)P), dim3(kSortBlock), 0, ctx->stream, ki,
-                           vi, ko, vo, n, range, shift, offs.get<const uint32_t>());
+                           vi, ko, vo, n, range, shift, scan.get<const uint32_t>(), totals);
         TID_HIP(hipGetLastError());
         flip = !flip;
     }
