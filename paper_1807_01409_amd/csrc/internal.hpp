@@ -196,14 +196,26 @@ void copy_bounds(tid_table *dst, const tid_table *src, const int *map, int n, in
 
 // ---- launchers implemented in the .hip files ------------------------------
 
-struct CompiledPattern;  // scan.hip
+// Values one position of a pattern may take (Sec. 4.2: a union of scans that
+// differ only in that constant, evaluated as one scan).  The pattern keeps a
+// constant there so that its schema is that of each scan of the union.
+constexpr int kMaxSet = 16;
+struct PatternSet {
+    int32_t pos = -1;  // -1: none
+    int32_t n = 0;
+    uint32_t v[kMaxSet] = {};
+};
 
 // Scan: fill `outs[j]` for k patterns in one pass.  Tables are allocated here.
+// sets (may be null): per pattern, a set of values for one position.
 void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                std::unique_ptr<tid_table> *outs);
+                std::unique_ptr<tid_table> *outs, const PatternSet *sets = nullptr);
 // any number of patterns, in as few passes over the graph as the kernels allow
 void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-               std::unique_ptr<tid_table> *outs);
+               std::unique_ptr<tid_table> *outs, const PatternSet *sets = nullptr);
+// rows a pattern (with its set, if any) can produce, from the load-time histograms
+uint64_t pattern_output_bound(const tid_graph *g, const tid_pattern &p,
+                              const PatternSet *set = nullptr);
 std::unique_ptr<tid_table> filter_range(tid_ctx *ctx, const tid_table *t, int col, uint32_t lo,
                                         uint32_t hi);
 // columns of L and of R kept, in that order, in a join's output

@@ -105,8 +105,9 @@ struct Entry {
 struct PlanRun {
     const tid_plan *plan = nullptr;
     std::vector<tid_pattern> scans;
-    std::vector<int> scan_at_op;
-    std::vector<char> fused;
+    std::vector<PatternSet> sets;  // per scan: a value set for one position, if any
+    std::vector<int> scan_at_op;   // per op: scan index, or kAbsorbed for a fused union member
+    std::vector<char> fused;       // per op: FILTER run inside its scan / UNION of one table
     std::vector<std::unique_ptr<tid_table>> scanned;
     int pc = 0;
     std::vector<Entry> st;
@@ -122,9 +123,59 @@ struct Needs {
     std::vector<PendingJoin *> joins;
 };
 
+constexpr int kAbsorbed = -2;
+
+// A UNION of the k scans just pushed (k consecutive SCAN ops right before it)
+// whose patterns bind the same variables at the same positions, carry the
+// same range, and differ in exactly one position, where each holds a
+// distinct constant, is one scan of a pattern whose value there is any of
+// those constants: no triple matches two of the scans, so the rows are the
+// same multiset, found in one pass over the graph (the union's result is
+// sorted afterwards either way).
+static void fuse_union(PlanRun &r, int pc, int k) {
+    const uint32_t *ops = r.plan->ops;
+    if (k < 2 || k > kMaxSet || pc < 2 * k) return;
+    for (int j = 0; j < k; ++j) {
+        const int at = pc - 2 * k + 2 * j;
+        if (ops[at] != TID_OP_SCAN || r.scan_at_op[at] < 0) return;
+    }
+    const int first = r.scan_at_op[pc - 2 * k];
+    if (first + k != (int)r.scans.size()) return;
+    const tid_pattern *q = &r.scans[first];
+    for (int j = 0; j < k; ++j)
+        if (r.sets[first + j].pos >= 0) return;
+    auto consts = [](const tid_pattern &p, int x) { return x == 0 ? p.s : x == 1 ? p.p : p.o; };
+    int pos = -1;
+    for (int x = 0; x < 3; ++x)
+        for (int j = 1; j < k; ++j)
+            if (consts(q[j], x) != consts(q[0], x)) {
+                if (pos >= 0 && pos != x) return;
+                pos = x;
+            }
+    if (pos < 0) return;
+    for (int j = 0; j < k; ++j) {
+        if (q[j].vs != q[0].vs || q[j].vp != q[0].vp || q[j].vo != q[0].vo) return;
+        if (q[j].range_pos != q[0].range_pos) return;
+        if (q[0].range_pos >= 0 && (q[j].lo != q[0].lo || q[j].hi != q[0].hi)) return;
+        if (consts(q[j], pos) == 0) return;
+        for (int i = 0; i < j; ++i)
+            if (consts(q[i], pos) == consts(q[j], pos)) return;
+    }
+    PatternSet set;
+    set.pos = pos;
+    set.n = k;
+    for (int j = 0; j < k; ++j) set.v[j] = consts(q[j], pos);
+    r.sets[first] = set;
+    r.scans.resize(first + 1);
+    r.sets.resize(first + 1);
+    for (int j = 1; j < k; ++j) r.scan_at_op[pc - 2 * k + 2 * j] = kAbsorbed;
+    r.fused[pc] = 1;
+}
+
 // Check the op stream and list one scan per SCAN op.  A FILTER right after a
 // SCAN on a variable that the pattern binds (and with no range yet) becomes
-// the pattern's range: the filter runs inside the search (Fig. 6).
+// the pattern's range: the filter runs inside the search (Fig. 6).  A UNION
+// of compatible scans becomes one scan (fuse_union).
 static void compile_plan(const tid_plan *plan, PlanRun &r) {
     TID_REQUIRE(plan, TID_E_INVALID_ARG, "plan: null");
     TID_REQUIRE(plan->n_patterns >= 0 && plan->n_ops >= 0, TID_E_INVALID_ARG, "plan: bad sizes");
@@ -164,6 +215,7 @@ static void compile_plan(const tid_plan *plan, PlanRun &r) {
             }
             r.scan_at_op[pc] = (int)r.scans.size();
             r.scans.push_back(p);
+            r.sets.emplace_back();
             ++depth;
             pc += 2;
         } else if (op == TID_OP_JOIN) {
@@ -175,6 +227,7 @@ static void compile_plan(const tid_plan *plan, PlanRun &r) {
             need(3);
             const uint32_t k = ops[pc + 1];
             TID_REQUIRE(k >= 1 && (int)k <= depth, TID_E_INVALID_ARG, "plan: bad UNION arity");
+            fuse_union(r, pc, (int)k);
             depth -= (int)k - 1;
             pc += 3;
         } else if (op == TID_OP_FILTER) {
@@ -238,7 +291,8 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
         const int pc = r.pc;
         const uint32_t op = ops[pc];
         if (op == TID_OP_SCAN) {
-            r.st.push_back({std::move(r.scanned[r.scan_at_op[pc]]), false});
+            if (r.scan_at_op[pc] != kAbsorbed)
+                r.st.push_back({std::move(r.scanned[r.scan_at_op[pc]]), false});
             r.pc += 2;
         } else if (op == TID_OP_JOIN) {
             tid_table *L = r.st[r.st.size() - 2].t.get();
@@ -271,7 +325,7 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
             r.st.pop_back();
             r.pc += 2;
         } else if (op == TID_OP_UNION) {
-            const int k = (int)ops[pc + 1];
+            const int k = r.fused[pc] ? 1 : (int)ops[pc + 1];
             const int d = ops[pc + 2] ? 1 : 0;
             bool wait = false;
             std::vector<const tid_table *> ins;
@@ -318,15 +372,17 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
     std::vector<PlanRun> runs(nq);
     for (int i = 0; i < nq; ++i) compile_plan(plans[i], runs[i]);
     std::vector<tid_pattern> all;
+    std::vector<PatternSet> all_sets;
     std::vector<std::pair<int, int>> where;
     for (int i = 0; i < nq; ++i)
         for (size_t s = 0; s < runs[i].scans.size(); ++s) {
             all.push_back(runs[i].scans[s]);
+            all_sets.push_back(runs[i].sets[s]);
             where.emplace_back(i, (int)s);
         }
     if (!all.empty()) {
         std::vector<std::unique_ptr<tid_table>> outs(all.size());
-        scan_many(ctx, g, all.data(), (int)all.size(), outs.data());
+        scan_many(ctx, g, all.data(), (int)all.size(), outs.data(), all_sets.data());
         for (size_t j = 0; j < all.size(); ++j)
             runs[where[j].first].scanned[where[j].second] = std::move(outs[j]);
     }
@@ -359,18 +415,17 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
     return out;
 }
 
-uint64_t pattern_output_bound(const tid_graph *g, const tid_pattern &p);
-
 // Device bytes the plan's scans will hold (their outputs are sized by the
 // load-time histograms), times two for the intermediate results of joins.
 uint64_t estimate_plan_bytes(const tid_graph *g, const tid_plan *plan) {
     PlanRun r;
     compile_plan(plan, r);
     uint64_t bytes = 0;
-    for (const tid_pattern &p : r.scans) {
+    for (size_t i = 0; i < r.scans.size(); ++i) {
         int32_t vars[3], src[3];
-        const int nc = pattern_schema(p, vars, src);
-        bytes += pattern_output_bound(g, p) * 4ull * (uint64_t)std::max(nc, 1);
+        const int nc = pattern_schema(r.scans[i], vars, src);
+        bytes += pattern_output_bound(g, r.scans[i], &r.sets[i]) * 4ull *
+                 (uint64_t)std::max(nc, 1);
     }
     return 2 * bytes;
 }

@@ -33,6 +33,9 @@ struct DevPattern {
     uint32_t lo, span;
     int32_t ncols;
     int32_t src[3];
+    int32_t set_pos;  // -1: no value set; else the value there is one of set[0..nset)
+    int32_t nset;
+    uint32_t set[kMaxSet];
 };
 
 template <int MAXK>
@@ -60,6 +63,12 @@ __device__ __forceinline__ bool match_pattern(const DevPattern &q, const Tri &t)
     ok &= !(q.eq & 2u) || t.v[0] == t.v[2];
     ok &= !(q.eq & 4u) || t.v[1] == t.v[2];
     if (q.rpos >= 0) ok &= (pick(t, q.rpos) - q.lo) < q.span;
+    if (q.set_pos >= 0) {
+        const uint32_t x = pick(t, q.set_pos);
+        bool in = false;
+        for (int i = 0; i < q.nset; ++i) in |= x == q.set[i];
+        ok &= in;
+    }
     return ok;
 }
 
@@ -334,8 +343,9 @@ int pattern_schema(const tid_pattern &p, int32_t *vars, int32_t *src) {
     return k;
 }
 
-static DevPattern compile_pattern(const tid_pattern &p) {
+static DevPattern compile_pattern(const tid_pattern &p, const PatternSet *set = nullptr) {
     DevPattern d{};
+    d.set_pos = -1;
     int32_t vars[3], src[3];
     d.ncols = pattern_schema(p, vars, src);
     const uint32_t c[3] = {p.s, p.p, p.o};
@@ -351,12 +361,32 @@ static DevPattern compile_pattern(const tid_pattern &p) {
     d.lo = p.lo;
     d.span = p.hi > p.lo ? p.hi - p.lo : 0u;
     for (int j = 0; j < d.ncols; ++j) d.src[j] = src[j];
+    if (set && set->pos >= 0) {
+        TID_REQUIRE(set->pos <= 2 && set->n >= 1 && set->n <= kMaxSet, TID_E_INTERNAL,
+                    "pattern set: bad position or size");
+        d.key[set->pos] = 0;
+        d.msk[set->pos] = 0;
+        d.set_pos = set->pos;
+        d.nset = set->n;
+        for (int i = 0; i < set->n; ++i) d.set[i] = set->v[i];
+    }
     return d;
 }
 
 // Upper bound on the rows a pattern can produce, from the load-time
-// histograms: the count of its rarest constant, and of its range.
-static uint64_t pattern_bound(const tid_graph *g, const tid_pattern &p) {
+// histograms: the count of its rarest constant, and of its range; with a
+// value set, the sum of that bound over the set's values.
+static uint64_t pattern_bound(const tid_graph *g, const tid_pattern &p,
+                              const PatternSet *set = nullptr) {
+    if (set && set->pos >= 0) {
+        uint64_t sum = 0;
+        for (int i = 0; i < set->n; ++i) {
+            tid_pattern q = p;
+            (set->pos == 0 ? q.s : set->pos == 1 ? q.p : q.o) = set->v[i];
+            sum += pattern_bound(g, q);
+        }
+        return std::min<uint64_t>(sum, g->n);
+    }
     uint64_t b = g->n;
     const uint32_t c[3] = {p.s, p.p, p.o};
     for (int x = 0; x < 3; ++x)
@@ -365,8 +395,8 @@ static uint64_t pattern_bound(const tid_graph *g, const tid_pattern &p) {
     return b;
 }
 
-uint64_t pattern_output_bound(const tid_graph *g, const tid_pattern &p) {
-    return pattern_bound(g, p);
+uint64_t pattern_output_bound(const tid_graph *g, const tid_pattern &p, const PatternSet *set) {
+    return pattern_bound(g, p, set);
 }
 
 struct Shape {
@@ -389,13 +419,13 @@ static uint32_t stage_words(tid_ctx *ctx) {
 // One pass over the graph for k patterns into the given tables.
 template <int MAXK>
 static void run_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                     tid_table *const *outs) {
+                     tid_table *const *outs, const PatternSet *sets) {
     ScanSrc<MAXK> src{};
     src.g = g->data.get<const uint32_t>();
     src.n = g->n;
     CompactArgs<MAXK, 3> a{};
     for (int j = 0; j < k; ++j) {
-        src.pat[j] = compile_pattern(pats[j]);
+        src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr);
         for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
         a.out[j].cap = outs[j]->cap;
         a.out[j].count = outs[j]->d_count;
@@ -458,13 +488,13 @@ static void launch_multi(tid_ctx *ctx, const tid_graph *g, MultiArgs &a, int k, 
 // Up to MAXK patterns in the generic compaction kernel, fully unrolled.
 template <int MAXK, int B, int I>
 static void run_unrolled(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                         tid_table *const *outs) {
+                         tid_table *const *outs, const PatternSet *sets) {
     ScanSrc<MAXK> src{};
     src.g = g->data.get<const uint32_t>();
     src.n = g->n;
     CompactArgs<MAXK, 3> a{};
     for (int j = 0; j < k; ++j) {
-        src.pat[j] = compile_pattern(pats[j]);
+        src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr);
         for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
         a.out[j].cap = outs[j]->cap;
         a.out[j].count = outs[j]->d_count;
@@ -475,13 +505,13 @@ static void run_unrolled(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pa
 
 template <int MAXK>
 static void run_unrolled_shape(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                               tid_table *const *outs, int shape) {
+                               tid_table *const *outs, int shape, const PatternSet *sets) {
     if (shape == 1)
-        run_unrolled<MAXK, 256, 8>(ctx, g, pats, k, outs);
+        run_unrolled<MAXK, 256, 8>(ctx, g, pats, k, outs, sets);
     else if (shape == 2)
-        run_unrolled<MAXK, 256, 16>(ctx, g, pats, k, outs);
+        run_unrolled<MAXK, 256, 16>(ctx, g, pats, k, outs, sets);
     else
-        run_unrolled<MAXK, 512, 8>(ctx, g, pats, k, outs);
+        run_unrolled<MAXK, 512, 8>(ctx, g, pats, k, outs, sets);
 }
 
 // multi_kernel option: 0 (default) the unrolled kernel for up to 4 patterns,
@@ -493,9 +523,9 @@ static void run_unrolled_shape(tid_ctx *ctx, const tid_graph *g, const tid_patte
 // eight patterns of ~1% selectivity.  multi_shape 0 is 512 threads x 8
 // triples for both.
 static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                         tid_table *const *outs) {
+                         tid_table *const *outs, const PatternSet *sets) {
     if (k == 1) {
-        run_scan<1>(ctx, g, pats, k, outs);
+        run_scan<1>(ctx, g, pats, k, outs, sets);
         return;
     }
     const int shape = (int)ctx->opt.multi_shape;
@@ -503,19 +533,20 @@ static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pa
         const int passes = (k + 3) / 4;
         for (int p0 = 0, p = 0; p < passes; ++p) {
             const int m = (k - p0) / (passes - p);
+            const PatternSet *ps = sets ? sets + p0 : nullptr;
             if (m == 1)
-                run_scan<1>(ctx, g, pats + p0, 1, outs + p0);
+                run_scan<1>(ctx, g, pats + p0, 1, outs + p0, ps);
             else if (m == 2)
-                run_unrolled_shape<2>(ctx, g, pats + p0, m, outs + p0, shape);
+                run_unrolled_shape<2>(ctx, g, pats + p0, m, outs + p0, shape, ps);
             else
-                run_unrolled_shape<4>(ctx, g, pats + p0, m, outs + p0, shape);
+                run_unrolled_shape<4>(ctx, g, pats + p0, m, outs + p0, shape, ps);
             p0 += m;
         }
         return;
     }
     MultiArgs a{};
     for (int j = 0; j < k; ++j) {
-        a.pat[j] = compile_pattern(pats[j]);
+        a.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr);
         for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
         a.out[j].cap = outs[j]->cap;
         a.out[j].count = outs[j]->d_count;
@@ -540,10 +571,13 @@ void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
 // through wide passes of up to 1024 patterns when there are at least
 // `wide_min` of them; the rest through passes of up to 16.
 void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-               std::unique_ptr<tid_table> *outs) {
+               std::unique_ptr<tid_table> *outs, const PatternSet *sets) {
     const int64_t wide_min = ctx->opt.wide_min > 0 ? ctx->opt.wide_min : 32;
     std::vector<int> wide, rest;
-    for (int j = 0; j < k; ++j) (wide_eligible(pats[j]) ? wide : rest).push_back(j);
+    for (int j = 0; j < k; ++j) {
+        const bool has_set = sets && sets[j].pos >= 0;
+        (!has_set && wide_eligible(pats[j]) ? wide : rest).push_back(j);
+    }
     if ((int64_t)wide.size() < wide_min || ctx->opt.capacity_override > 0 || g->n == 0) {
         rest.insert(rest.end(), wide.begin(), wide.end());
         wide.clear();
@@ -569,21 +603,25 @@ void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
     for (size_t r0 = 0; r0 < rest.size(); r0 += TID_MAX_MULTI) {
         const int m = (int)std::min<size_t>(TID_MAX_MULTI, rest.size() - r0);
         std::vector<tid_pattern> rp(m);
+        std::vector<PatternSet> rs(m);
         std::unique_ptr<tid_table> rt[TID_MAX_MULTI];
-        for (int j = 0; j < m; ++j) rp[j] = pats[rest[r0 + j]];
-        scan_multi(ctx, g, rp.data(), m, rt);
+        for (int j = 0; j < m; ++j) {
+            rp[j] = pats[rest[r0 + j]];
+            if (sets) rs[j] = sets[rest[r0 + j]];
+        }
+        scan_multi(ctx, g, rp.data(), m, rt, rs.data());
         for (int j = 0; j < m; ++j) outs[rest[r0 + j]] = std::move(rt[j]);
     }
 }
 
 void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                std::unique_ptr<tid_table> *outs) {
+                std::unique_ptr<tid_table> *outs, const PatternSet *sets) {
     TID_REQUIRE(k >= 1 && k <= TID_MAX_MULTI, TID_E_INVALID_ARG, "scan: 1..16 patterns per pass");
     std::vector<uint64_t> bound(k);
     for (int j = 0; j < k; ++j) {
         int32_t vars[3], src[3];
         const int nc = pattern_schema(pats[j], vars, src);
-        bound[j] = pattern_bound(g, pats[j]);
+        bound[j] = pattern_bound(g, pats[j], sets ? &sets[j] : nullptr);
         uint64_t cap = ctx->opt.capacity_override > 0 ? (uint64_t)ctx->opt.capacity_override
                                                       : bound[j];
         outs[j] = make_table(ctx, nc, vars, cap);
@@ -596,7 +634,7 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
     }
     std::vector<tid_table *> raw(k);
     for (int j = 0; j < k; ++j) raw[j] = outs[j].get();
-    run_scan_any(ctx, g, pats, k, raw.data());
+    run_scan_any(ctx, g, pats, k, raw.data(), sets);
 
     // Outputs sized by the histogram bound cannot overflow.  A smaller
     // capacity (forced for tests) is checked and, if allowed, run again at
@@ -611,6 +649,7 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
     if (redo.empty()) return;
     TID_REQUIRE(ctx->opt.retry, TID_E_CAPACITY, "scan: result exceeds the output capacity");
     std::vector<tid_pattern> rp;
+    std::vector<PatternSet> rs;
     std::vector<tid_table *> rt;
     for (int j : redo) {
         const uint64_t need = outs[j]->nrows;
@@ -619,9 +658,10 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
         bigger->maxv_known = outs[j]->maxv_known;
         outs[j] = std::move(bigger);
         rp.push_back(pats[j]);
+        rs.push_back(sets ? sets[j] : PatternSet{});
         rt.push_back(outs[j].get());
     }
-    run_scan_any(ctx, g, rp.data(), (int)rp.size(), rt.data());
+    run_scan_any(ctx, g, rp.data(), (int)rp.size(), rt.data(), rs.data());
 }
 
 // ---------------------------------------------------------------------------

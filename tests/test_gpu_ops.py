@@ -197,3 +197,47 @@ def test_query_batch_equals_alone(ctx, graphs):
         assert np.array_equal(t.to_numpy(), alone.to_numpy())
         same(t, oracle.query(g, p))
     assert ctx.query_batch(G, []) == []
+
+
+def test_union_of_scans(ctx, graphs):
+    """UNIONs of scans, fusable into one scan (distinct constants in one
+    position) and not (repeated constants, different variable layouts, more
+    constants than a set holds, different ranges), with and without
+    DISTINCT, alone and under a join: all equal the oracle."""
+    g = graphs("small")
+    G = ctx.load(g)
+    hub = int(np.bincount(g[:, 2]).argmax())
+
+    def union_plan(patterns, dedupe, tail=None):
+        n = {}
+        p = Plan()
+        for text in patterns:
+            p.scan(text if isinstance(text, Pattern) else pat(text, n))
+        p.union(len(patterns), dedupe)
+        if tail:
+            tail(p, n)
+        return p
+
+    cases = [
+        (["?s 3 ?o", "?s 4 ?o", "?s 5 ?o", "?s 6 ?o"], False),
+        (["?s 3 ?o", "?s 4 ?o", "?s 5 ?o", "?s 6 ?o"], True),
+        (["?s 3 ?o", "?s 3 ?o", "?s 5 ?o"], False),           # repeated constant: bag
+        ([f"?s {q} {hub}" for q in range(1, 12)], False),       # set on the predicate, one variable
+        (["?s 3 ?o", "?o 4 ?s", "?s 5 ?o"], False),           # variables move
+        ([f"?s {q} ?o" for q in range(1, 19)], True),           # more than a set holds
+        ([Pattern(0, 3, 0, 0, -1, 1, range_pos=2, lo=1, hi=4000),
+          Pattern(0, 4, 0, 0, -1, 1, range_pos=2, lo=1, hi=4000)], False),
+        ([Pattern(0, 3, 0, 0, -1, 1, range_pos=2, lo=1, hi=4000),
+          Pattern(0, 4, 0, 0, -1, 1, range_pos=2, lo=1, hi=9000)], False),
+    ]
+    for patterns, dedupe in cases:
+        plan = union_plan(patterns, dedupe)
+        same(ctx.query(G, plan), oracle.query(g, plan))
+    # a fused union joined with another scan on ?s
+    plan = union_plan(["?s 3 ?o", "?s 4 ?o", "?s 5 ?o"], False,
+                      lambda p, n: p.scan(pat("?s 7 ?x", n)).join(n["?s"]))
+    same(ctx.query(G, plan), oracle.query(g, plan))
+    # the same unions inside one batch
+    plans = [union_plan(pp, d) for pp, d in cases[:4]]
+    for t, plan in zip(ctx.query_batch(G, plans), plans):
+        same(t, oracle.query(g, plan))
