@@ -2,8 +2,9 @@
 
 Every function named tid_* here calls the C entry point of the same name;
 every step of the query path runs in the library's HIP kernels.  PyTorch
-supplies the device memory (its caching allocator, through the allocation
-callbacks) and the stream.
+supplies the stream, and optionally the device memory (its caching
+allocator, through the allocation callbacks); by default the library's own
+native pool allocates.
 """
 from __future__ import annotations
 
@@ -54,10 +55,12 @@ class Context:
 
     The context enqueues on `stream` (a torch.cuda.Stream); by default it makes
     a stream of its own, so that its work never rides on the legacy default
-    stream.  allocator="torch" routes device memory through torch's caching
-    allocator on that stream; allocator="pool" uses the library's own pool."""
+    stream.  allocator="pool" (default) uses the library's own native pool;
+    allocator="torch" routes device memory through torch's caching allocator
+    on that stream (one Python callback per allocation), for callers that
+    share memory accounting with torch."""
 
-    def __init__(self, device: int = 0, stream=None, allocator: str = "torch"):
+    def __init__(self, device: int = 0, stream=None, allocator: str = "pool"):
         import torch
         lib = L.load_library()
         self._torch = torch

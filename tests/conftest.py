@@ -25,7 +25,7 @@ def oracle_lib():
 
 @pytest.fixture(scope="session")
 def ctx():
-    """One library context on cuda:0 for the GPU tests (torch allocator)."""
+    """One library context on cuda:0 for the GPU tests (native pool allocator)."""
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")

@@ -171,10 +171,10 @@ def test_filter_parity(ctx, graphs):
         same(ctx.filter(t, col, lo, hi), oracle.filter(o, col, lo, hi))
 
 
-def test_pool_allocator_matches(ctx, graphs):
+def test_torch_allocator_matches(ctx, graphs):
     from paper_1807_01409_amd import Context
     g = graphs("small")
-    with Context(0, allocator="pool") as c2:
+    with Context(0, allocator="torch") as c2:
         G = c2.load(g)
         p = pat("?s 9 ?o")
         assert np.array_equal(c2.scan(G, p).to_numpy(), oracle.scan(g, p).rows)
