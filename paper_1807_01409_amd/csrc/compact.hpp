@@ -682,10 +682,7 @@ void launch_chunked(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
 // caller fills a.out[0..k) (columns, caps, counts, ncols); staging areas are
 // laid out here over `stage_words` words of LDS.  The context's
 // compact_kernel option picks the kernel: 1 block-ranged (PREFETCH picks its
-// prefetching variant), 2 chunked, 0 (default) block-ranged when every
-// output's row bound per range is under an eighth of its staging area (its
-// writes at the end are then short, and it has no per-chunk placement), else
-// chunked.
+// prefetching variant), 2 chunked, 0 (default) by the output bounds (below).
 template <class Src, int BLOCK, int IPT, int MAXK, int MAXC, bool PREFETCH = false>
 void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, int k,
                     uint32_t stage_words) {
@@ -704,9 +701,18 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
             1, std::min<uint64_t>({(n + TILE - 1) / TILE,
                                    (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx),
                                    (uint64_t)BLOCK * kPrefixPer}));
+        // One output: chunked where the block-ranged staging would overflow
+        // (that kernel would re-read the graph), and from an eighth of the
+        // staging area on while there are few chunks per workgroup (the
+        // chunked placements overlap the writes that the block-ranged kernel
+        // leaves to its end; each placement is a fixed cost, so on large
+        // inputs the block-ranged kernel wins until it overflows).  Several
+        // outputs: block-ranged (measured faster on the batched query mix).
+        const uint64_t tiles = (n + TILE - 1) / TILE;
+        const bool few_chunks = tiles / kMaxBigTiles <= 12 * ranges;
+        const uint64_t limit = few_chunks ? rows_per / 8 : rows_per;
         kind = 1;
-        for (int j = 0; j < k; ++j)
-            if (a.out[j].ncols && a.out[j].cap / ranges > rows_per / 8) kind = 2;
+        if (MAXK == 1 && a.out[0].ncols && a.out[0].cap / ranges > limit) kind = 2;
     }
     if (kind == 2) {
         launch_chunked<Src, BLOCK, IPT, MAXK, MAXC>(ctx, src, a, k, stage_words);

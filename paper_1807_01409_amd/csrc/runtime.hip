@@ -14,10 +14,14 @@ namespace tid {
 
 size_t Pool::size_class(size_t bytes) {
     if (bytes <= 4096) return 4096;
-    // round to 1/8 of the next power of two: at most 12.5% slack
     size_t p = 1;
     while (p < bytes) p <<= 1;
-    size_t step = std::max<size_t>(p / 8, 4096);
+    // Up to 256 MiB a block is the next power of two, so that blocks of the
+    // many intermediate tables of varying size are reused rather than
+    // allocated again; above, 1/8 of the next power of two (at most 12.5%
+    // slack) keeps large tables and graphs tight.
+    if (p <= (size_t(256) << 20)) return p;
+    const size_t step = p / 8;
     return (bytes + step - 1) / step * step;
 }
 
