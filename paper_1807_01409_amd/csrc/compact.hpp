@@ -16,8 +16,10 @@
 //            of the range from the first unstaged tile and write directly.
 // Workgroups take their range index from an atomic counter, so a workgroup
 // only ever waits on ranges handed out before its own, whose workgroups are
-// already running: every wait ends.  The workgroup that finishes last clears
-// the sync words for the next launch.
+// already running: every wait ends.  Range counts carry the launch's epoch
+// stamp, so they need no clearing, and the workgroup that finishes last
+// resets the ticket and done counters with relaxed atomics: no release fence,
+// which on MI355X would write back the XCD's L2 once per workgroup.
 #pragma once
 
 #include "device_common.hpp"
@@ -137,7 +139,8 @@ __device__ __forceinline__ uint32_t offsets_in_place(uint32_t *s) {
 
 template <class Src, int BLOCK, int IPT, int MAXK, int MAXC, bool PREFETCH = false>
 __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAXK, MAXC> a,
-                                                         uint64_t *sync, uint32_t *flags) {
+                                                         uint64_t *sync, uint32_t *counters,
+                                                         uint32_t *flags) {
     constexpr int NW = BLOCK / dev::kWave;
     constexpr int NV = IPT * NW;
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
     const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
     const int k = MAXK == 1 ? 1 : a.k;
     const uint32_t P = a.P;
-    uint32_t *counters = reinterpret_cast<uint32_t *>(sync + (size_t)k * P);
+    const uint64_t stamp = (uint64_t)a.epoch << kEpochShift;
     if (tid == 0) s_wg = atomicAdd(&counters[0], 1u);
     if (tid < k) {
         s_cnt[tid] = 0;
@@ -221,7 +224,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
     // ---- prefix over earlier ranges ----------------------------------------
     if (tid < k) {
         if (s_ovf[tid] == kNoTile) s_staged[tid] = s_cnt[tid];
-        dev::publish(&sync[(size_t)tid * P + wg], kPublished | s_cnt[tid]);
+        dev::publish(&sync[(size_t)tid * P + wg], stamp | s_cnt[tid]);
     }
     // all predecessor counts are requested at once (kPrefixPer per thread),
     // then any not yet published are polled again
@@ -230,14 +233,14 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
 #pragma unroll
         for (int u = 0; u < kPrefixPer; ++u) {
             const uint32_t i = tid + u * BLOCK;
-            w[u] = i < wg ? dev::peek(&sync[(size_t)j * P + i]) : kPublished;
+            w[u] = i < wg ? dev::peek(&sync[(size_t)j * P + i]) : stamp;
         }
         uint64_t part = 0;
 #pragma unroll
         for (int u = 0; u < kPrefixPer; ++u) {
             const uint32_t i = tid + u * BLOCK;
             uint32_t spins = 0;
-            while (!(w[u] & kPublished)) {
+            while ((w[u] >> kEpochShift) != a.epoch) {
                 if (++spins > kSpinLimit) {
                     atomicOr(&flags[0], 1u);
                     break;
@@ -245,7 +248,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
                 __builtin_amdgcn_s_sleep(2);
                 w[u] = dev::peek(&sync[(size_t)j * P + i]);
             }
-            part += w[u] & ~kPublished;
+            part += w[u] & kRowsMask;
         }
         part = dev::wave_sum(part);
         if (lane == 0) s_red[j][wave] = part;
@@ -310,7 +313,17 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
         if (tid < k && s_ovf[tid] <= t0) s_run[tid] += s_tot[tid];
     }
     if (wg == P - 1 && tid < k) *a.out[tid].count = s_pre[tid] + s_cnt[tid];
-    dev::release_state(sync, (size_t)k * P, counters, P);
+    // the last workgroup out resets the ticket and done counters (the count
+    // words carry this launch's epoch and need no clearing)
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t d = __hip_atomic_fetch_add(&counters[1], 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (d == P - 1) {
+            __hip_atomic_store(&counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 
@@ -702,17 +715,12 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
                                    (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx),
                                    (uint64_t)BLOCK * kPrefixPer}));
         // One output: chunked where the block-ranged staging would overflow
-        // (that kernel would re-read the graph), and from an eighth of the
-        // staging area on while there are few chunks per workgroup (the
-        // chunked placements overlap the writes that the block-ranged kernel
-        // leaves to its end; each placement is a fixed cost, so on large
-        // inputs the block-ranged kernel wins until it overflows).  Several
-        // outputs: block-ranged (measured faster on the batched query mix).
-        const uint64_t tiles = (n + TILE - 1) / TILE;
-        const bool few_chunks = tiles / kMaxBigTiles <= 12 * ranges;
-        const uint64_t limit = few_chunks ? rows_per / 8 : rows_per;
+        // (that kernel would then re-read the graph); block-ranged otherwise
+        // (it has no per-chunk placements and, without a release fence, no
+        // fixed cost at its end beyond one round trip).  Several outputs:
+        // block-ranged (measured faster on the batched query mix).
         kind = 1;
-        if (MAXK == 1 && a.out[0].ncols && a.out[0].cap / ranges > limit) kind = 2;
+        if (MAXK == 1 && a.out[0].ncols && a.out[0].cap / ranges > rows_per) kind = 2;
     }
     if (kind == 2) {
         launch_chunked<Src, BLOCK, IPT, MAXK, MAXC>(ctx, src, a, k, stage_words);
@@ -733,10 +741,11 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
     a.k = k;
     a.P = (uint32_t)P;
     a.range = range;
-    uint64_t *sync = static_cast<uint64_t *>(
-        ctx->lookback_state(((size_t)k * P + 1) * sizeof(uint64_t)));
-    hipLaunchKernelGGL(kern, dim3((uint32_t)P), dim3(BLOCK), lds, ctx->stream, src, a, sync,
-                       ctx->d_flags);
+    // epoch state: the ticket and done counters (one u64 word), then k * P count words
+    uint64_t *state = nullptr;
+    a.epoch = ctx->next_epoch(((size_t)k * P + 1) * sizeof(uint64_t), &state);
+    hipLaunchKernelGGL(kern, dim3((uint32_t)P), dim3(BLOCK), lds, ctx->stream, src, a, state + 1,
+                       reinterpret_cast<uint32_t *>(state), ctx->d_flags);
     TID_HIP(hipGetLastError());
 }
 
