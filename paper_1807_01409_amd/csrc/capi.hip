@@ -88,7 +88,6 @@ void tid_ctx_destroy(tid_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    if (ctx->lb_state) ctx->free(ctx->lb_state, ctx->lb_bytes);
     if (ctx->ep_state) ctx->free(ctx->ep_state, ctx->ep_bytes);
     if (ctx->d_flags) ctx->free(ctx->d_flags, 2 * sizeof(uint32_t));
     if (ctx->rw_dev) ctx->free(ctx->rw_dev, ctx->rw_cap * 16);

@@ -54,7 +54,6 @@ struct CompactArgs {
 };
 
 constexpr uint64_t kNoTile = ~0ull;
-constexpr uint64_t kPublished = 1ull << 63;
 constexpr uint32_t kSpinLimit = 1u << 22;
 constexpr int kPrefixPer = 8;  // ranges per thread in the prefix read: P <= BLOCK * 8
 constexpr int kEpochShift = 40;                  // count slot: epoch << 40 | rows

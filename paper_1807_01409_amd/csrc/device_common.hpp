@@ -52,29 +52,5 @@ __device__ __forceinline__ uint64_t peek(const uint64_t *word) {
                              __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// End of a kernel that uses sync words, called by every thread of every
-// workgroup.  The sync words are all zero when a kernel starts: the workgroup
-// that finishes last (counted on counters[1]) clears the `nwords` words and
-// the `ncounters` counter words for the next launch.  Every other workgroup has made its last state access
-// before its increment of done.
-__device__ __forceinline__ void release_state(uint64_t *state, size_t nwords,
-                                              uint32_t *counters, uint32_t num_tiles,
-                                              int ncounters = 2) {
-    __shared__ int s_last;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        const uint32_t d = __hip_atomic_fetch_add(&counters[1], 1u, __ATOMIC_ACQ_REL,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-        s_last = d == num_tiles - 1;
-    }
-    __syncthreads();
-    if (s_last) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        for (size_t i = threadIdx.x; i < nwords; i += blockDim.x) state[i] = 0;
-        for (int i = threadIdx.x; i < ncounters; i += blockDim.x) counters[i] = 0;
-    }
-}
-
 }  // namespace dev
 }  // namespace tid

@@ -77,11 +77,9 @@ struct tid_ctx {
     tid::Pool pool;
     std::string last_error;
     tid::Options opt;
-    // scratch for look-back state: grown on demand, owned by the context
-    void *lb_state = nullptr;
-    size_t lb_bytes = 0;
-    // epoch-stamped count slots of the chunked compaction (two counter words
-    // first); zeroed when grown and when the epoch wraps
+    // cross-workgroup state of the compaction kernels: a ticket and a done
+    // counter, then epoch-stamped count words; zeroed when grown and when the
+    // epoch wraps
     void *ep_state = nullptr;
     size_t ep_bytes = 0;
     uint32_t epoch = 0;
@@ -94,7 +92,6 @@ struct tid_ctx {
 
     void *alloc(size_t bytes);
     void free(void *p, size_t bytes);
-    void *lookback_state(size_t bytes);  // all zero between kernels
     // stamp for the next chunked launch; *state gets the slot area of `bytes`
     uint32_t next_epoch(size_t bytes, uint64_t **state);
     void sync();

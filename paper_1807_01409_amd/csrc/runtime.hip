@@ -301,19 +301,6 @@ void tid_ctx::free(void *p, size_t bytes) {
 // Look-back state shared by the context's kernels (one stream, so launches
 // never overlap).  Kernels leave it all zero when they finish; a new buffer is
 // cleared here once.
-void *tid_ctx::lookback_state(size_t bytes) {
-    if (lb_bytes < bytes) {
-        const size_t want = tid::align_up(std::max(bytes, lb_bytes + lb_bytes / 2), 4096);
-        if (lb_state) free(lb_state, lb_bytes);
-        lb_state = nullptr;
-        lb_bytes = 0;
-        lb_state = alloc(want);
-        lb_bytes = want;
-        TID_HIP(hipMemsetAsync(lb_state, 0, want, stream));
-    }
-    return lb_state;
-}
-
 uint32_t tid_ctx::next_epoch(size_t bytes, uint64_t **state) {
     bool zero = false;
     if (ep_bytes < bytes) {

@@ -119,6 +119,7 @@ struct MultiArgs {
     int32_t k;
     uint32_t P;
     uint64_t range;
+    uint32_t epoch;  // stamp of this launch's count words
 };
 
 template <int BLOCK, int IPT>
@@ -135,7 +136,8 @@ __device__ __forceinline__ uint32_t multi_bits(const DevPattern &q, const Tri *t
 template <int BLOCK, int IPT>
 __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__restrict__ g,
                                                             uint64_t n, MultiArgs a,
-                                                            uint64_t *sync, uint32_t *flags) {
+                                                            uint64_t *sync, uint32_t *counters,
+                                                            uint32_t *flags) {
     constexpr int NW = BLOCK / dev::kWave;
     constexpr int NV = IPT * NW;
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
@@ -152,7 +154,7 @@ __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__res
     const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
     const int k = a.k;
     const uint32_t P = a.P;
-    uint32_t *counters = reinterpret_cast<uint32_t *>(sync + (size_t)k * P);
+    const uint64_t stamp = (uint64_t)a.epoch << kEpochShift;
     // thread j copies descriptor j (static indices into the kernel arguments)
 #pragma unroll
     for (int j = 0; j < TID_MAX_MULTI; ++j)
@@ -231,21 +233,21 @@ __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__res
     // ---- prefix over earlier ranges ----------------------------------------
     if (tid < k) {
         if (s_ovf[tid] == kNoTile) s_staged[tid] = s_cnt[tid];
-        dev::publish(&sync[(size_t)tid * P + wg], kPublished | s_cnt[tid]);
+        dev::publish(&sync[(size_t)tid * P + wg], stamp | s_cnt[tid]);
     }
     for (int j = 0; j < k; ++j) {
         uint64_t w[kPrefixPer];
 #pragma unroll
         for (int u = 0; u < kPrefixPer; ++u) {
             const uint32_t i = tid + u * BLOCK;
-            w[u] = i < wg ? dev::peek(&sync[(size_t)j * P + i]) : kPublished;
+            w[u] = i < wg ? dev::peek(&sync[(size_t)j * P + i]) : stamp;
         }
         uint64_t part = 0;
 #pragma unroll
         for (int u = 0; u < kPrefixPer; ++u) {
             const uint32_t i = tid + u * BLOCK;
             uint32_t spins = 0;
-            while (!(w[u] & kPublished)) {
+            while ((w[u] >> kEpochShift) != a.epoch) {
                 if (++spins > kSpinLimit) {
                     atomicOr(&flags[0], 1u);
                     break;
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__res
                 __builtin_amdgcn_s_sleep(2);
                 w[u] = dev::peek(&sync[(size_t)j * P + i]);
             }
-            part += w[u] & ~kPublished;
+            part += w[u] & kRowsMask;
         }
         part = dev::wave_sum(part);
         if (lane == 0) s_red[j][wave] = part;
@@ -312,7 +314,15 @@ __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__res
         if (tid < k && s_ovf[tid] <= t0) s_run[tid] += s_tot[tid];
     }
     if (wg == P - 1 && tid < k) *s_out[tid].count = s_pre[tid] + s_cnt[tid];
-    dev::release_state(sync, (size_t)k * P, counters, P);
+    __syncthreads();
+    if (tid == 0) {
+        const uint32_t d = __hip_atomic_fetch_add(&counters[1], 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+        if (d == P - 1) {
+            __hip_atomic_store(&counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -478,10 +488,12 @@ static void launch_multi(tid_ctx *ctx, const tid_graph *g, MultiArgs &a, int k, 
     a.k = k;
     a.P = (uint32_t)P;
     a.range = range;
-    uint64_t *sync =
-        static_cast<uint64_t *>(ctx->lookback_state(((size_t)k * P + 1) * sizeof(uint64_t)));
+    uint64_t *state = nullptr;
+    a.epoch = ctx->next_epoch(((size_t)k * P + 1) * sizeof(uint64_t), &state);
+    uint64_t *sync = state + 1;
+    uint32_t *counters = reinterpret_cast<uint32_t *>(state);
     hipLaunchKernelGGL(kern, dim3((uint32_t)P), dim3(BLOCK), lds, ctx->stream,
-                       g->data.get<const uint32_t>(), n, a, sync, ctx->d_flags);
+                       g->data.get<const uint32_t>(), n, a, sync, counters, ctx->d_flags);
     TID_HIP(hipGetLastError());
 }
 
