@@ -90,7 +90,15 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           from a ticket and place each chunk one chunk
                           later); 0 (default): block-ranged when the output
                           bound per range is small, chunked otherwise
-     "chunk_epoch"        stamp of the last chunked launch; the next launch
+     "semijoin"           1 (default): in a conjunctive plan (only SCAN, JOIN
+                          and FILTER up to its last JOIN, no UNION), large
+                          scans run after a smaller scan sharing a variable
+                          and keep only rows whose value there passes a Bloom
+                          filter of that scan's values (same result, smaller
+                          joins); 0: every scan in one round, unfiltered
+     "semijoin_min"       bound (rows, from the histograms) a scan needs
+                          before it is filtered (default 65536)
+     "chunk_epoch"        stamp of the last compaction launch; the next launch
                           uses stamp + 1 and, past 2^23 - 1, clears the
                           context's count slots and restarts at 1 (settable
                           so that tests can reach the wrap)

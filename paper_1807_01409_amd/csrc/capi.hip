@@ -127,6 +127,11 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
         } else if (k == "multi_shape") {
             TID_REQUIRE(value >= 0 && value <= 3, TID_E_INVALID_ARG, "multi_shape is 0..3");
             ctx->opt.multi_shape = value;
+        } else if (k == "semijoin") {
+            ctx->opt.semijoin = value ? 1 : 0;
+        } else if (k == "semijoin_min") {
+            TID_REQUIRE(value >= 0, TID_E_INVALID_ARG, "semijoin_min must be >= 0");
+            ctx->opt.semijoin_min = value;
         } else if (k == "chunk_epoch") {
             TID_REQUIRE(value >= 0 && value <= (int64_t)tid::kEpochMax, TID_E_INVALID_ARG,
                         "chunk_epoch is 0..2^23-1");
@@ -165,6 +170,8 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "multi_shape") *value = ctx->opt.multi_shape;
         else if (k == "compact_kernel") *value = ctx->opt.compact_kernel;
         else if (k == "chunk_epoch") *value = ctx->epoch;
+        else if (k == "semijoin") *value = ctx->opt.semijoin;
+        else if (k == "semijoin_min") *value = ctx->opt.semijoin_min;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });
 }

@@ -21,6 +21,29 @@ __device__ __forceinline__ uint32_t rank_in_mask(uint64_t mask) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// 32-bit finaliser of MurmurHash3 (Appleby): every input bit affects every
+// output bit
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x85ebca6bu;
+    x ^= x >> 13;
+    x *= 0xc2b2ae35u;
+    x ^= x >> 16;
+    return x;
+}
+
+// Bloom filter of (mask + 1) bits, a power of two, with two hash positions.
+__device__ __forceinline__ bool bloom_has(const uint32_t *bits, uint32_t mask, uint32_t x) {
+    const uint32_t h1 = hash32(x) & mask, h2 = hash32(x ^ 0x9E3779B9u) & mask;
+    return ((bits[h1 >> 5] >> (h1 & 31u)) & (bits[h2 >> 5] >> (h2 & 31u)) & 1u) != 0u;
+}
+
+__device__ __forceinline__ void bloom_add(uint32_t *bits, uint32_t mask, uint32_t x) {
+    const uint32_t h1 = hash32(x) & mask, h2 = hash32(x ^ 0x9E3779B9u) & mask;
+    atomicOr(&bits[h1 >> 5], 1u << (h1 & 31u));
+    atomicOr(&bits[h2 >> 5], 1u << (h2 & 31u));
+}
+
 // inclusive prefix sum across the wave
 template <class T>
 __device__ __forceinline__ T wave_inclusive_sum(T v) {

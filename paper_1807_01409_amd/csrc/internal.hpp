@@ -62,6 +62,8 @@ struct Options {
     int64_t multi_kernel = 0;    // 0 passes of <= 4 unrolled patterns, 1 LDS pattern loop
     int64_t multi_shape = 0;     // launch shape index of the chosen multi-pattern kernel
     int64_t compact_kernel = 0;  // 0 auto, 1 block-ranged, 2 chunked compaction
+    int64_t semijoin = 1;        // filter scans of conjunctive plans by join values
+    int64_t semijoin_min = 1 << 16;  // rows a scan's bound needs before it is filtered
 };
 
 }  // namespace tid
@@ -166,7 +168,10 @@ struct tid_table {
     uint64_t cap = 0;                 // rows allocated per column
     uint64_t nrows = 0;               // valid when count_known
     bool count_known = false;
-    tid::DevBuf block;                // columns (each align_up(cap*4)) + 8-byte device count
+    // columns (each align_up(cap*4)) + 8-byte device count; shared by the
+    // tables that alias one result (tables are never written after they are
+    // produced)
+    std::shared_ptr<tid::DevBuf> block;
     uint32_t *col[TID_MAX_COLS] = {};
     uint64_t *d_count = nullptr;
     // host-side upper bound of every column's values (valid when maxv_known);
@@ -203,13 +208,27 @@ struct PatternSet {
     uint32_t v[kMaxSet] = {};
 };
 
+// A membership filter on one position of a pattern: a Bloom filter of
+// (mask + 1) bits over the values another scan of the same conjunctive plan
+// binds to the variable at that position.  A row whose value is not in it
+// cannot take part in the plan's join; a false positive only keeps a row that
+// the join then drops.
+struct ScanFilter {
+    const uint32_t *bits = nullptr;
+    uint32_t mask = 0;
+    int32_t pos = -1;  // -1: none
+};
+
 // Scan: fill `outs[j]` for k patterns in one pass.  Tables are allocated here.
-// sets (may be null): per pattern, a set of values for one position.
+// sets, filters (each may be null): per pattern, a set of values for one
+// position, and a membership filter on one position.
 void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                std::unique_ptr<tid_table> *outs, const PatternSet *sets = nullptr);
+                std::unique_ptr<tid_table> *outs, const PatternSet *sets = nullptr,
+                const ScanFilter *filters = nullptr);
 // any number of patterns, in as few passes over the graph as the kernels allow
 void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-               std::unique_ptr<tid_table> *outs, const PatternSet *sets = nullptr);
+               std::unique_ptr<tid_table> *outs, const PatternSet *sets = nullptr,
+               const ScanFilter *filters = nullptr);
 // rows a pattern (with its set, if any) can produce, from the load-time histograms
 uint64_t pattern_output_bound(const tid_graph *g, const tid_pattern &p,
                               const PatternSet *set = nullptr);

@@ -178,15 +178,6 @@ __global__ void merge_counts(const uint64_t *qk, uint64_t nq, const uint64_t *bk
 // hash build and probe
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ uint32_t hash32(uint32_t x) {
-    // 32-bit finaliser (MurmurHash3 fmix32)
-    x ^= x >> 16;
-    x *= 0x85ebca6bu;
-    x ^= x >> 13;
-    x *= 0xc2b2ae35u;
-    x ^= x >> 16;
-    return x;
-}
 
 // slot words hold key + 1 (0 = empty)
 __global__ void hash_insert(const uint32_t *keys, uint64_t n, unsigned long long *slots,
@@ -194,7 +185,7 @@ __global__ void hash_insert(const uint32_t *keys, uint64_t n, unsigned long long
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const unsigned long long want = (unsigned long long)keys[i] + 1ull;
-        uint32_t h = hash32(keys[i]) & mask;
+        uint32_t h = dev::hash32(keys[i]) & mask;
         for (uint32_t probe = 0; probe <= mask; ++probe) {
             unsigned long long cur = slots[h];
             if (cur == 0ull) cur = atomicCAS(&slots[h], 0ull, want);
@@ -224,7 +215,7 @@ __global__ void hash_probe(const uint32_t *keys, uint64_t n, const unsigned long
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const unsigned long long want = (unsigned long long)keys[i] + 1ull;
-        uint32_t h = hash32(keys[i]) & mask;
+        uint32_t h = dev::hash32(keys[i]) & mask;
         uint32_t c = 0, s = 0;
         for (uint32_t probe = 0; probe <= mask; ++probe) {
             const unsigned long long cur = slots[h];

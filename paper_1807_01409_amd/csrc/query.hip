@@ -7,6 +7,9 @@
 // lockstep, so the host waits for the device once per round for all plans.
 #include "compact.hpp"
 
+#include <map>
+#include <string>
+
 #include <algorithm>
 
 namespace tid {
@@ -102,10 +105,20 @@ struct Entry {
 
 // One plan in flight: its compiled scans, its stack, and the join (if any)
 // waiting for its output size.
+// Where a scan sits in the semi-join rounds of its plan: the round it runs in,
+// and the scan whose rows filter it on a shared variable (-1: unfiltered).
+struct ScanRound {
+    int round = 0;
+    int src = -1;
+    int32_t var = -1;
+};
+
 struct PlanRun {
     const tid_plan *plan = nullptr;
     std::vector<tid_pattern> scans;
     std::vector<PatternSet> sets;  // per scan: a value set for one position, if any
+    std::vector<ScanRound> rounds; // per scan
+    bool conjunctive = false;      // the result is the natural join of all its scans
     std::vector<int> scan_at_op;   // per op: scan index, or kAbsorbed for a fused union member
     std::vector<char> fused;       // per op: FILTER run inside its scan / UNION of one table
     std::vector<std::unique_ptr<tid_table>> scanned;
@@ -250,6 +263,136 @@ static void compile_plan(const tid_plan *plan, PlanRun &r) {
     }
     TID_REQUIRE(depth == 1, TID_E_INVALID_ARG, "plan: must leave exactly one table");
     r.scanned.resize(r.scans.size());
+    r.rounds.assign(r.scans.size(), ScanRound{});
+    // Conjunctive: at least one JOIN, no UNION, and nothing but SCAN, JOIN and
+    // FILTER up to the last JOIN.  Every JOIN is a natural join (all shared
+    // variables must agree) and filters only remove rows, so the result is
+    // the natural join of all scans, filtered, then projected or deduplicated.
+    int last_join = -1;
+    for (int pc = 0; pc < nops;) {
+        const uint32_t op = ops[pc];
+        if (op == TID_OP_JOIN) last_join = pc;
+        pc += op == TID_OP_SCAN || op == TID_OP_JOIN ? 2 : op == TID_OP_UNION ? 3
+            : op == TID_OP_FILTER ? 4 : op == TID_OP_PROJECT ? 2 + (int)ops[pc + 1] : 1;
+    }
+    bool conj = last_join >= 0;
+    for (int pc = 0; pc < nops && conj;) {
+        const uint32_t op = ops[pc];
+        if (op == TID_OP_UNION) conj = false;
+        if (pc < last_join && op != TID_OP_SCAN && op != TID_OP_JOIN && op != TID_OP_FILTER)
+            conj = false;
+        pc += op == TID_OP_SCAN || op == TID_OP_JOIN ? 2 : op == TID_OP_UNION ? 3
+            : op == TID_OP_FILTER ? 4 : op == TID_OP_PROJECT ? 2 + (int)ops[pc + 1] : 1;
+    }
+    r.conjunctive = conj;
+}
+
+static bool binds(const tid_pattern &p, int32_t v) { return p.vs == v || p.vp == v || p.vo == v; }
+
+static int position_of(const tid_pattern &p, int32_t v) {
+    return p.vs == v ? 0 : p.vp == v ? 1 : p.vo == v ? 2 : -1;
+}
+
+// Semi-join rounds of a conjunctive plan (Sec. 4.2 joins, reduced first):
+// the scan with the smallest bound runs unfiltered in round 0; going outward
+// over the scans that share a variable, each large scan is filtered by the
+// smallest already-placed scan it shares a variable with, one round after
+// it.  A scan whose bound is under `min_rows`, or under 8x its filter
+// source's, is not worth a round and runs unfiltered in round 0.
+static void plan_rounds(const tid_graph *g, PlanRun &r, uint64_t min_rows) {
+    const int n = (int)r.scans.size();
+    if (!r.conjunctive || n < 2) return;
+    std::vector<uint64_t> bound(n);
+    for (int i = 0; i < n; ++i) bound[i] = pattern_output_bound(g, r.scans[i], &r.sets[i]);
+    int seed = 0;
+    for (int i = 1; i < n; ++i)
+        if (bound[i] < bound[seed]) seed = i;
+    std::vector<char> placed(n, 0);
+    std::vector<int> queue{seed};
+    placed[seed] = 1;
+    for (size_t qi = 0; qi < queue.size(); ++qi) {
+        const int u = queue[qi];
+        const tid_pattern &pu = r.scans[u];
+        const int32_t uv[3] = {pu.vs, pu.vp, pu.vo};
+        for (int j = 0; j < n; ++j) {
+            if (placed[j]) continue;
+            bool shares = false;
+            for (int x = 0; x < 3; ++x) shares |= uv[x] >= 0 && binds(r.scans[j], uv[x]);
+            if (!shares) continue;
+            // filter source: the smallest placed scan sharing a variable with j
+            int src = -1;
+            int32_t var = -1;
+            for (int i = 0; i < n; ++i) {
+                if (!placed[i]) continue;
+                const tid_pattern &pi = r.scans[i];
+                const int32_t iv[3] = {pi.vs, pi.vp, pi.vo};
+                for (int x = 0; x < 3; ++x)
+                    if (iv[x] >= 0 && binds(r.scans[j], iv[x]) &&
+                        (src < 0 || bound[i] < bound[src])) {
+                        src = i;
+                        var = iv[x];
+                    }
+            }
+            placed[j] = 1;
+            queue.push_back(j);
+            if (bound[j] >= min_rows && bound[j] >= 8 * bound[src])
+                r.rounds[j] = ScanRound{r.rounds[src].round + 1, src, var};
+        }
+    }
+}
+
+// Scans that compute the same rows: the pattern with its variables renamed
+// by first appearance, its value set and its filter.
+static std::string scan_key(const tid_pattern &p, const PatternSet &set, const ScanFilter &f) {
+    tid_pattern q = p;
+    int32_t *v[3] = {&q.vs, &q.vp, &q.vo};
+    int32_t seen[3] = {-1, -1, -1};
+    int nseen = 0;
+    for (int x = 0; x < 3; ++x) {
+        if (*v[x] < 0) continue;
+        int id = -1;
+        for (int i = 0; i < nseen; ++i)
+            if (seen[i] == *v[x]) id = i;
+        if (id < 0) {
+            seen[nseen] = *v[x];
+            id = nseen++;
+        }
+        *v[x] = id;
+    }
+    std::string k(reinterpret_cast<const char *>(&q), sizeof q);
+    k.append(reinterpret_cast<const char *>(&set.pos), sizeof set.pos);
+    k.append(reinterpret_cast<const char *>(&set.n), sizeof set.n);
+    k.append(reinterpret_cast<const char *>(set.v), sizeof(uint32_t) * (size_t)std::max(set.n, 0));
+    k.append(reinterpret_cast<const char *>(&f.bits), sizeof f.bits);
+    k.append(reinterpret_cast<const char *>(&f.mask), sizeof f.mask);
+    k.append(reinterpret_cast<const char *>(&f.pos), sizeof f.pos);
+    return k;
+}
+
+// The same rows under the variable ids of pattern p (no copy: the columns
+// are shared).
+static std::unique_ptr<tid_table> alias_table(const tid_table *t, const tid_pattern &p) {
+    auto out = std::make_unique<tid_table>(*t);
+    int32_t vars[3], src[3];
+    const int nc = pattern_schema(p, vars, src);
+    TID_REQUIRE(nc == t->ncols, TID_E_INTERNAL, "scan alias: schema mismatch");
+    for (int c = 0; c < nc; ++c) out->vars[c] = vars[c];
+    return out;
+}
+
+// One Bloom filter per job: the values of a table column.
+struct BloomJob {
+    const uint32_t *vals;
+    uint64_t n;
+    uint32_t *bits;
+    uint32_t mask;
+};
+
+__global__ void bloom_build(const BloomJob *jobs) {
+    const BloomJob j = jobs[blockIdx.y];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < j.n; i += stride)
+        dev::bloom_add(j.bits, j.mask, j.vals[i]);
 }
 
 static bool need_count(tid_table *t, Needs &needs) {
@@ -370,21 +513,94 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
 std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph *g,
                                                   const tid_plan *const *plans, int nq) {
     std::vector<PlanRun> runs(nq);
-    for (int i = 0; i < nq; ++i) compile_plan(plans[i], runs[i]);
-    std::vector<tid_pattern> all;
-    std::vector<PatternSet> all_sets;
-    std::vector<std::pair<int, int>> where;
-    for (int i = 0; i < nq; ++i)
-        for (size_t s = 0; s < runs[i].scans.size(); ++s) {
-            all.push_back(runs[i].scans[s]);
-            all_sets.push_back(runs[i].sets[s]);
-            where.emplace_back(i, (int)s);
+    int nrounds = 1;
+    for (int i = 0; i < nq; ++i) {
+        compile_plan(plans[i], runs[i]);
+        if (ctx->opt.semijoin) plan_rounds(g, runs[i], (uint64_t)ctx->opt.semijoin_min);
+        for (const ScanRound &sr : runs[i].rounds) nrounds = std::max(nrounds, sr.round + 1);
+    }
+    // Scans in rounds: each round's patterns of all plans share passes over
+    // the graph; a filtered scan's Bloom filter is built from its source
+    // table, which an earlier round produced.
+    for (int rd = 0; rd < nrounds; ++rd) {
+        std::vector<tid_pattern> all;
+        std::vector<PatternSet> all_sets;
+        std::vector<ScanFilter> all_filters;
+        std::vector<std::pair<int, int>> where;
+        std::vector<tid_table *> sources;
+        for (int i = 0; i < nq; ++i)
+            for (size_t s = 0; s < runs[i].scans.size(); ++s) {
+                const ScanRound &sr = runs[i].rounds[s];
+                if (sr.round != rd) continue;
+                all.push_back(runs[i].scans[s]);
+                all_sets.push_back(runs[i].sets[s]);
+                all_filters.emplace_back();
+                where.emplace_back(i, (int)s);
+                if (sr.src >= 0) sources.push_back(runs[i].scanned[sr.src].get());
+            }
+        if (all.empty()) continue;
+        resolve_counts(ctx, sources.data(), (int)sources.size());
+        // size the filters: 16 bits per source row, a power of two in [2^12, 2^28]
+        std::vector<BloomJob> jobs;
+        std::vector<size_t> at;
+        size_t words = 0;
+        for (size_t j = 0; j < all.size(); ++j) {
+            const ScanRound &sr = runs[where[j].first].rounds[where[j].second];
+            if (sr.src < 0) continue;
+            const tid_table *S = runs[where[j].first].scanned[sr.src].get();
+            const int c = col_of(S, sr.var);
+            TID_REQUIRE(c >= 0, TID_E_INTERNAL, "semi-join: source lacks the variable");
+            uint64_t bits = 4096;
+            while (bits < 16 * S->nrows && bits < (1ull << 28)) bits <<= 1;
+            jobs.push_back(BloomJob{S->col[c], S->nrows, nullptr, (uint32_t)(bits - 1)});
+            at.push_back(j);
+            all_filters[j].pos = position_of(all[j], sr.var);
+            all_filters[j].mask = (uint32_t)(bits - 1);
+            words += bits / 32;
         }
-    if (!all.empty()) {
-        std::vector<std::unique_ptr<tid_table>> outs(all.size());
-        scan_many(ctx, g, all.data(), (int)all.size(), outs.data(), all_sets.data());
+        DevBuf filter_bits(ctx, words * 4), job_table(ctx, jobs.size() * sizeof(BloomJob));
+        if (!jobs.empty()) {
+            size_t w = 0;
+            uint64_t most = 0;
+            for (size_t x = 0; x < jobs.size(); ++x) {
+                jobs[x].bits = filter_bits.get<uint32_t>() + w;
+                all_filters[at[x]].bits = jobs[x].bits;
+                w += ((uint64_t)jobs[x].mask + 1) / 32;
+                most = std::max(most, jobs[x].n);
+            }
+            TID_HIP(hipMemsetAsync(filter_bits.get(), 0, words * 4, ctx->stream));
+            TID_HIP(hipMemcpyAsync(job_table.get(), jobs.data(), jobs.size() * sizeof(BloomJob),
+                                   hipMemcpyHostToDevice, ctx->stream));
+            const unsigned gx = (unsigned)std::max<uint64_t>(
+                1, std::min<uint64_t>((most + 255) / 256, 256));
+            for (size_t y0 = 0; y0 < jobs.size(); y0 += 65535) {
+                const unsigned gy = (unsigned)std::min<size_t>(65535, jobs.size() - y0);
+                hipLaunchKernelGGL(bloom_build, dim3(gx, gy), dim3(256), 0, ctx->stream,
+                                   job_table.get<const BloomJob>() + y0);
+                TID_HIP(hipGetLastError());
+            }
+        }
+        // identical scans (across plans) run once; the others alias the result
+        std::map<std::string, size_t> uniq;
+        std::vector<size_t> rep(all.size());
+        std::vector<tid_pattern> upats;
+        std::vector<PatternSet> usets;
+        std::vector<ScanFilter> ufilters;
+        for (size_t j = 0; j < all.size(); ++j) {
+            const auto ins =
+                uniq.emplace(scan_key(all[j], all_sets[j], all_filters[j]), upats.size());
+            rep[j] = ins.first->second;
+            if (ins.second) {
+                upats.push_back(all[j]);
+                usets.push_back(all_sets[j]);
+                ufilters.push_back(all_filters[j]);
+            }
+        }
+        std::vector<std::unique_ptr<tid_table>> outs(upats.size());
+        scan_many(ctx, g, upats.data(), (int)upats.size(), outs.data(), usets.data(),
+                  ufilters.data());
         for (size_t j = 0; j < all.size(); ++j)
-            runs[where[j].first].scanned[where[j].second] = std::move(outs[j]);
+            runs[where[j].first].scanned[where[j].second] = alias_table(outs[rep[j]].get(), all[j]);
     }
     for (;;) {
         Needs needs;

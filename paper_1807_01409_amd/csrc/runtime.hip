@@ -81,8 +81,8 @@ std::unique_ptr<tid_table> make_table(tid_ctx *ctx, int32_t ncols, const int32_t
     t->cap = cap;
     const size_t stride = align_up(std::max<uint64_t>(cap, 1) * sizeof(uint32_t));
     const size_t bytes = stride * (size_t)ncols + kAlign;
-    t->block = DevBuf(ctx, bytes);
-    char *base = t->block.get<char>();
+    t->block = std::make_shared<DevBuf>(ctx, bytes);
+    char *base = t->block->get<char>();
     for (int c = 0; c < ncols; ++c) t->col[c] = reinterpret_cast<uint32_t *>(base + stride * c);
     t->d_count = reinterpret_cast<uint64_t *>(base + stride * (size_t)ncols);
     return t;

@@ -36,6 +36,9 @@ struct DevPattern {
     int32_t set_pos;  // -1: no value set; else the value there is one of set[0..nset)
     int32_t nset;
     uint32_t set[kMaxSet];
+    const uint32_t *fbits;  // membership filter on position fpos (-1: none)
+    uint32_t fmask;
+    int32_t fpos;
 };
 
 template <int MAXK>
@@ -69,6 +72,7 @@ __device__ __forceinline__ bool match_pattern(const DevPattern &q, const Tri &t)
         for (int i = 0; i < q.nset; ++i) in |= x == q.set[i];
         ok &= in;
     }
+    if (ok && q.fpos >= 0) ok = dev::bloom_has(q.fbits, q.fmask, pick(t, q.fpos));
     return ok;
 }
 
@@ -353,9 +357,17 @@ int pattern_schema(const tid_pattern &p, int32_t *vars, int32_t *src) {
     return k;
 }
 
-static DevPattern compile_pattern(const tid_pattern &p, const PatternSet *set = nullptr) {
+static DevPattern compile_pattern(const tid_pattern &p, const PatternSet *set = nullptr,
+                                  const ScanFilter *filter = nullptr) {
     DevPattern d{};
     d.set_pos = -1;
+    d.fpos = -1;
+    if (filter && filter->pos >= 0) {
+        TID_REQUIRE(filter->pos <= 2 && filter->bits, TID_E_INTERNAL, "scan filter: bad position");
+        d.fbits = filter->bits;
+        d.fmask = filter->mask;
+        d.fpos = filter->pos;
+    }
     int32_t vars[3], src[3];
     d.ncols = pattern_schema(p, vars, src);
     const uint32_t c[3] = {p.s, p.p, p.o};
@@ -429,13 +441,14 @@ static uint32_t stage_words(tid_ctx *ctx) {
 // One pass over the graph for k patterns into the given tables.
 template <int MAXK>
 static void run_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                     tid_table *const *outs, const PatternSet *sets) {
+                     tid_table *const *outs, const PatternSet *sets, const ScanFilter *filters) {
     ScanSrc<MAXK> src{};
     src.g = g->data.get<const uint32_t>();
     src.n = g->n;
     CompactArgs<MAXK, 3> a{};
     for (int j = 0; j < k; ++j) {
-        src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr);
+        src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr,
+                                     filters ? &filters[j] : nullptr);
         for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
         a.out[j].cap = outs[j]->cap;
         a.out[j].count = outs[j]->d_count;
@@ -500,13 +513,15 @@ static void launch_multi(tid_ctx *ctx, const tid_graph *g, MultiArgs &a, int k, 
 // Up to MAXK patterns in the generic compaction kernel, fully unrolled.
 template <int MAXK, int B, int I>
 static void run_unrolled(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                         tid_table *const *outs, const PatternSet *sets) {
+                         tid_table *const *outs, const PatternSet *sets,
+                         const ScanFilter *filters) {
     ScanSrc<MAXK> src{};
     src.g = g->data.get<const uint32_t>();
     src.n = g->n;
     CompactArgs<MAXK, 3> a{};
     for (int j = 0; j < k; ++j) {
-        src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr);
+        src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr,
+                                     filters ? &filters[j] : nullptr);
         for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
         a.out[j].cap = outs[j]->cap;
         a.out[j].count = outs[j]->d_count;
@@ -517,13 +532,14 @@ static void run_unrolled(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pa
 
 template <int MAXK>
 static void run_unrolled_shape(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                               tid_table *const *outs, int shape, const PatternSet *sets) {
+                               tid_table *const *outs, int shape, const PatternSet *sets,
+                               const ScanFilter *filters) {
     if (shape == 1)
-        run_unrolled<MAXK, 256, 8>(ctx, g, pats, k, outs, sets);
+        run_unrolled<MAXK, 256, 8>(ctx, g, pats, k, outs, sets, filters);
     else if (shape == 2)
-        run_unrolled<MAXK, 256, 16>(ctx, g, pats, k, outs, sets);
+        run_unrolled<MAXK, 256, 16>(ctx, g, pats, k, outs, sets, filters);
     else
-        run_unrolled<MAXK, 512, 8>(ctx, g, pats, k, outs, sets);
+        run_unrolled<MAXK, 512, 8>(ctx, g, pats, k, outs, sets, filters);
 }
 
 // multi_kernel option: 0 (default) the unrolled kernel for up to 4 patterns,
@@ -535,9 +551,10 @@ static void run_unrolled_shape(tid_ctx *ctx, const tid_graph *g, const tid_patte
 // eight patterns of ~1% selectivity.  multi_shape 0 is 512 threads x 8
 // triples for both.
 static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                         tid_table *const *outs, const PatternSet *sets) {
+                         tid_table *const *outs, const PatternSet *sets,
+                         const ScanFilter *filters) {
     if (k == 1) {
-        run_scan<1>(ctx, g, pats, k, outs, sets);
+        run_scan<1>(ctx, g, pats, k, outs, sets, filters);
         return;
     }
     const int shape = (int)ctx->opt.multi_shape;
@@ -546,19 +563,21 @@ static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pa
         for (int p0 = 0, p = 0; p < passes; ++p) {
             const int m = (k - p0) / (passes - p);
             const PatternSet *ps = sets ? sets + p0 : nullptr;
+            const ScanFilter *pf = filters ? filters + p0 : nullptr;
             if (m == 1)
-                run_scan<1>(ctx, g, pats + p0, 1, outs + p0, ps);
+                run_scan<1>(ctx, g, pats + p0, 1, outs + p0, ps, pf);
             else if (m == 2)
-                run_unrolled_shape<2>(ctx, g, pats + p0, m, outs + p0, shape, ps);
+                run_unrolled_shape<2>(ctx, g, pats + p0, m, outs + p0, shape, ps, pf);
             else
-                run_unrolled_shape<4>(ctx, g, pats + p0, m, outs + p0, shape, ps);
+                run_unrolled_shape<4>(ctx, g, pats + p0, m, outs + p0, shape, ps, pf);
             p0 += m;
         }
         return;
     }
     MultiArgs a{};
     for (int j = 0; j < k; ++j) {
-        a.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr);
+        a.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr,
+                                   filters ? &filters[j] : nullptr);
         for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
         a.out[j].cap = outs[j]->cap;
         a.out[j].count = outs[j]->d_count;
@@ -577,13 +596,14 @@ static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pa
 
 bool wide_eligible(const tid_pattern &p);
 void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-              tid_table *const *outs);
+              tid_table *const *outs, const ScanFilter *filters);
 
 // Any number of patterns: those with a constant (bucketable) predicate go
 // through wide passes of up to 1024 patterns when there are at least
 // `wide_min` of them; the rest through passes of up to 16.
 void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-               std::unique_ptr<tid_table> *outs, const PatternSet *sets) {
+               std::unique_ptr<tid_table> *outs, const PatternSet *sets,
+               const ScanFilter *filters) {
     const int64_t wide_min = ctx->opt.wide_min > 0 ? ctx->opt.wide_min : 32;
     std::vector<int> wide, rest;
     for (int j = 0; j < k; ++j) {
@@ -598,6 +618,7 @@ void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
     for (size_t w0 = 0; w0 < wide.size(); w0 += 1024) {
         const int m = (int)std::min<size_t>(1024, wide.size() - w0);
         std::vector<tid_pattern> wp(m);
+        std::vector<ScanFilter> wf(m);
         std::vector<tid_table *> wt(m);
         for (int j = 0; j < m; ++j) {
             const tid_pattern &p = pats[wide[w0 + j]];
@@ -607,27 +628,31 @@ void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
             for (int c = 0; c < nc; ++c) t->maxv[c] = g->max_id[src[c]];
             t->maxv_known = true;
             wp[j] = p;
+            if (filters) wf[j] = filters[wide[w0 + j]];
             wt[j] = t.get();
             outs[wide[w0 + j]] = std::move(t);
         }
-        run_wide(ctx, g, wp.data(), m, wt.data());
+        run_wide(ctx, g, wp.data(), m, wt.data(), wf.data());
     }
     for (size_t r0 = 0; r0 < rest.size(); r0 += TID_MAX_MULTI) {
         const int m = (int)std::min<size_t>(TID_MAX_MULTI, rest.size() - r0);
         std::vector<tid_pattern> rp(m);
         std::vector<PatternSet> rs(m);
+        std::vector<ScanFilter> rf(m);
         std::unique_ptr<tid_table> rt[TID_MAX_MULTI];
         for (int j = 0; j < m; ++j) {
             rp[j] = pats[rest[r0 + j]];
             if (sets) rs[j] = sets[rest[r0 + j]];
+            if (filters) rf[j] = filters[rest[r0 + j]];
         }
-        scan_multi(ctx, g, rp.data(), m, rt, rs.data());
+        scan_multi(ctx, g, rp.data(), m, rt, rs.data(), rf.data());
         for (int j = 0; j < m; ++j) outs[rest[r0 + j]] = std::move(rt[j]);
     }
 }
 
 void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                std::unique_ptr<tid_table> *outs, const PatternSet *sets) {
+                std::unique_ptr<tid_table> *outs, const PatternSet *sets,
+                const ScanFilter *filters) {
     TID_REQUIRE(k >= 1 && k <= TID_MAX_MULTI, TID_E_INVALID_ARG, "scan: 1..16 patterns per pass");
     std::vector<uint64_t> bound(k);
     for (int j = 0; j < k; ++j) {
@@ -646,7 +671,7 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
     }
     std::vector<tid_table *> raw(k);
     for (int j = 0; j < k; ++j) raw[j] = outs[j].get();
-    run_scan_any(ctx, g, pats, k, raw.data(), sets);
+    run_scan_any(ctx, g, pats, k, raw.data(), sets, filters);
 
     // Outputs sized by the histogram bound cannot overflow.  A smaller
     // capacity (forced for tests) is checked and, if allowed, run again at
@@ -662,6 +687,7 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
     TID_REQUIRE(ctx->opt.retry, TID_E_CAPACITY, "scan: result exceeds the output capacity");
     std::vector<tid_pattern> rp;
     std::vector<PatternSet> rs;
+    std::vector<ScanFilter> rf;
     std::vector<tid_table *> rt;
     for (int j : redo) {
         const uint64_t need = outs[j]->nrows;
@@ -671,9 +697,10 @@ void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k
         outs[j] = std::move(bigger);
         rp.push_back(pats[j]);
         rs.push_back(sets ? sets[j] : PatternSet{});
+        rf.push_back(filters ? filters[j] : ScanFilter{});
         rt.push_back(outs[j].get());
     }
-    run_scan_any(ctx, g, rp.data(), (int)rp.size(), rt.data(), rs.data());
+    run_scan_any(ctx, g, rp.data(), (int)rp.size(), rt.data(), rs.data(), rf.data());
 }
 
 // ---------------------------------------------------------------------------

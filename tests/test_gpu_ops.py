@@ -241,3 +241,44 @@ def test_union_of_scans(ctx, graphs):
     plans = [union_plan(pp, d) for pp, d in cases[:4]]
     for t, plan in zip(ctx.query_batch(G, plans), plans):
         same(t, oracle.query(g, plan))
+
+
+@pytest.mark.parametrize("semijoin_min", [0, 1 << 16])
+def test_semijoin_reduced_plans(ctx, graphs, semijoin_min):
+    """Star and chain plans of the batched mix with semi-join rounds (forced on
+    every scan by a zero threshold, and at the default threshold) equal the
+    oracle, alone and in a batch."""
+    from synth.batch import PredIndex, batch_queries
+    g = graphs("small")
+    G = ctx.load(g)
+    plans, _ = batch_queries(PredIndex(g), nq=64, seed=7, max_rows=1 << 16, workers=1)
+    ctx.set_option("semijoin_min", semijoin_min)
+    try:
+        for p in plans:
+            same(ctx.query(G, p), oracle.query(g, p))
+        for t, p in zip(ctx.query_batch(G, plans), plans):
+            same(t, oracle.query(g, p))
+    finally:
+        ctx.set_option("semijoin_min", 1 << 16)
+
+
+def test_semijoin_random_plans(ctx):
+    """Random plans (joins, unions, filters, projections, DISTINCT) with the
+    reduction forced wherever a plan is conjunctive, and switched off: both
+    equal the oracle."""
+    rng = np.random.default_rng(77)
+    try:
+        for i in range(120):
+            g = tiny_graph(900 + i, int(rng.integers(1, 40)), 4)
+            plan = random_plan(rng)
+            G = ctx.load(g)
+            want = oracle.query(g, plan)
+            ctx.set_option("semijoin_min", 0)
+            same(ctx.query(G, plan), want)
+            ctx.set_option("semijoin", 0)
+            same(ctx.query(G, plan), want)
+            ctx.set_option("semijoin", 1)
+            G.free()
+    finally:
+        ctx.set_option("semijoin", 1)
+        ctx.set_option("semijoin_min", 1 << 16)
