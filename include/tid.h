@@ -90,6 +90,9 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           from a ticket and place each chunk one chunk
                           later); 0 (default): block-ranged when the output
                           bound per range is small, chunked otherwise
+     "range_factor"       block-ranged compaction: ranges per resident
+                          workgroup, 1..8 (default 1; more ranges measured
+                          slower on 50M and 200M triples)
      "semijoin"           1 (default): in a conjunctive plan (only SCAN, JOIN
                           and FILTER up to its last JOIN, no UNION), large
                           scans run after a smaller scan sharing a variable

@@ -127,6 +127,9 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
         } else if (k == "multi_shape") {
             TID_REQUIRE(value >= 0 && value <= 3, TID_E_INVALID_ARG, "multi_shape is 0..3");
             ctx->opt.multi_shape = value;
+        } else if (k == "range_factor") {
+            TID_REQUIRE(value >= 1 && value <= 8, TID_E_INVALID_ARG, "range_factor is 1..8");
+            ctx->opt.range_factor = value;
         } else if (k == "semijoin") {
             ctx->opt.semijoin = value ? 1 : 0;
         } else if (k == "semijoin_min") {
@@ -171,6 +174,7 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "compact_kernel") *value = ctx->opt.compact_kernel;
         else if (k == "chunk_epoch") *value = ctx->epoch;
         else if (k == "semijoin") *value = ctx->opt.semijoin;
+        else if (k == "range_factor") *value = ctx->opt.range_factor;
         else if (k == "semijoin_min") *value = ctx->opt.semijoin_min;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });

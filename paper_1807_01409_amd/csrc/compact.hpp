@@ -711,7 +711,8 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
     if (kind == 0) {
         const uint64_t ranges = std::max<uint64_t>(
             1, std::min<uint64_t>({(n + TILE - 1) / TILE,
-                                   (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx),
+                                   (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx) *
+                                       (uint64_t)std::max<int64_t>(1, ctx->opt.range_factor),
                                    (uint64_t)BLOCK * kPrefixPer}));
         // One output: chunked where the block-ranged staging would overflow
         // (that kernel would then re-read the graph); block-ranged otherwise
@@ -732,7 +733,8 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
         off += rows_per * (uint32_t)a.out[j].ncols;
     }
     const uint64_t tiles = (n + TILE - 1) / TILE;
-    const uint64_t resident = (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx);
+    const uint64_t resident = (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx) *
+                              (uint64_t)std::max<int64_t>(1, ctx->opt.range_factor);
     uint64_t P = std::max<uint64_t>(1, std::min({tiles, resident, (uint64_t)BLOCK * kPrefixPer}));
     const uint64_t range = (tiles + P - 1) / P * TILE;
     P = (n + range - 1) / range;

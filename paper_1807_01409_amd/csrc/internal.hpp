@@ -63,6 +63,7 @@ struct Options {
     int64_t multi_shape = 0;     // launch shape index of the chosen multi-pattern kernel
     int64_t compact_kernel = 0;  // 0 auto, 1 block-ranged, 2 chunked compaction
     int64_t semijoin = 1;        // filter scans of conjunctive plans by join values
+    int64_t range_factor = 1;    // block-ranged kernel: ranges per resident workgroup
     int64_t semijoin_min = 1 << 16;  // rows a scan's bound needs before it is filtered
 };
 
