@@ -107,7 +107,16 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           so that tests can reach the wrap)
      "wide_min"           a plan batch with at least this many patterns of
                           constant predicate uses the bucketed wide pass
-                          (0 = default 32) */
+                          (0 = default 32)
+     "wide_slice"         1 (default): in a wide pass, a predicate that at
+                          least two of its patterns share, with at least
+                          "slice_rows" triples, is sliced: the graph pass
+                          writes the predicate's (s, o) rows once, in triple
+                          order, and a pass over that slice alone fills the
+                          predicate's patterns (same tables); 0: every pattern
+                          is tested in the graph pass
+     "slice_rows"         triples a predicate needs to be sliced (0 = default:
+                          the larger of 65536 and 1/4096 of the graph) */
 tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value);
 tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value);
 

@@ -135,6 +135,11 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
         } else if (k == "semijoin_min") {
             TID_REQUIRE(value >= 0, TID_E_INVALID_ARG, "semijoin_min must be >= 0");
             ctx->opt.semijoin_min = value;
+        } else if (k == "wide_slice") {
+            ctx->opt.wide_slice = value ? 1 : 0;
+        } else if (k == "slice_rows") {
+            TID_REQUIRE(value >= 0, TID_E_INVALID_ARG, "slice_rows must be >= 0");
+            ctx->opt.slice_rows = value;
         } else if (k == "chunk_epoch") {
             TID_REQUIRE(value >= 0 && value <= (int64_t)tid::kEpochMax, TID_E_INVALID_ARG,
                         "chunk_epoch is 0..2^23-1");
@@ -176,6 +181,8 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "semijoin") *value = ctx->opt.semijoin;
         else if (k == "range_factor") *value = ctx->opt.range_factor;
         else if (k == "semijoin_min") *value = ctx->opt.semijoin_min;
+        else if (k == "wide_slice") *value = ctx->opt.wide_slice;
+        else if (k == "slice_rows") *value = ctx->opt.slice_rows;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });
 }

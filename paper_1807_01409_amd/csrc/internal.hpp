@@ -65,6 +65,8 @@ struct Options {
     int64_t semijoin = 1;        // filter scans of conjunctive plans by join values
     int64_t range_factor = 1;    // block-ranged kernel: ranges per resident workgroup
     int64_t semijoin_min = 1 << 16;  // rows a scan's bound needs before it is filtered
+    int64_t wide_slice = 1;      // wide passes slice predicates shared by patterns
+    int64_t slice_rows = 0;      // rows a predicate needs to be sliced (0 = default)
 };
 
 }  // namespace tid

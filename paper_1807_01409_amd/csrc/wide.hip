@@ -13,7 +13,11 @@
 //     offset for the sub-range plus its rank: ascending triple position per
 //     pattern, as a single-pattern scan gives.
 // The graph is read twice per pass; the work per triple is the size of its
-// predicate's bucket.
+// predicate's bucket, and a wave steps through the longest bucket among its
+// lanes.  A predicate that many patterns of one pass share is therefore
+// sliced: the graph pass writes that predicate's (s, o) rows once, in triple
+// order, in place of its patterns, and a second pass over the slice alone
+// tests them, every lane on the same predicate.
 #include "compact.hpp"
 
 #include <algorithm>
@@ -49,7 +53,9 @@ struct WideOut {
 };
 
 struct WideArgs {
-    const uint32_t *g;
+    const uint32_t *g;          // AoS triples (graph pass)
+    const uint32_t *ss, *so;    // slice pass: subject and object columns ...
+    uint32_t sp;                // ... of the rows whose predicate is sp
     uint64_t n;
     const WidePat *pats;      // k
     const uint32_t *bucket;   // kWidePreds words: start << 12 | len
@@ -78,8 +84,14 @@ __device__ __forceinline__ bool wide_match(const WidePat &q, const WTri &t) {
     return ok;
 }
 
+// Lanes that match the same pattern id as the calling lane (0 if it matches
+// none).  No ballots beyond the first when nothing matched, and one more when
+// every matching lane tests the same pattern (always so in a slice pass).
 __device__ __forceinline__ uint64_t match_pid(uint32_t pid, bool m) {
     uint64_t peers = dev::ballot(m);
+    if (peers == 0) return 0;
+    const uint32_t lead = __builtin_amdgcn_readlane(pid, __builtin_ctzll(peers));
+    if (dev::ballot(m && pid != lead) == 0) return m ? peers : 0;
 #pragma unroll
     for (int b = 0; b < kWideIdBits; ++b) {
         const bool bit = (pid >> b) & 1u;
@@ -103,7 +115,20 @@ __device__ __forceinline__ void wide_setup(const WideArgs &a, WidePat *s_pat, ui
 // wave's running count of that pattern (s_run) advances by the number of
 // lanes matching it in the same step; the write pass (WRITE) also stores the
 // binding at that running count plus the lane's rank among them.
-template <bool WRITE>
+// triple i of the pass's source
+template <bool SLICE>
+__device__ __forceinline__ WTri wide_load(const WideArgs &a, uint64_t i) {
+    if (SLICE) {
+        WTri t;
+        t.v[0] = a.ss[i];
+        t.v[1] = a.sp;
+        t.v[2] = a.so[i];
+        return t;
+    }
+    return *reinterpret_cast<const WTri *>(a.g + 3 * i);
+}
+
+template <bool WRITE, bool SLICE>
 __device__ __forceinline__ void wide_walk(const WideArgs &a, const WidePat *s_pat,
                                           const uint32_t *s_bucket, const uint16_t *s_ids,
                                           uint32_t *s_run, uint64_t r0, uint64_t r1,
@@ -115,7 +140,7 @@ __device__ __forceinline__ void wide_walk(const WideArgs &a, const WidePat *s_pa
 #pragma unroll
         for (int it = 0; it < kWideIPT; ++it) {
             const uint64_t i = t0 + (uint64_t)it * dev::kWave + lane;
-            if (i < r1) t[it] = *reinterpret_cast<const WTri *>(a.g + 3 * i);
+            if (i < r1) t[it] = wide_load<SLICE>(a, i);
             else t[it].v[0] = t[it].v[1] = t[it].v[2] = 0;
         }
 #pragma unroll
@@ -173,6 +198,7 @@ __device__ __forceinline__ WideLds wide_lds(uint32_t *lds, int k) {
     return l;
 }
 
+template <bool SLICE>
 __global__ __launch_bounds__(kWideBlock) void wide_count(WideArgs a, uint32_t *flags) {
     extern __shared__ uint32_t lds[];
     const WideLds l = wide_lds(lds, a.k);
@@ -188,7 +214,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_count(WideArgs a, uint32_t *f
     const uint32_t gw = blockIdx.x * kWideNW + wave;
     if (gw < a.W) {
         const uint64_t r0 = (uint64_t)gw * a.sub, r1 = min(a.n, r0 + a.sub);
-        wide_walk<false>(a, s_pat, s_bucket, s_ids, run, r0, r1, flags);
+        wide_walk<false, SLICE>(a, s_pat, s_bucket, s_ids, run, r0, r1, flags);
         for (int j = lane; j < a.k; j += dev::kWave) a.cnt[(size_t)gw * a.k + j] = run[j];
     }
 }
@@ -224,6 +250,7 @@ __global__ __launch_bounds__(kColBlock) void wide_offsets(WideArgs a) {
     }
 }
 
+template <bool SLICE>
 __global__ __launch_bounds__(kWideBlock) void wide_write(WideArgs a, uint32_t *flags) {
     extern __shared__ uint32_t lds[];
     const WideLds l = wide_lds(lds, a.k);
@@ -240,7 +267,7 @@ __global__ __launch_bounds__(kWideBlock) void wide_write(WideArgs a, uint32_t *f
     __syncthreads();
     if (gw < a.W) {
         const uint64_t r0 = (uint64_t)gw * a.sub, r1 = min(a.n, r0 + a.sub);
-        wide_walk<true>(a, s_pat, s_bucket, s_ids, run, r0, r1, flags);
+        wide_walk<true, SLICE>(a, s_pat, s_bucket, s_ids, run, r0, r1, flags);
     }
 }
 
@@ -280,17 +307,39 @@ static size_t wide_lds_bytes(int k) {
            4 * (size_t)kWideNW * (size_t)k;
 }
 
-// One wide pass for k <= kWideMax eligible patterns into preallocated tables.
-void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-              tid_table *const *outs, const ScanFilter *filters) {
+// What one pass reads: the graph, or the (s, o) slice of one predicate.
+struct WideSource {
+    const uint32_t *g = nullptr;
+    const uint32_t *s = nullptr, *o = nullptr;
+    uint32_t p = 0;
+    uint64_t n = 0;
+};
+
+template <bool SLICE>
+static void set_wide_lds_limit() {
+    static bool done = false;
+    if (done) return;  // allow up to 160 KB of dynamic LDS per workgroup
+    TID_HIP(hipFuncSetAttribute((const void *)wide_count<SLICE>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    TID_HIP(hipFuncSetAttribute((const void *)wide_write<SLICE>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    done = true;
+}
+
+// One pass for k <= kWideMax eligible patterns into preallocated tables.  In
+// a slice pass every pattern has the slice's predicate.
+static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pats, int k,
+                      tid_table *const *outs, const ScanFilter *filters) {
     TID_REQUIRE(k >= 1 && k <= kWideMax, TID_E_INTERNAL, "wide pass: bad pattern count");
+    const bool slice = src.g == nullptr;
     std::vector<WidePat> wp(k);
     std::vector<WideOut> wo(k);
     std::vector<WideFilter> wf(k);
     std::vector<uint64_t *> wc(k);
     std::vector<std::vector<uint16_t>> by_pred(kWidePreds);
     for (int j = 0; j < k; ++j) {
-        TID_REQUIRE(wide_eligible(pats[j]), TID_E_INTERNAL, "wide pass: pattern not eligible");
+        TID_REQUIRE(wide_eligible(pats[j]) && (!slice || pats[j].p == src.p), TID_E_INTERNAL,
+                    "wide pass: pattern not eligible");
         wp[j] = compile_wide(pats[j]);
         wf[j] = WideFilter{nullptr, 0u, -1};
         if (filters && filters[j].pos >= 0) {
@@ -329,26 +378,25 @@ void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
     char *d = dconst.get<char>();
 
     const size_t lds = wide_lds_bytes(k);
-    static bool attr_set = false;
-    if (!attr_set) {  // allow up to 160 KB of dynamic LDS per workgroup
-        TID_HIP(hipFuncSetAttribute((const void *)wide_count,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        TID_HIP(hipFuncSetAttribute((const void *)wide_write,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-        attr_set = true;
-    }
-    const int per_cu = resident_blocks((const void *)wide_write, kWideBlock, lds);
+    const void *count_fn = slice ? (const void *)wide_count<true> : (const void *)wide_count<false>;
+    const void *write_fn = slice ? (const void *)wide_write<true> : (const void *)wide_write<false>;
+    if (slice) set_wide_lds_limit<true>();
+    else set_wide_lds_limit<false>();
+    const int per_cu = resident_blocks(write_fn, kWideBlock, lds);
     const uint64_t waves = (uint64_t)per_cu * device_cus(ctx) * kWideNW;
     const uint64_t unit = (uint64_t)dev::kWave * kWideIPT;
-    const uint64_t units = (g->n + unit - 1) / unit;
+    const uint64_t units = (src.n + unit - 1) / unit;
     uint64_t W = std::max<uint64_t>(1, std::min(units, waves));
     const uint64_t sub = (units + W - 1) / W * unit;
-    W = (g->n + sub - 1) / sub;
+    W = std::max<uint64_t>(1, (src.n + sub - 1) / sub);
     DevBuf cnt(ctx, (size_t)W * k * 4);
 
     WideArgs a{};
-    a.g = g->data.get<const uint32_t>();
-    a.n = g->n;
+    a.g = src.g;
+    a.ss = src.s;
+    a.so = src.o;
+    a.sp = src.p;
+    a.n = src.n;
     a.pats = reinterpret_cast<const WidePat *>(d);
     a.bucket = reinterpret_cast<const uint32_t *>(d + b_pats);
     a.ids = reinterpret_cast<const uint16_t *>(d + b_pats + b_bucket);
@@ -362,15 +410,84 @@ void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
     a.W = (uint32_t)W;
     a.cnt = cnt.get<uint32_t>();
     const unsigned blocks = (unsigned)((W + kWideNW - 1) / kWideNW);
-    hipLaunchKernelGGL(wide_count, dim3(blocks), dim3(kWideBlock), lds, ctx->stream, a,
-                       ctx->d_flags);
+    void *args[] = {&a, &ctx->d_flags};
+    TID_HIP(hipLaunchKernel(count_fn, dim3(blocks), dim3(kWideBlock), args, lds, ctx->stream));
     TID_HIP(hipGetLastError());
     hipLaunchKernelGGL(wide_offsets, dim3((unsigned)((k + dev::kWave - 1) / dev::kWave)),
                        dim3(kColBlock), 0, ctx->stream, a);
     TID_HIP(hipGetLastError());
-    hipLaunchKernelGGL(wide_write, dim3(blocks), dim3(kWideBlock), lds, ctx->stream, a,
-                       ctx->d_flags);
-    TID_HIP(hipGetLastError());
+    TID_HIP(hipLaunchKernel(write_fn, dim3(blocks), dim3(kWideBlock), args, lds, ctx->stream));
+}
+
+// One wide pass over the graph for k <= kWideMax eligible patterns.  Each
+// predicate with at least two of the patterns and, by the histograms, at
+// least the slice threshold's rows is sliced: the graph pass carries one
+// (?s p ?o) pattern for it instead, into a temporary two-column table, and a
+// slice pass over that table then fills the predicate's own patterns.  Both
+// keep triple order, so every table comes out as the graph pass alone would
+// write it.
+void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+              tid_table *const *outs, const ScanFilter *filters) {
+    WideSource whole;
+    whole.g = g->data.get<const uint32_t>();
+    whole.n = g->n;
+    std::vector<std::vector<int>> by_pred(kWidePreds);
+    for (int j = 0; j < k; ++j)
+        if (wide_eligible(pats[j])) by_pred[pats[j].p].push_back(j);
+    const uint64_t min_rows = ctx->opt.slice_rows > 0
+                                  ? (uint64_t)ctx->opt.slice_rows
+                                  : std::max<uint64_t>(uint64_t(1) << 16, g->n >> 12);
+    std::vector<uint32_t> sliced;
+    if (ctx->opt.wide_slice && !g->cdf[1].empty())
+        for (uint32_t p = 1; p < kWidePreds; ++p)
+            if (by_pred[p].size() >= 2 && g->count_in(1, p, p + 1) >= min_rows) sliced.push_back(p);
+    if (sliced.empty()) {
+        wide_pass(ctx, whole, pats, k, outs, filters);
+        return;
+    }
+    std::vector<char> is_sliced(kWidePreds, 0);
+    for (uint32_t p : sliced) is_sliced[p] = 1;
+    std::vector<tid_pattern> gp;
+    std::vector<tid_table *> gt;
+    std::vector<ScanFilter> gf;
+    for (int j = 0; j < k; ++j) {
+        if (wide_eligible(pats[j]) && is_sliced[pats[j].p]) continue;
+        gp.push_back(pats[j]);
+        gt.push_back(outs[j]);
+        gf.push_back(filters ? filters[j] : ScanFilter{});
+    }
+    std::vector<std::unique_ptr<tid_table>> slices;
+    for (uint32_t p : sliced) {
+        tid_pattern v{};  // (?a p ?b): two projected columns, s then o
+        v.p = p;
+        v.vs = 0;
+        v.vp = -1;
+        v.vo = 1;
+        v.range_pos = -1;
+        const int32_t vars[2] = {0, 1};
+        slices.push_back(make_table(ctx, 2, vars, g->count_in(1, p, p + 1)));
+        gp.push_back(v);
+        gt.push_back(slices.back().get());
+        gf.push_back(ScanFilter{});
+    }
+    wide_pass(ctx, whole, gp.data(), (int)gp.size(), gt.data(), gf.data());
+    for (size_t i = 0; i < sliced.size(); ++i) {
+        const uint32_t p = sliced[i];
+        WideSource part;
+        part.s = slices[i]->col[0];
+        part.o = slices[i]->col[1];
+        part.p = p;
+        part.n = slices[i]->cap;  // the histogram count is exact
+        std::vector<tid_pattern> sp;
+        std::vector<tid_table *> st;
+        std::vector<ScanFilter> sf;
+        for (int j : by_pred[p]) {
+            sp.push_back(pats[j]);
+            st.push_back(outs[j]);
+            sf.push_back(filters ? filters[j] : ScanFilter{});
+        }
+        wide_pass(ctx, part, sp.data(), (int)sp.size(), st.data(), sf.data());
+    }
 }
 
 }  // namespace tid

@@ -282,3 +282,68 @@ def test_semijoin_random_plans(ctx):
     finally:
         ctx.set_option("semijoin", 1)
         ctx.set_option("semijoin_min", 1 << 16)
+
+
+@pytest.mark.parametrize("slice_rows", [1, 0])
+def test_wide_slices(ctx, graphs, slice_rows):
+    """Single-scan plans sharing predicates, run as one batch through the wide
+    pass, with every shared predicate sliced (slice_rows 1) and at the default
+    threshold (no predicate of this graph reaches it), and with slicing off:
+    every table equals the oracle's.  The shapes cover bound subjects and
+    objects, a repeated variable, ranges on each position and projections."""
+    g = graphs("small")
+    G = ctx.load(g)
+    rng = np.random.default_rng(31)
+    preds = np.argsort(-np.bincount(g[:, 1]), kind="stable")[:3]
+    plans = []
+    for i in range(60):
+        p = int(preds[i % 3])
+        rows = g[g[:, 1] == p]
+        r = rows[int(rng.integers(rows.shape[0]))]
+        shape = i % 6
+        if shape == 0:
+            q = Pattern(0, p, 0, 0, -1, 1)
+        elif shape == 1:
+            q = Pattern(int(r[0]), p, 0, -1, -1, 0)
+        elif shape == 2:
+            q = Pattern(0, p, int(r[2]), 0, -1, -1)
+        elif shape == 3:
+            q = Pattern(0, p, 0, 0, -1, 0)
+        elif shape == 4:
+            lo = int(rng.integers(1, 5000))
+            q = Pattern(0, p, 0, 0, -1, 1, range_pos=int(rng.choice([0, 2])), lo=lo,
+                        hi=lo + int(rng.integers(1, 8000)))
+        else:
+            q = Pattern(0, p, 0, -1, -1, 0, range_pos=1, lo=p, hi=p + 1 + i % 2)
+        plans.append(Plan().scan(q))
+    try:
+        ctx.set_option("wide_min", 1)
+        for mode in ((1, slice_rows), (0, 0)):
+            ctx.set_option("wide_slice", mode[0])
+            ctx.set_option("slice_rows", mode[1])
+            for t, p in zip(ctx.query_batch(G, plans), plans):
+                same(t, oracle.query(g, p))
+    finally:
+        ctx.set_option("wide_min", 0)
+        ctx.set_option("wide_slice", 1)
+        ctx.set_option("slice_rows", 0)
+
+
+def test_wide_slices_semijoin_batch(ctx, graphs):
+    """The batched star/chain mix with semi-join rounds forced on every scan,
+    the wide pass forced on every round and every shared predicate sliced:
+    equal to the oracle."""
+    from synth.batch import PredIndex, batch_queries
+    g = graphs("small")
+    G = ctx.load(g)
+    plans, _ = batch_queries(PredIndex(g), nq=96, seed=11, max_rows=1 << 16, workers=1)
+    try:
+        ctx.set_option("semijoin_min", 0)
+        ctx.set_option("wide_min", 1)
+        ctx.set_option("slice_rows", 1)
+        for t, p in zip(ctx.query_batch(G, plans), plans):
+            same(t, oracle.query(g, p))
+    finally:
+        ctx.set_option("semijoin_min", 1 << 16)
+        ctx.set_option("wide_min", 0)
+        ctx.set_option("slice_rows", 0)
