@@ -251,7 +251,7 @@ struct PendingJoin {
     JoinPlan jp;
     std::vector<int32_t> vars;
     DevBuf start, count, off, keys[4], vals[4];
-    DevBuf slots, slot_of, slot_count, slot_start, cursor, rows;
+    DevBuf slots, slot_of, rank, slot_start, rows;  // slots: slot words, then counts
     const uint32_t *qrow = nullptr, *brow = nullptr;
     int probe_is_left = 1;
     uint64_t nq = 0;

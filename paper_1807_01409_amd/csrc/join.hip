@@ -115,10 +115,54 @@ __global__ __launch_bounds__(kScanBlock) void range_scan(const uint32_t *__restr
 
 __global__ void set_zero_u64(uint64_t *p) { *p = 0; }
 
+// The whole scan in one workgroup, tile by tile (small inputs: one launch).
+constexpr int kOneBlock = 1024;
+constexpr uint64_t kOneTile = (uint64_t)kOneBlock * kScanIPT;
+constexpr uint64_t kOneMax = 8 * kOneTile;
+__global__ __launch_bounds__(kOneBlock) void one_block_scan(const uint32_t *__restrict__ in,
+                                                            uint64_t n, uint64_t *out) {
+    __shared__ uint64_t s_w[kOneBlock / dev::kWave];
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    uint64_t carry = 0;
+    for (uint64_t t0 = 0; t0 < n; t0 += kOneTile) {
+        uint32_t v[kScanIPT];
+        uint64_t local = 0;
+#pragma unroll
+        for (int u = 0; u < kScanIPT; ++u) {
+            const uint64_t i = t0 + (uint64_t)tid * kScanIPT + u;
+            v[u] = i < n ? in[i] : 0u;
+            local += v[u];
+        }
+        const uint64_t incl = dev::wave_inclusive_sum(local);
+        if (lane == dev::kWave - 1) s_w[wave] = incl;
+        __syncthreads();
+        uint64_t before = carry, tile = 0;
+        for (int w = 0; w < kOneBlock / dev::kWave; ++w) {
+            if (w < wave) before += s_w[w];
+            tile += s_w[w];
+        }
+        uint64_t run = before + incl - local;
+#pragma unroll
+        for (int u = 0; u < kScanIPT; ++u) {
+            const uint64_t i = t0 + (uint64_t)tid * kScanIPT + u;
+            if (i < n) out[i] = run;
+            run += v[u];
+        }
+        carry += tile;
+        __syncthreads();  // s_w is rewritten by the next tile
+    }
+    if (tid == 0) out[n] = carry;
+}
+
 // out[0..n] = exclusive prefix sums of in[0..n); out[n] = total, left on the device.
 void exclusive_scan_async(tid_ctx *ctx, const uint32_t *in, uint64_t n, uint64_t *out) {
     if (n == 0) {
         hipLaunchKernelGGL(set_zero_u64, dim3(1), dim3(1), 0, ctx->stream, out);
+        TID_HIP(hipGetLastError());
+        return;
+    }
+    if (n <= kOneMax) {
+        hipLaunchKernelGGL(one_block_scan, dim3(1), dim3(kOneBlock), 0, ctx->stream, in, n, out);
         TID_HIP(hipGetLastError());
         return;
     }
@@ -179,34 +223,82 @@ __global__ void merge_counts(const uint64_t *qk, uint64_t nq, const uint64_t *bk
 // ---------------------------------------------------------------------------
 
 
-// slot words hold key + 1 (0 = empty)
-__global__ void hash_insert(const uint32_t *keys, uint64_t n, unsigned long long *slots,
-                            uint32_t mask, uint32_t *slot_of, uint32_t *slot_count) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const unsigned long long want = (unsigned long long)keys[i] + 1ull;
-        uint32_t h = dev::hash32(keys[i]) & mask;
-        for (uint32_t probe = 0; probe <= mask; ++probe) {
-            unsigned long long cur = slots[h];
-            if (cur == 0ull) cur = atomicCAS(&slots[h], 0ull, want);
-            if (cur == 0ull || cur == want) {
-                slot_of[i] = h;
-                atomicAdd(&slot_count[h], 1u);
-                break;
+// Build: every build row finds (or claims) its key's slot -- slot words hold
+// key + 1, 0 = empty -- and takes a rank among the rows of that slot.  The
+// ranks are reserved per workgroup round, not per row: the round's rows are
+// grouped by slot in an LDS table, and one global atomic per slot present
+// reserves that group's ranks, so a key held by many rows (a hub) costs one
+// global atomic per round instead of one per row.
+constexpr int kHashBlock = 256;
+constexpr int kHashIPT = 4;
+constexpr int kHashLds = 2048;  // entries; a round holds at most 1024 distinct slots
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
+__global__ __launch_bounds__(kHashBlock) void hash_insert(const uint32_t *keys, uint64_t n,
+                                                          unsigned long long *slots, uint32_t mask,
+                                                          uint32_t *slot_of, uint32_t *rank_of,
+                                                          uint32_t *slot_count) {
+    __shared__ uint32_t s_slot[kHashLds], s_cnt[kHashLds], s_base[kHashLds];
+    for (int x = threadIdx.x; x < kHashLds; x += kHashBlock) {
+        s_slot[x] = kNoSlot;
+        s_cnt[x] = 0;
+    }
+    __syncthreads();
+    const uint64_t per_round = (uint64_t)kHashBlock * kHashIPT;
+    // the trip count is the same for every thread of the workgroup
+    for (uint64_t i0 = (uint64_t)blockIdx.x * per_round; i0 < n;
+         i0 += (uint64_t)gridDim.x * per_round) {
+        uint32_t h[kHashIPT], e[kHashIPT], local[kHashIPT];
+#pragma unroll
+        for (int u = 0; u < kHashIPT; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kHashBlock + threadIdx.x;
+            if (i >= n) continue;
+            const uint32_t key = keys[i];
+            const unsigned long long want = (unsigned long long)key + 1ull;
+            uint32_t hh = dev::hash32(key) & mask;
+            for (uint32_t probe = 0; probe <= mask; ++probe) {
+                unsigned long long cur = slots[hh];
+                if (cur == 0ull) cur = atomicCAS(&slots[hh], 0ull, want);
+                if (cur == 0ull || cur == want) break;
+                hh = (hh + 1) & mask;
             }
-            h = (h + 1) & mask;
+            uint32_t ee = hh & (kHashLds - 1);
+            for (;;) {  // ends: fewer distinct slots per round than entries
+                const uint32_t prev = atomicCAS(&s_slot[ee], kNoSlot, hh);
+                if (prev == kNoSlot || prev == hh) break;
+                ee = (ee + 1) & (kHashLds - 1);
+            }
+            h[u] = hh;
+            e[u] = ee;
+            local[u] = atomicAdd(&s_cnt[ee], 1u);
         }
+        __syncthreads();
+        // reserve each group's ranks and clear the entry for the next round
+        for (int x = threadIdx.x; x < kHashLds; x += kHashBlock) {
+            const uint32_t sl = s_slot[x];
+            if (sl != kNoSlot) {
+                s_base[x] = atomicAdd(&slot_count[sl], s_cnt[x]);
+                s_slot[x] = kNoSlot;
+                s_cnt[x] = 0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kHashIPT; ++u) {
+            const uint64_t i = i0 + (uint64_t)u * kHashBlock + threadIdx.x;
+            if (i >= n) continue;
+            slot_of[i] = h[u];
+            rank_of[i] = s_base[e[u]] + local[u];
+        }
+        // s_base is next written after the next round's first barrier
     }
 }
 
-__global__ void hash_fill(const uint32_t *slot_of, uint64_t n, const uint64_t *slot_start,
-                          uint32_t *cursor, uint32_t *rows) {
+__global__ void hash_fill(const uint32_t *slot_of, const uint32_t *rank_of, uint64_t n,
+                          const uint64_t *slot_start, uint32_t *rows) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t h = slot_of[i];
-        const uint32_t at = atomicAdd(&cursor[h], 1u);
-        rows[slot_start[h] + at] = (uint32_t)i;
-    }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        rows[slot_start[slot_of[i]] + rank_of[i]] = (uint32_t)i;
 }
 
 __global__ void hash_probe(const uint32_t *keys, uint64_t n, const unsigned long long *slots,
@@ -359,32 +451,29 @@ std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64
         while (cap < 2 * nb) cap <<= 1;
         TID_REQUIRE(cap <= (1ull << 31), TID_E_UNSUPPORTED, "join: hash table too large");
         const uint32_t mask = (uint32_t)(cap - 1);
-        pj->slots = DevBuf(ctx, cap * 8);
-        pj->slot_count = DevBuf(ctx, cap * 4);
-        pj->cursor = DevBuf(ctx, cap * 4);
+        // slot words (cap x 8 B) then slot counts (cap x 4 B): one clear
+        pj->slots = DevBuf(ctx, cap * 12);
+        unsigned long long *slots = pj->slots.get<unsigned long long>();
+        uint32_t *slot_count = reinterpret_cast<uint32_t *>(slots + cap);
+        pj->rank = DevBuf(ctx, nb * 4);
         pj->slot_of = DevBuf(ctx, nb * 4);
         pj->slot_start = DevBuf(ctx, (cap + 1) * 8);
         pj->rows = DevBuf(ctx, nb * 4);
-        TID_HIP(hipMemsetAsync(pj->slots.get(), 0, cap * 8, ctx->stream));
-        TID_HIP(hipMemsetAsync(pj->slot_count.get(), 0, cap * 4, ctx->stream));
-        TID_HIP(hipMemsetAsync(pj->cursor.get(), 0, cap * 4, ctx->stream));
-        hipLaunchKernelGGL(hash_insert, dim3(grid_of(nb)), dim3(256), 0, ctx->stream, bkey, nb,
-                           pj->slots.get<unsigned long long>(), mask, pj->slot_of.get<uint32_t>(),
-                           pj->slot_count.get<uint32_t>());
+        TID_HIP(hipMemsetAsync(slots, 0, cap * 12, ctx->stream));
+        hipLaunchKernelGGL(hash_insert, dim3(grid_of(nb, kHashBlock * kHashIPT)),
+                           dim3(kHashBlock), 0, ctx->stream, bkey, nb, slots, mask,
+                           pj->slot_of.get<uint32_t>(), pj->rank.get<uint32_t>(), slot_count);
         TID_HIP(hipGetLastError());
-        exclusive_scan_async(ctx, pj->slot_count.get<const uint32_t>(), cap,
-                             pj->slot_start.get<uint64_t>());
+        exclusive_scan_async(ctx, slot_count, cap, pj->slot_start.get<uint64_t>());
         hipLaunchKernelGGL(hash_fill, dim3(grid_of(nb)), dim3(256), 0, ctx->stream,
-                           pj->slot_of.get<const uint32_t>(), nb,
-                           pj->slot_start.get<const uint64_t>(), pj->cursor.get<uint32_t>(),
-                           pj->rows.get<uint32_t>());
+                           pj->slot_of.get<const uint32_t>(), pj->rank.get<const uint32_t>(), nb,
+                           pj->slot_start.get<const uint64_t>(), pj->rows.get<uint32_t>());
         TID_HIP(hipGetLastError());
         pj->nq = nq;
         pj->start = DevBuf(ctx, nq * 4);
         pj->count = DevBuf(ctx, nq * 4);
         hipLaunchKernelGGL(hash_probe, dim3(grid_of(nq)), dim3(256), 0, ctx->stream, qkey, nq,
-                           pj->slots.get<const unsigned long long>(), mask,
-                           pj->slot_count.get<const uint32_t>(),
+                           pj->slots.get<const unsigned long long>(), mask, slot_count,
                            pj->slot_start.get<const uint64_t>(), pj->start.get<uint32_t>(),
                            pj->count.get<uint32_t>());
         TID_HIP(hipGetLastError());
