@@ -14,6 +14,8 @@
 //   scatter  each workgroup walks its range tile by tile and writes every
 //            element at its digit's running offset plus its stable rank,
 //            found with ballots that group the lanes holding equal digits.
+// Up to 8192 pairs are sorted by one workgroup instead, every pass in LDS,
+// in one launch (small sorts are otherwise bound by launches, three a pass).
 // A row of k columns is sorted as one or more packed 64-bit keys (as many
 // leading columns as fit their bit widths), least significant group first,
 // carrying the row permutation as the value.
@@ -182,6 +184,103 @@ __global__ __launch_bounds__(kSortBlock) void radix_scatter(
     }
 }
 
+// One workgroup sorts n <= kSmallBlock * kSmallIPT pairs on key bits
+// [0, bits), in place: the pairs stay in LDS between passes, and each pass
+// ranks items like the scatter kernel (waves in item order, ballots within a
+// wave) and writes them back to LDS at their new places.
+constexpr int kSmallBlock = 1024;
+constexpr int kSmallIPT = 8;
+constexpr int kSmallNW = kSmallBlock / dev::kWave;
+constexpr uint64_t kSmallMax = (uint64_t)kSmallBlock * kSmallIPT;
+constexpr size_t kSmallLds = kSmallMax * 12 + (size_t)kSmallNW * kRadix * 4 + kRadix * 4;
+
+// item `it` of lane `lane` in wave `wave`: each wave owns 64 * kSmallIPT
+// consecutive items
+__device__ __forceinline__ uint32_t small_item(int wave, int it, int lane) {
+    return (uint32_t)(wave * (dev::kWave * kSmallIPT) + it * dev::kWave + lane);
+}
+
+__global__ __launch_bounds__(kSmallBlock) void small_sort(uint64_t *keys, uint32_t *vals,
+                                                          uint32_t n, int bits) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    uint64_t *s_key = reinterpret_cast<uint64_t *>(lds);
+    uint32_t *s_val = lds + 2 * kSmallMax;
+    uint32_t(*s_wh)[kRadix] = reinterpret_cast<uint32_t(*)[kRadix]>(s_val + kSmallMax);
+    uint32_t *s_run = s_val + kSmallMax + kSmallNW * kRadix;
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    constexpr int kPer = kRadix / dev::kWave;
+    for (int shift = 0; shift < bits; shift += kRadixBits) {
+        uint64_t key[kSmallIPT];
+        uint32_t val[kSmallIPT], rank[kSmallIPT];
+#pragma unroll
+        for (int it = 0; it < kSmallIPT; ++it) {
+            const uint32_t i = small_item(wave, it, lane);
+            key[it] = 0;
+            val[it] = 0;
+            if (i < n) {
+                key[it] = shift == 0 ? keys[i] : s_key[i];
+                val[it] = shift == 0 ? vals[i] : s_val[i];
+            }
+        }
+        for (uint32_t d = lane; d < kRadix; d += dev::kWave) s_wh[wave][d] = 0;
+#pragma unroll
+        for (int it = 0; it < kSmallIPT; ++it) {
+            const bool valid = small_item(wave, it, lane) < n;
+            const uint32_t d = (uint32_t)(key[it] >> shift) & (kRadix - 1);
+            const uint64_t peers = match_digit(d, valid);
+            const uint32_t before = valid ? s_wh[wave][d] : 0u;
+            rank[it] = before + (uint32_t)__popcll(peers & lt);
+            if (valid && lane == __builtin_ctzll(peers)) s_wh[wave][d] = before + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();  // every item is in registers and every wave has counted
+        if (tid < (int)kRadix) {
+            uint32_t t = 0;
+            for (int w = 0; w < kSmallNW; ++w) t += s_wh[w][tid];
+            s_run[tid] = t;
+        }
+        __syncthreads();
+        if (wave == 0) {  // digit totals -> digit bases
+            uint32_t v[kPer], loc = 0;
+#pragma unroll
+            for (int x = 0; x < kPer; ++x) {
+                v[x] = s_run[lane * kPer + x];
+                loc += v[x];
+            }
+            uint32_t run = dev::wave_inclusive_sum(loc) - loc;
+#pragma unroll
+            for (int x = 0; x < kPer; ++x) {
+                s_run[lane * kPer + x] = run;
+                run += v[x];
+            }
+        }
+        __syncthreads();
+        if (tid < (int)kRadix) {  // per-wave bases of each digit, waves in item order
+            uint32_t run = s_run[tid];
+            for (int w = 0; w < kSmallNW; ++w) {
+                const uint32_t c = s_wh[w][tid];
+                s_wh[w][tid] = run;
+                run += c;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kSmallIPT; ++it) {
+            if (small_item(wave, it, lane) < n) {
+                const uint32_t d = (uint32_t)(key[it] >> shift) & (kRadix - 1);
+                const uint32_t pos = s_wh[wave][d] + rank[it];
+                s_key[pos] = key[it];
+                s_val[pos] = val[it];
+            }
+        }
+        __syncthreads();  // the next pass reads the new order
+    }
+    for (uint32_t i = tid; i < n; i += kSmallBlock) {
+        keys[i] = s_key[i];
+        vals[i] = s_val[i];
+    }
+}
+
 __global__ void iota_u32(uint32_t *v, uint64_t n) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
@@ -283,6 +382,18 @@ bool radix_sort_pairs(tid_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
                       uint64_t n, int bits) {
     if (n <= 1 || bits <= 0) return false;
     TID_REQUIRE(n < (1ull << 32), TID_E_UNSUPPORTED, "sort: more than 2^32-1 rows");
+    if (n <= kSmallMax) {
+        static bool attr_set = false;
+        if (!attr_set) {
+            TID_HIP(hipFuncSetAttribute((const void *)small_sort,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLds));
+            attr_set = true;
+        }
+        hipLaunchKernelGGL(small_sort, dim3(1), dim3(kSmallBlock), kSmallLds, ctx->stream, k0, v0,
+                           (uint32_t)n, bits);
+        TID_HIP(hipGetLastError());
+        return false;
+    }
     const uint64_t tiles = (n + kSortTile - 1) / kSortTile;
     uint64_t P = std::max<uint64_t>(1, std::min<uint64_t>(tiles, 2ull * device_cus(ctx)));
     const uint64_t range = (tiles + P - 1) / P * kSortTile;

@@ -33,19 +33,15 @@ constexpr int kWideIPT = 8;
 
 // A pattern with a constant predicate, compacted for LDS.
 struct WidePat {
-    uint32_t s, o;       // constants (0 = free)
-    uint32_t lo, span;   // range test (x - lo) < span on position rpos
-    uint32_t flags;      // bit0 s bound, bit1 o bound, bit2 s==o, bits 3-4 range pos+1,
-                         // bits 5-6 ncols, bits 8-9/10-11/12-13 source position of col 0/1/2,
-                         // bit 14 membership filter (WideFilter of the same index)
+    const uint32_t *fbits;  // membership filter (Bloom bits), if flagged
+    uint32_t s, o;          // constants (0 = free)
+    uint32_t lo, span;      // range test (x - lo) < span on position rpos
+    uint32_t flags;         // bit0 s bound, bit1 o bound, bit2 s==o, bits 3-4 range pos+1,
+                            // bits 5-6 ncols, bits 8-9/10-11/12-13 source position of
+                            // col 0/1/2, bit 14 filtered, bits 15-16 filter position
+    uint32_t fmask;         // filter bits - 1
 };
 constexpr uint32_t kWideFiltered = 1u << 14;
-
-struct WideFilter {
-    const uint32_t *bits;
-    uint32_t mask;
-    int32_t pos;
-};
 
 struct WideOut {
     uint32_t *col[3];
@@ -61,7 +57,6 @@ struct WideArgs {
     const uint32_t *bucket;   // kWidePreds words: start << 12 | len
     const uint16_t *ids;      // k pattern ids grouped by predicate
     const WideOut *outs;      // k
-    const WideFilter *filters;  // k (read only for patterns flagged kWideFiltered)
     uint64_t **counts_out;    // k device row-count words
     int k;
     uint64_t sub;             // triples per wave sub-range
@@ -153,9 +148,10 @@ __device__ __forceinline__ void wide_walk(const WideArgs &a, const WidePat *s_pa
                 const uint32_t pid = has ? s_ids[start + c] : 0u;
                 bool m = has && wide_match(s_pat[pid], t[it]);
                 if (m && (s_pat[pid].flags & kWideFiltered)) {
-                    const WideFilter f = a.filters[pid];
-                    const uint32_t x = f.pos == 0 ? t[it].v[0] : (f.pos == 1 ? t[it].v[1] : t[it].v[2]);
-                    m = dev::bloom_has(f.bits, f.mask, x);
+                    const WidePat &q = s_pat[pid];
+                    const uint32_t fp = (q.flags >> 15) & 3u;
+                    const uint32_t x = fp == 0 ? t[it].v[0] : (fp == 1 ? t[it].v[1] : t[it].v[2]);
+                    m = dev::bloom_has(q.fbits, q.fmask, x);
                 }
                 const uint64_t peers = match_pid(pid, m);
                 if (!m) continue;
@@ -200,7 +196,7 @@ __device__ __forceinline__ WideLds wide_lds(uint32_t *lds, int k) {
 
 template <bool SLICE>
 __global__ __launch_bounds__(kWideBlock) void wide_count(WideArgs a, uint32_t *flags) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const WideLds l = wide_lds(lds, a.k);
     WidePat *s_pat = l.pat;
     uint32_t *s_bucket = l.bucket;
@@ -252,7 +248,7 @@ __global__ __launch_bounds__(kColBlock) void wide_offsets(WideArgs a) {
 
 template <bool SLICE>
 __global__ __launch_bounds__(kWideBlock) void wide_write(WideArgs a, uint32_t *flags) {
-    extern __shared__ uint32_t lds[];
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
     const WideLds l = wide_lds(lds, a.k);
     WidePat *s_pat = l.pat;
     uint32_t *s_bucket = l.bucket;
@@ -334,17 +330,16 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
     const bool slice = src.g == nullptr;
     std::vector<WidePat> wp(k);
     std::vector<WideOut> wo(k);
-    std::vector<WideFilter> wf(k);
     std::vector<uint64_t *> wc(k);
     std::vector<std::vector<uint16_t>> by_pred(kWidePreds);
     for (int j = 0; j < k; ++j) {
         TID_REQUIRE(wide_eligible(pats[j]) && (!slice || pats[j].p == src.p), TID_E_INTERNAL,
                     "wide pass: pattern not eligible");
         wp[j] = compile_wide(pats[j]);
-        wf[j] = WideFilter{nullptr, 0u, -1};
         if (filters && filters[j].pos >= 0) {
-            wp[j].flags |= kWideFiltered;
-            wf[j] = WideFilter{filters[j].bits, filters[j].mask, filters[j].pos};
+            wp[j].flags |= kWideFiltered | ((uint32_t)filters[j].pos << 15);
+            wp[j].fbits = filters[j].bits;
+            wp[j].fmask = filters[j].mask;
         }
         for (int c = 0; c < 3; ++c) wo[j].col[c] = c < outs[j]->ncols ? outs[j]->col[c] : nullptr;
         wo[j].cap = outs[j]->cap;
@@ -361,9 +356,8 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
     // tables of constants, in one device block
     const size_t b_pats = align_up(sizeof(WidePat) * k), b_bucket = align_up(4 * kWidePreds),
                  b_ids = align_up(2 * (size_t)k), b_outs = align_up(sizeof(WideOut) * k),
-                 b_cnts = align_up(8 * (size_t)k), b_tot = align_up(8 * (size_t)k),
-                 b_filt = align_up(sizeof(WideFilter) * k);
-    const size_t consts = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot + b_filt;
+                 b_cnts = align_up(8 * (size_t)k), b_tot = align_up(8 * (size_t)k);
+    const size_t consts = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot;
     std::vector<char> host(consts, 0);
     char *h = host.data();
     std::memcpy(h, wp.data(), sizeof(WidePat) * k);
@@ -371,8 +365,6 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
     std::memcpy(h + b_pats + b_bucket, ids.data(), 2 * (size_t)k);
     std::memcpy(h + b_pats + b_bucket + b_ids, wo.data(), sizeof(WideOut) * k);
     std::memcpy(h + b_pats + b_bucket + b_ids + b_outs, wc.data(), 8 * (size_t)k);
-    std::memcpy(h + b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot, wf.data(),
-                sizeof(WideFilter) * k);
     DevBuf dconst(ctx, consts);
     TID_HIP(hipMemcpyAsync(dconst.get(), host.data(), consts, hipMemcpyHostToDevice, ctx->stream));
     char *d = dconst.get<char>();
@@ -403,8 +395,6 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
     a.outs = reinterpret_cast<const WideOut *>(d + b_pats + b_bucket + b_ids);
     a.counts_out = reinterpret_cast<uint64_t **>(d + b_pats + b_bucket + b_ids + b_outs);
     a.tot = reinterpret_cast<uint64_t *>(d + b_pats + b_bucket + b_ids + b_outs + b_cnts);
-    a.filters =
-        reinterpret_cast<const WideFilter *>(d + b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot);
     a.k = k;
     a.sub = sub;
     a.W = (uint32_t)W;

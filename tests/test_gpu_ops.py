@@ -30,7 +30,8 @@ def rand_table(rng, n, k, hi):
 
 @pytest.mark.parametrize("n,k,hi", [(0, 2, 10), (1, 3, 5), (100, 1, 7), (5000, 2, 50),
                                     (70001, 3, 1000), (20000, 3, 2**32 - 1),
-                                    (30000, 5, 2**31), (4097, 4, 3)])
+                                    (30000, 5, 2**31), (4097, 4, 3), (8192, 3, 2**32 - 1),
+                                    (8193, 2, 100), (2, 2, 2**32 - 1), (6000, 5, 2**31)])
 def test_sort_and_distinct(ctx, n, k, hi):
     rng = np.random.default_rng(n + k)
     rows = rand_table(rng, n, k, hi)
