@@ -203,7 +203,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
                     const uint32_t r =
                         (uint32_t)cnt + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
                     const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
-                    for (int c = 0; c < o.ncols; ++c)
+                    TID_FOR_COLS(MAXC, c, o.ncols)
                         stage[o.stage_off + (uint32_t)c * o.stage_cap + r] =
                             src.value(j, c, item[it], i);
                 }
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
         for (uint32_t r = tid; r < st; r += BLOCK) {
             const uint64_t dst = pre + r;
             if (dst < o.cap) {
-                for (int c = 0; c < o.ncols; ++c)
+                TID_FOR_COLS(MAXC, c, o.ncols)
                     o.col[c][dst] = stage[o.stage_off + (uint32_t)c * o.stage_cap + r];
             } else {
                 atomicOr(&flags[1], 1u);
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
                     const uint64_t dst = base + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
                     const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
                     if (dst < o.cap) {
-                        for (int c = 0; c < o.ncols; ++c) o.col[c][dst] = src.value(j, c, item[it], i);
+                        TID_FOR_COLS(MAXC, c, o.ncols) o.col[c][dst] = src.value(j, c, item[it], i);
                     } else {
                         atomicOr(&flags[1], 1u);
                     }
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
             for (uint32_t r = tid; r < stg; r += BLOCK) {
                 const uint64_t dst = pre + r;
                 if (dst < o.cap) {
-                    for (int c = 0; c < o.ncols; ++c)
+                    TID_FOR_COLS(MAXC, c, o.ncols)
                         o.col[c][dst] = pb[o.stage_off + (uint32_t)c * o.stage_cap + r];
                 } else {
                     atomicOr(&flags[1], 1u);
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
                             base + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
                         const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
                         if (dst < o.cap) {
-                            for (int c = 0; c < o.ncols; ++c)
+                            TID_FOR_COLS(MAXC, c, o.ncols)
                                 o.col[c][dst] = src.value(j, c, item[it], i);
                         } else {
                             atomicOr(&flags[1], 1u);
@@ -571,7 +571,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
                         const uint32_t r =
                             (uint32_t)cnt + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
                         const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
-                        for (int c = 0; c < o.ncols; ++c)
+                        TID_FOR_COLS(MAXC, c, o.ncols)
                             st[o.stage_off + (uint32_t)c * o.stage_cap + r] =
                                 src.value(j, c, item[it], i);
                     }

@@ -6,6 +6,13 @@
 
 #include <cstdint>
 
+// Loop over the first n of at most MAXC output columns.  For small MAXC the
+// loop is unrolled to MAXC steps with a guard, so that per-column constants
+// indexed by c (source positions, column pointers) are loop-invariant loads
+// the compiler can hoist, rather than loads repeated for every staged row.
+#define TID_FOR_COLS(MAXC, c, n) \
+    _Pragma("unroll") for (int c = 0; c < ((MAXC) <= 4 ? (MAXC) : (n)); ++c) if (c < (n))
+
 namespace tid {
 namespace dev {
 

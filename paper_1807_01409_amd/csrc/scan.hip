@@ -41,7 +41,9 @@ struct DevPattern {
     int32_t fpos;
 };
 
-template <int MAXK>
+// EXT false: no pattern of the pass has a value set or a membership filter,
+// and their tests are compiled out.
+template <int MAXK, bool EXT = true>
 struct ScanSrc {
     const uint32_t *g;
     uint64_t n;
@@ -76,14 +78,26 @@ __device__ __forceinline__ bool match_pattern(const DevPattern &q, const Tri &t)
     return ok;
 }
 
-template <int MAXK>
-__device__ __forceinline__ bool ScanSrc<MAXK>::match(int j, const Item &t) const {
-    return match_pattern(pat[j], t);
+// constants, repeated variables and the range only
+__device__ __forceinline__ bool match_plain(const DevPattern &q, const Tri &t) {
+    uint32_t diff = ((t.v[0] ^ q.key[0]) & q.msk[0]) | ((t.v[1] ^ q.key[1]) & q.msk[1]) |
+                    ((t.v[2] ^ q.key[2]) & q.msk[2]);
+    bool ok = diff == 0;
+    ok &= !(q.eq & 1u) || t.v[0] == t.v[1];
+    ok &= !(q.eq & 2u) || t.v[0] == t.v[2];
+    ok &= !(q.eq & 4u) || t.v[1] == t.v[2];
+    if (q.rpos >= 0) ok &= (pick(t, q.rpos) - q.lo) < q.span;
+    return ok;
 }
 
-template <int MAXK>
-__device__ __forceinline__ uint32_t ScanSrc<MAXK>::value(int j, int c, const Item &t,
-                                                         uint64_t) const {
+template <int MAXK, bool EXT>
+__device__ __forceinline__ bool ScanSrc<MAXK, EXT>::match(int j, const Item &t) const {
+    return EXT ? match_pattern(pat[j], t) : match_plain(pat[j], t);
+}
+
+template <int MAXK, bool EXT>
+__device__ __forceinline__ uint32_t ScanSrc<MAXK, EXT>::value(int j, int c, const Item &t,
+                                                              uint64_t) const {
     return pick(t, pat[j].src[c]);
 }
 
@@ -218,7 +232,7 @@ __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__res
                 if (bit) {
                     const uint32_t r =
                         (uint32_t)cnt + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
-                    for (int c = 0; c < o.ncols; ++c)
+                    TID_FOR_COLS(3, c, o.ncols)
                         stage[o.stage_off + (uint32_t)c * o.stage_cap + r] = pick(t[it], q.src[c]);
                 }
             }
@@ -282,7 +296,7 @@ __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__res
         for (uint32_t r = tid; r < st; r += BLOCK) {
             const uint64_t dst = pre + r;
             if (dst < o.cap) {
-                for (int c = 0; c < o.ncols; ++c)
+                TID_FOR_COLS(3, c, o.ncols)
                     o.col[c][dst] = stage[o.stage_off + (uint32_t)c * o.stage_cap + r];
             } else {
                 atomicOr(&flags[1], 1u);
@@ -307,7 +321,7 @@ __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__res
                 if (bit) {
                     const uint64_t dst = base + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
                     if (dst < o.cap) {
-                        for (int c = 0; c < o.ncols; ++c) o.col[c][dst] = pick(t[it], q.src[c]);
+                        TID_FOR_COLS(3, c, o.ncols) o.col[c][dst] = pick(t[it], q.src[c]);
                     } else {
                         atomicOr(&flags[1], 1u);
                     }
@@ -438,14 +452,18 @@ static uint32_t stage_words(tid_ctx *ctx) {
     return ctx->opt.stage_words > 0 ? (uint32_t)ctx->opt.stage_words : 16384u;
 }
 
-// One pass over the graph for k patterns into the given tables.
-template <int MAXK>
-static void run_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
-                     tid_table *const *outs, const PatternSet *sets, const ScanFilter *filters) {
-    ScanSrc<MAXK> src{};
+static bool any_ext(int k, const PatternSet *sets, const ScanFilter *filters) {
+    for (int j = 0; j < k; ++j)
+        if ((sets && sets[j].pos >= 0) || (filters && filters[j].pos >= 0)) return true;
+    return false;
+}
+
+template <class SRC, int MAXK>
+static void fill_scan_args(const tid_graph *g, const tid_pattern *pats, int k,
+                           tid_table *const *outs, const PatternSet *sets,
+                           const ScanFilter *filters, SRC &src, CompactArgs<MAXK, 3> &a) {
     src.g = g->data.get<const uint32_t>();
     src.n = g->n;
-    CompactArgs<MAXK, 3> a{};
     for (int j = 0; j < k; ++j) {
         src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr,
                                      filters ? &filters[j] : nullptr);
@@ -454,8 +472,25 @@ static void run_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, 
         a.out[j].count = outs[j]->d_count;
         a.out[j].ncols = outs[j]->ncols;
     }
+}
+
+// One pass over the graph for k patterns into the given tables.  The default
+// launch shape has a variant without value-set and filter tests.
+template <int MAXK>
+static void run_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+                     tid_table *const *outs, const PatternSet *sets, const ScanFilter *filters) {
     const Shape sh = scan_shape(ctx);
     const uint32_t sw = stage_words(ctx);
+    if (sh.block == 512 && sh.ipt == 8 && sh.prefetch && !any_ext(k, sets, filters)) {
+        ScanSrc<MAXK, false> src{};
+        CompactArgs<MAXK, 3> a{};
+        fill_scan_args(g, pats, k, outs, sets, filters, src, a);
+        launch_compact<ScanSrc<MAXK, false>, 512, 8, MAXK, 3, true>(ctx, src, a, k, sw);
+        return;
+    }
+    ScanSrc<MAXK> src{};
+    CompactArgs<MAXK, 3> a{};
+    fill_scan_args(g, pats, k, outs, sets, filters, src, a);
 #define TID_SCAN_CASE(B, I)                                                         \
     if (sh.block == B && sh.ipt == I) {                                             \
         if (sh.prefetch)                                                            \
@@ -515,18 +550,16 @@ template <int MAXK, int B, int I>
 static void run_unrolled(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                          tid_table *const *outs, const PatternSet *sets,
                          const ScanFilter *filters) {
-    ScanSrc<MAXK> src{};
-    src.g = g->data.get<const uint32_t>();
-    src.n = g->n;
-    CompactArgs<MAXK, 3> a{};
-    for (int j = 0; j < k; ++j) {
-        src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr,
-                                     filters ? &filters[j] : nullptr);
-        for (int c = 0; c < outs[j]->ncols; ++c) a.out[j].col[c] = outs[j]->col[c];
-        a.out[j].cap = outs[j]->cap;
-        a.out[j].count = outs[j]->d_count;
-        a.out[j].ncols = outs[j]->ncols;
+    if (B == 512 && I == 8 && !any_ext(k, sets, filters)) {
+        ScanSrc<MAXK, false> src{};
+        CompactArgs<MAXK, 3> a{};
+        fill_scan_args(g, pats, k, outs, sets, filters, src, a);
+        launch_compact<ScanSrc<MAXK, false>, B, I, MAXK, 3, true>(ctx, src, a, k, stage_words(ctx));
+        return;
     }
+    ScanSrc<MAXK> src{};
+    CompactArgs<MAXK, 3> a{};
+    fill_scan_args(g, pats, k, outs, sets, filters, src, a);
     launch_compact<ScanSrc<MAXK>, B, I, MAXK, 3, true>(ctx, src, a, k, stage_words(ctx));
 }
 

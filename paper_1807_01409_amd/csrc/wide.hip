@@ -162,7 +162,7 @@ __device__ __forceinline__ void wide_walk(const WideArgs &a, const WidePat *s_pa
                     const WideOut &o = a.outs[pid];
                     const int nc = (q.flags >> 5) & 3u;
                     if (pos < o.cap) {
-                        for (int cc = 0; cc < nc; ++cc) {
+                        TID_FOR_COLS(3, cc, nc) {
                             const uint32_t src = (q.flags >> (8 + 2 * cc)) & 3u;
                             o.col[cc][pos] = t[it].v[src];
                         }
