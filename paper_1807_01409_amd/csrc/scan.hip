@@ -71,7 +71,9 @@ __device__ __forceinline__ bool match_pattern(const DevPattern &q, const Tri &t)
     if (q.set_pos >= 0) {
         const uint32_t x = pick(t, q.set_pos);
         bool in = false;
-        for (int i = 0; i < q.nset; ++i) in |= x == q.set[i];
+        // unrolled to the bound so the set values are loop-invariant loads
+#pragma unroll
+        for (int i = 0; i < kMaxSet; ++i) in |= i < q.nset && x == q.set[i];
         ok &= in;
     }
     if (ok && q.fpos >= 0) ok = dev::bloom_has(q.fbits, q.fmask, pick(t, q.fpos));
