@@ -49,8 +49,13 @@ struct ScanSrc {
     uint64_t n;
     DevPattern pat[MAXK];
     using Item = Tri;
+    // the graph is streamed once per pass: non-temporal loads
     __device__ __forceinline__ Item load(uint64_t i) const {
-        return *reinterpret_cast<const Tri *>(g + 3 * i);
+        Tri t;
+        t.v[0] = __builtin_nontemporal_load(g + 3 * i);
+        t.v[1] = __builtin_nontemporal_load(g + 3 * i + 1);
+        t.v[2] = __builtin_nontemporal_load(g + 3 * i + 2);
+        return t;
     }
     __device__ __forceinline__ bool match(int j, const Item &t) const;
     __device__ __forceinline__ uint32_t value(int j, int c, const Item &t, uint64_t) const;
@@ -196,8 +201,13 @@ __global__ __launch_bounds__(BLOCK) void scan_multi_kernel(const uint32_t *__res
 #pragma unroll
         for (int it = 0; it < IPT; ++it) {
             const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
-            if (i < r1) t[it] = *reinterpret_cast<const Tri *>(g + 3 * i);
-            else t[it].v[0] = t[it].v[1] = t[it].v[2] = 0;
+            if (i < r1) {  // streamed once: non-temporal loads
+                t[it].v[0] = __builtin_nontemporal_load(g + 3 * i);
+                t[it].v[1] = __builtin_nontemporal_load(g + 3 * i + 1);
+                t[it].v[2] = __builtin_nontemporal_load(g + 3 * i + 2);
+            } else {
+                t[it].v[0] = t[it].v[1] = t[it].v[2] = 0;
+            }
         }
     };
     auto count_tile = [&](uint64_t t0) {

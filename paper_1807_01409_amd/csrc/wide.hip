@@ -120,7 +120,11 @@ __device__ __forceinline__ WTri wide_load(const WideArgs &a, uint64_t i) {
         t.v[2] = a.so[i];
         return t;
     }
-    return *reinterpret_cast<const WTri *>(a.g + 3 * i);
+    WTri t;  // the graph is streamed once per pass: non-temporal loads
+    t.v[0] = __builtin_nontemporal_load(a.g + 3 * i);
+    t.v[1] = __builtin_nontemporal_load(a.g + 3 * i + 1);
+    t.v[2] = __builtin_nontemporal_load(a.g + 3 * i + 2);
+    return t;
 }
 
 template <bool WRITE, bool SLICE>
