@@ -105,9 +105,10 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           uses stamp + 1 and, past 2^23 - 1, clears the
                           context's count slots and restarts at 1 (settable
                           so that tests can reach the wrap)
-     "wide_min"           a plan batch with at least this many patterns of
-                          constant predicate uses the bucketed wide pass
-                          (0 = default 32)
+     "wide_min"           a round of plan scans with at least this many
+                          patterns of constant predicate uses the bucketed
+                          wide pass (0 = default 8: from 8 patterns on, its two
+                          graph reads cost no more than passes of 4)
      "wide_slice"         1 (default): in a wide pass, a predicate that at
                           least two of its patterns share, with at least
                           "slice_rows" triples, is sliced: the graph pass

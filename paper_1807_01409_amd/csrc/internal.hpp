@@ -57,7 +57,7 @@ struct Options {
     int64_t scan_items = 0;   // 0 = built-in default
     int64_t scan_block = 0;
     int64_t stage_words = 0;  // LDS staging words per workgroup (0 = default)
-    int64_t wide_min = 0;     // patterns needed before wide passes are used (0 = 32)
+    int64_t wide_min = 0;     // patterns needed before wide passes are used (0 = 8)
     int64_t scan_prefetch = -1;  // -1 built-in default, 0 off, 1 prefetch the next tile
     int64_t multi_kernel = 0;    // 0 passes of <= 4 unrolled patterns, 1 LDS pattern loop
     int64_t multi_shape = 0;     // launch shape index of the chosen multi-pattern kernel

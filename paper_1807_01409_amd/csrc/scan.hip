@@ -649,7 +649,7 @@ void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
 void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                std::unique_ptr<tid_table> *outs, const PatternSet *sets,
                const ScanFilter *filters) {
-    const int64_t wide_min = ctx->opt.wide_min > 0 ? ctx->opt.wide_min : 32;
+    const int64_t wide_min = ctx->opt.wide_min > 0 ? ctx->opt.wide_min : 8;
     std::vector<int> wide, rest;
     for (int j = 0; j < k; ++j) {
         const bool has_set = sets && sets[j].pos >= 0;
