@@ -134,6 +134,14 @@ tid_status tid_load(tid_ctx *ctx, const uint32_t *triples, uint64_t n, int src_o
 tid_status tid_load_file(tid_ctx *ctx, const char *path, tid_graph **out);
 /* Number of triples and the device address of the resident array. */
 tid_status tid_graph_info(const tid_graph *g, uint64_t *n, const uint32_t **device_triples);
+/* Number of triples whose position `pos` (0 s, 1 p, 2 o) holds an ID in
+   [lo, hi), from the per-position histograms built at load (Sec. 3: the
+   TripleID array kept resident; these counts size scan outputs and bound
+   plans).  lo >= hi gives 0.  Host only, no device work.  TID_E_UNSUPPORTED
+   if the position has no histogram (its largest ID is 2^28 or more, or the
+   graph holds 2^32 triples or more). */
+tid_status tid_graph_count(const tid_graph *g, int32_t pos, uint32_t lo, uint32_t hi,
+                           uint64_t *count);
 void tid_graph_free(tid_graph *g);
 
 /* ---- triple pattern (Sec. 3: key with 0 as "?") ----------------------- */

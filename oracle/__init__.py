@@ -19,7 +19,7 @@ from typing import List, Sequence
 
 import numpy as np
 
-from .encode import encode_graph
+from .encode import decode_row, encode_graph
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
@@ -237,4 +237,5 @@ def query(g, plan) -> Table:
 
 
 __all__ = ["build", "Table", "OracleError", "scan_flags", "scan_multi", "scan",
-           "filter", "join", "union", "sort_rows", "distinct", "query", "encode_graph"]
+           "filter", "join", "union", "sort_rows", "distinct", "query", "encode_graph",
+           "decode_row"]

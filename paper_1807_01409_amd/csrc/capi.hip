@@ -237,6 +237,14 @@ tid_status tid_graph_info(const tid_graph *g, uint64_t *n, const uint32_t **devi
     return TID_OK;
 }
 
+tid_status tid_graph_count(const tid_graph *g, int32_t pos, uint32_t lo, uint32_t hi,
+                           uint64_t *count) {
+    if (!g || !count || pos < 0 || pos > 2) return TID_E_INVALID_ARG;
+    if (g->n && g->cdf[pos].empty()) return TID_E_UNSUPPORTED;
+    *count = g->n ? g->count_in(pos, lo, hi) : 0;
+    return TID_OK;
+}
+
 void tid_graph_free(tid_graph *g) {
     if (!g) return;
     (void)hipSetDevice(g->ctx->device);

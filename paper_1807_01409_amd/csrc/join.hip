@@ -233,6 +233,9 @@ constexpr int kHashBlock = 256;
 constexpr int kHashIPT = 4;
 constexpr int kHashLds = 2048;  // entries; a round holds at most 1024 distinct slots
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+// largest build side the automatic choice sends to the hash join (2^23 rows:
+// 2^24 slots of 12 B = 192 MB)
+constexpr uint64_t kHashAutoMaxRows = 1ull << 23;
 
 __global__ __launch_bounds__(kHashBlock) void hash_insert(const uint32_t *keys, uint64_t n,
                                                           unsigned long long *slots, uint32_t mask,
@@ -400,7 +403,12 @@ std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64
     }
     TID_REQUIRE(nl < (1ull << 32) && nr < (1ull << 32), TID_E_UNSUPPORTED,
                 "join: inputs of 2^32 rows or more");
-    if (algo == 0) algo = 1;
+    // automatic choice by size: a hash table over the smaller side while its
+    // slot words and counts (12 B per slot, at least two slots per build row)
+    // fit the 256 MB last-level cache, so probes mostly stay on chip;
+    // sort-merge above that, where the sorts stream both sides through HBM
+    // instead of probing it at random
+    if (algo == 0) algo = std::min(nl, nr) <= kHashAutoMaxRows ? 1 : 2;
     if (algo == 2) {
         // sort both sides on the key, then find each left key's run on the right
         uint32_t ml, mr;

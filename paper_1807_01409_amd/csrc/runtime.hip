@@ -208,27 +208,78 @@ __global__ void init_minmax(uint32_t *mm) {
     else if (threadIdx.x < 6) mm[threadIdx.x] = 0u;
 }
 
-// histogram of one position; small ID ranges are counted in LDS first
-template <int LDS_BINS>
-__global__ void hist_kernel(const uint32_t *__restrict__ g, uint64_t n, int pos, uint32_t nbins,
-                            uint32_t *hist) {
-    __shared__ uint32_t s_h[LDS_BINS > 0 ? LDS_BINS : 1];
-    if (LDS_BINS > 0) {
-        for (uint32_t b = threadIdx.x; b < nbins; b += blockDim.x) s_h[b] = 0;
-        __syncthreads();
+// Per-position ID histograms in one pass over the graph.  Each workgroup
+// counts in LDS first and adds its counts to the global bins at the end:
+//  - a position whose IDs fit kDirectBins bins (the predicates) is counted
+//    in LDS bins directly;
+//  - any other position goes through a small open-addressing LDS table of
+//    kHashEntries (ID, count) entries, so the hubs of a skewed position
+//    (Zipf subjects and objects) cost one global atomic per workgroup
+//    instead of one per triple; an ID that finds no free entry within
+//    kHashProbes steps is added to its global bin directly.
+// IDs are >= 1 here (checked before), so key 0 marks an empty entry.
+int device_cus(tid_ctx *ctx);
+
+constexpr uint32_t kDirectBins = 8192;
+constexpr uint32_t kHashEntries = 2048;
+constexpr int kHashProbes = 16;
+constexpr int kHistBlock = 1024;
+
+struct HistArgs {
+    uint32_t *hist[3];   // global bins per position (null: not counted)
+    uint32_t nbins[3];
+};
+
+__global__ __launch_bounds__(kHistBlock) void hist3_kernel(const uint32_t *__restrict__ g,
+                                                           uint64_t n, HistArgs a) {
+    // per position a region of kDirectBins words: direct bins, or hash keys
+    // (first kHashEntries words) and their counts (next kHashEntries words)
+    __shared__ uint32_t s[3][kDirectBins];
+    for (int x = 0; x < 3; ++x)
+        for (uint32_t b = threadIdx.x; b < kDirectBins; b += kHistBlock) s[x][b] = 0;
+    __syncthreads();
+    bool direct[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x) direct[x] = a.nbins[x] <= kDirectBins;
+    const uint64_t stride = (uint64_t)gridDim.x * kHistBlock;
+    for (uint64_t i = (uint64_t)blockIdx.x * kHistBlock + threadIdx.x; i < n; i += stride) {
+        uint32_t v[3];
+        v[0] = __builtin_nontemporal_load(g + 3 * i);
+        v[1] = __builtin_nontemporal_load(g + 3 * i + 1);
+        v[2] = __builtin_nontemporal_load(g + 3 * i + 2);
+#pragma unroll
+        for (int x = 0; x < 3; ++x) {
+            if (!a.hist[x]) continue;
+            if (direct[x]) {
+                atomicAdd(&s[x][v[x]], 1u);
+                continue;
+            }
+            uint32_t h = dev::hash32(v[x]) & (kHashEntries - 1);
+            bool done = false;
+            for (int probe = 0; probe < kHashProbes && !done; ++probe) {
+                uint32_t k = s[x][h];
+                if (k == 0) k = atomicCAS(&s[x][h], 0u, v[x]);
+                if (k == 0 || k == v[x]) {
+                    atomicAdd(&s[x][kHashEntries + h], 1u);
+                    done = true;
+                }
+                h = (h + 1) & (kHashEntries - 1);
+            }
+            if (!done) atomicAdd(&a.hist[x][v[x]], 1u);
+        }
     }
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const uint32_t v = g[3 * i + pos];
-        if (LDS_BINS > 0)
-            atomicAdd(&s_h[v], 1u);
-        else
-            atomicAdd(&hist[v], 1u);
-    }
-    if (LDS_BINS > 0) {
-        __syncthreads();
-        for (uint32_t b = threadIdx.x; b < nbins; b += blockDim.x)
-            if (s_h[b]) atomicAdd(&hist[b], s_h[b]);
+    __syncthreads();
+    for (int x = 0; x < 3; ++x) {
+        if (!a.hist[x]) continue;
+        if (direct[x]) {
+            for (uint32_t b = threadIdx.x; b < a.nbins[x]; b += kHistBlock)
+                if (s[x][b]) atomicAdd(&a.hist[x][b], s[x][b]);
+        } else {
+            for (uint32_t e = threadIdx.x; e < kHashEntries; e += kHistBlock) {
+                const uint32_t k = s[x][e], c = s[x][kHashEntries + e];
+                if (k && c) atomicAdd(&a.hist[x][k], c);
+            }
+        }
     }
 }
 
@@ -251,29 +302,35 @@ void build_stats(tid_ctx *ctx, tid_graph *g) {
         g->max_id[x] = h[3 + x];
     }
     if (g->n >= (1ull << 32)) return;  // counts would not fit the uint32 bins
+    // bins of the counted positions, one allocation, one clear
+    HistArgs a{};
+    size_t off[3] = {0, 0, 0}, total = 0;
     for (int x = 0; x < 3; ++x) {
         if (h[3 + x] >= kMaxHistIds) continue;
-        const uint32_t nbins = h[3 + x] + 1;
-        DevBuf hist(ctx, (size_t)nbins * sizeof(uint32_t));
-        TID_HIP(hipMemsetAsync(hist.get(), 0, (size_t)nbins * sizeof(uint32_t), ctx->stream));
-        const int hb = (int)std::min<uint64_t>((g->n + 1023) / 1024, 8192);
-        if (nbins <= 8192)
-            hipLaunchKernelGGL((hist_kernel<8192>), dim3(hb), dim3(1024), 0, ctx->stream,
-                               g->data.get<const uint32_t>(), g->n, x, nbins,
-                               hist.get<uint32_t>());
-        else
-            hipLaunchKernelGGL((hist_kernel<0>), dim3(hb), dim3(1024), 0, ctx->stream,
-                               g->data.get<const uint32_t>(), g->n, x, nbins,
-                               hist.get<uint32_t>());
-        TID_HIP(hipGetLastError());
-        std::vector<uint32_t> hh(nbins);
-        TID_HIP(hipMemcpyAsync(hh.data(), hist.get(), (size_t)nbins * sizeof(uint32_t),
-                               hipMemcpyDeviceToHost, ctx->stream));
-        TID_HIP(hipStreamSynchronize(ctx->stream));
+        a.nbins[x] = h[3 + x] + 1;
+        off[x] = total;
+        total += align_up((size_t)a.nbins[x] * sizeof(uint32_t));
+    }
+    if (total == 0) return;
+    DevBuf hist(ctx, total);
+    TID_HIP(hipMemsetAsync(hist.get(), 0, total, ctx->stream));
+    for (int x = 0; x < 3; ++x)
+        if (a.nbins[x]) a.hist[x] = reinterpret_cast<uint32_t *>(hist.get<char>() + off[x]);
+    const int hb = (int)std::min<uint64_t>((g->n + kHistBlock - 1) / kHistBlock,
+                                           2ull * (uint64_t)device_cus(ctx));
+    hipLaunchKernelGGL(hist3_kernel, dim3(hb), dim3(kHistBlock), 0, ctx->stream,
+                       g->data.get<const uint32_t>(), g->n, a);
+    TID_HIP(hipGetLastError());
+    std::vector<uint32_t> hh(total / sizeof(uint32_t));
+    TID_HIP(hipMemcpyAsync(hh.data(), hist.get(), total, hipMemcpyDeviceToHost, ctx->stream));
+    TID_HIP(hipStreamSynchronize(ctx->stream));
+    for (int x = 0; x < 3; ++x) {
+        if (!a.nbins[x]) continue;
+        const uint32_t *b = hh.data() + off[x] / sizeof(uint32_t);
         auto &c = g->cdf[x];
-        c.resize((size_t)nbins + 1);
+        c.resize((size_t)a.nbins[x] + 1);
         c[0] = 0;
-        for (uint32_t b = 0; b < nbins; ++b) c[b + 1] = c[b] + hh[b];
+        for (uint32_t i = 0; i < a.nbins[x]; ++i) c[i + 1] = c[i] + b[i];
     }
 }
 

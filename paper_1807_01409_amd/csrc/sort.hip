@@ -22,6 +22,7 @@
 #include "compact.hpp"
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
 
 namespace tid {
@@ -383,12 +384,13 @@ bool radix_sort_pairs(tid_ctx *ctx, uint64_t *k0, uint32_t *v0, uint64_t *k1, ui
     if (n <= 1 || bits <= 0) return false;
     TID_REQUIRE(n < (1ull << 32), TID_E_UNSUPPORTED, "sort: more than 2^32-1 rows");
     if (n <= kSmallMax) {
-        static bool attr_set = false;
-        if (!attr_set) {
+        // once per process, also when several host threads (serving workers,
+        // each with its own context) reach the first small sort together
+        static std::once_flag attr_once;
+        std::call_once(attr_once, [] {
             TID_HIP(hipFuncSetAttribute((const void *)small_sort,
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLds));
-            attr_set = true;
-        }
+        });
         hipLaunchKernelGGL(small_sort, dim3(1), dim3(kSmallBlock), kSmallLds, ctx->stream, k0, v0,
                            (uint32_t)n, bits);
         TID_HIP(hipGetLastError());

@@ -21,6 +21,7 @@
 #include "compact.hpp"
 
 #include <algorithm>
+#include <mutex>
 
 namespace tid {
 
@@ -315,15 +316,17 @@ struct WideSource {
     uint64_t n = 0;
 };
 
+// Allow up to 160 KB of dynamic LDS per workgroup: once per process, also
+// when several host threads (each with its own context) arrive together.
 template <bool SLICE>
 static void set_wide_lds_limit() {
-    static bool done = false;
-    if (done) return;  // allow up to 160 KB of dynamic LDS per workgroup
-    TID_HIP(hipFuncSetAttribute((const void *)wide_count<SLICE>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    TID_HIP(hipFuncSetAttribute((const void *)wide_write<SLICE>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
-    done = true;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        TID_HIP(hipFuncSetAttribute((const void *)wide_count<SLICE>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+        TID_HIP(hipFuncSetAttribute((const void *)wide_write<SLICE>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    });
 }
 
 // One pass for k <= kWideMax eligible patterns into preallocated tables.  In

@@ -178,6 +178,9 @@ class Graph:
         self.n = int(n.value)
         self.device_ptr = int(d.value or 0)
 
+    def count(self, pos: int, lo: int, hi: int) -> int:
+        return tid_graph_count(self, pos, lo, hi)
+
     def free(self):
         if self._p:
             self.ctx._lib.tid_graph_free(self._p)
@@ -270,6 +273,13 @@ def tid_load_file(ctx: Context, path: str) -> Graph:
     out = ctypes.c_void_p()
     _check(ctx.ptr, ctx._lib.tid_load_file(ctx.ptr, path.encode(), ctypes.byref(out)))
     return Graph(ctx, out)
+
+
+def tid_graph_count(g: Graph, pos: int, lo: int, hi: int) -> int:
+    v = ctypes.c_uint64()
+    _check(g.ctx.ptr, g.ctx._lib.tid_graph_count(g._p, int(pos), int(lo), int(hi),
+                                                 ctypes.byref(v)))
+    return int(v.value)
 
 
 def tid_scan(ctx: Context, g: Graph, pattern) -> Table:

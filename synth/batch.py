@@ -6,7 +6,8 @@ target is met with a predicate whose share of the graph is closest (in log
 scale) or, below the rarest predicate's share, with a (predicate, object)
 pair of about the target count; in a chain only the last pattern may bind an
 object.  A query whose join prefix (in plan order, left to right) would
-exceed `max_rows` rows is drawn again.  Sizes are counted from a
+exceed `max_rows` rows, or whose result is empty, draws its selectivities
+again (its pattern count and shape are kept).  Sizes are counted from a
 (predicate, subject)-ordered copy of the graph: counts only, no bindings.
 """
 from __future__ import annotations
@@ -193,9 +194,13 @@ def _one_query(idx: PredIndex, q: int, seed: int, lo: float, hi: float, max_rows
     """Query q of the mix, drawn from its own seeded stream (so queries can be
     drawn in any order or process and come out the same)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0xBA7C, q])))
-    for attempt in range(1000):
-        k = int(rng.integers(1, max_patterns + 1))
-        shape = "star" if rng.random() < 0.5 else "chain"
+    # the pattern count and shape are drawn once, so redraws keep their law;
+    # a count that finds no non-empty query in 250 draws is lowered by one
+    k = k_drawn = int(rng.integers(1, max_patterns + 1))
+    shape = "star" if rng.random() < 0.5 else "chain"
+    for attempt in range(250 * max_patterns):
+        if attempt and attempt % 250 == 0 and k > 1:
+            k -= 1
         sig = 10.0 ** rng.uniform(lo, hi, size=k)
         terms = [_realise(idx, float(s), rng, shape == "star" or i == k - 1)
                  for i, s in enumerate(sig)]
@@ -204,9 +209,9 @@ def _one_query(idx: PredIndex, q: int, seed: int, lo: float, hi: float, max_rows
         else:
             pref = _chain_prefix_counts(idx, terms, max_rows)
         pat_rows = [float(idx.start[t.p + 1] - idx.start[t.p]) for t in terms]
-        if max(pref) <= max_rows:
+        if max(pref) <= max_rows and pref[-1] >= 1:
             break
-    info = {"shape": shape, "k": k, "sigma": [float(s) for s in sig],
+    info = {"shape": shape, "k": k, "k_drawn": k_drawn, "sigma": [float(s) for s in sig],
             "rows": int(pref[-1]), "prefix_rows": [int(x) for x in pref],
             "pattern_rows_max": int(max(pat_rows)), "attempts": attempt + 1}
     return _plan(shape, terms), info

@@ -120,3 +120,56 @@ def range_pattern(g: np.ndarray, keep: float = 0.05) -> Tuple[Pattern, Dict]:
     lo, hi = object_range(g, keep)
     p = Pattern(0, 0, 0, 0, 1, 2, range_pos=2, lo=lo, hi=hi)
     return p, {"lo": lo, "hi": hi}
+
+
+def chain_count(g: np.ndarray, pids) -> int:
+    """Exact row count of the chain (?x0 p1 ?x1) . (?x1 p2 ?x2) . ... by
+    propagating per-value path counts hop by hop (a count, not a result):
+    w(v) = number of paths ending in value v; one hop over predicate q maps
+    w to w'(o) = sum over triples (s, q, o) of w(s)."""
+    s, p, o = g[:, 0], g[:, 1], g[:, 2]
+    size = int(max(s.max(), o.max())) + 1 if g.shape[0] else 1
+    sel = p == pids[0]
+    w = np.bincount(o[sel], minlength=size).astype(np.float64)
+    for q in pids[1:]:
+        sel = p == q
+        w = np.bincount(o[sel], weights=w[s[sel]], minlength=size)
+    return int(round(w.sum()))
+
+
+def chain_query(g: np.ndarray, start_rank: int = 2, lo: float = 1e6, hi: float = 1e8,
+                length: int = 4) -> Tuple[Plan, Dict]:
+    """4-pattern chain (?a p1 ?b) . (?b p2 ?c) . (?c p3 ?d) . (?d p4 ?e) over
+    predicates given by frequency rank.  Candidates start from every hop at
+    rank `start_rank`; while the exact count is below `lo`, hops move one at
+    a time, left to right, to the next more frequent rank (2,2,2,2 ->
+    1,2,2,2 -> 1,1,2,2 -> ...); while it is above `hi`, to the next rarer
+    one (2,2,2,2 -> 3,2,2,2 -> ...).  The first candidate in [lo, hi] is
+    taken."""
+    hist_p = np.bincount(g[:, 1])
+    order = np.argsort(-hist_p, kind="stable")
+    nranks = int((hist_p > 0).sum())
+    ranks = [start_rank] * length
+    tried = {}
+    while all(1 <= r <= nranks for r in ranks) and tuple(ranks) not in tried:
+        pids = [int(order[r - 1]) for r in ranks]
+        c = tried[tuple(ranks)] = chain_count(g, pids)
+        if lo <= c <= hi:
+            break
+        step = -1 if c < lo else 1
+        # the leftmost hop still at the current rank level moves one rank
+        level = max(ranks) if step < 0 else min(ranks)
+        i = ranks.index(level)
+        ranks[i] += step
+    else:
+        raise ValueError(f"no chain in the requested size band: {tried}")
+    pids = [int(order[r - 1]) for r in ranks]
+    names = ["?a", "?b", "?c", "?d", "?e", "?f", "?g"][:length + 1]
+    n: Dict[str, int] = {}
+    plan = Plan()
+    for i in range(length):
+        plan.scan(pat(f"{names[i]} {pids[i]} {names[i + 1]}", n))
+        if i:
+            plan.join(n[names[i]])
+    return plan, {"ranks": list(ranks), "predicates": pids, "rows": tried[tuple(ranks)],
+                  "pattern_rows": [int(hist_p[q]) for q in pids]}

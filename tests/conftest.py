@@ -50,3 +50,33 @@ def graphs():
             _GRAPHS[key] = make_graph(spec)
         return _GRAPHS[key]
     return get
+
+
+# Full-size graphs (500M and 1B triples) take minutes to draw.  Graph
+# generation forks worker processes only while this process holds no GPU
+# state, so when tests that need them are selected they are drawn here,
+# after collection and before the first test initialises the GPU.
+_FULL_SIZE = {"test_gpu_large": "large", "test_gpu_serving_size": "serving"}
+
+
+def pytest_collection_finish(session):
+    want = []
+    for item in session.items:
+        name = _FULL_SIZE.get(item.module.__name__.rsplit(".", 1)[-1])
+        if name and name not in want:
+            want.append(name)
+    if not want:
+        return
+    try:
+        import torch
+        if torch.cuda.device_count() == 0:   # counts devices without initialising one
+            return
+    except Exception:  # noqa: BLE001
+        return
+    import time
+    from synth import CONFIGS, make_graph
+    for name in want:
+        t0 = time.time()
+        _GRAPHS[(name, None)] = make_graph(CONFIGS[name])
+        print(f"\n[conftest] drew the {name} graph ({CONFIGS[name].n} triples) in "
+              f"{time.time() - t0:.0f}s", flush=True)

@@ -343,3 +343,62 @@ ALL_CHECKS = [check_rule11, check_toy_sec3, check_exhaustive_scan, check_exhaust
               check_table3_matrix, check_union_listing4, check_scan_multi_bruteforce,
               check_union_bruteforce, check_filter_bruteforce, check_random_plans,
               check_random_plans_sortmerge, check_invariants_tiny_config]
+
+
+# ---------------------------------------------------------------------------
+# dictionary encoder (Sec. 3: terms -> IDs from 1, first appearance, s p o)
+# ---------------------------------------------------------------------------
+
+SUBCLASS_TRIPLES = [["Cat", "subClassOf", "Mammal"], ["Mammal", "subClassOf", "Animal"],
+                    ["Dog", "subClassOf", "Mammal"], ["Animal", "subClassOf", "Thing"],
+                    ["Cat", "label", "cat"], ["Fish", "subClassOf", "Animal"],
+                    ["Mammal", "subClassOf", "Vertebrate"], ["Cat", "subClassOf", "Mammal"]]
+
+
+def _first_appearance_ids(triples):
+    """IDs by first appearance over the flattened s, p, o stream, computed
+    with numpy's unique (an independent construction of the same order)."""
+    flat = np.array([x for t in triples for x in t], dtype=object)
+    uniq, first = np.unique(flat.astype(str), return_index=True)
+    order = np.argsort(first, kind="stable")
+    return {str(uniq[j]): i + 1 for i, j in enumerate(order)}
+
+
+def check_encoder(O):
+    """Shared and per-position dictionaries: IDs from 1 in order of first
+    appearance; decode inverts encode; and with one shared dictionary a join
+    that pairs an object with a subject (Table 3's OS type) gives, decoded,
+    exactly the join computed on the strings themselves."""
+    gd = _gold("toy_sec3.json")
+    for triples in (gd["triples"], SUBCLASS_TRIPLES):
+        g, dicts = O.encode_graph(triples, shared=True)
+        assert dicts[0] is dicts[1] is dicts[2]
+        want = _first_appearance_ids(triples)
+        assert dicts[0] == want, (dicts[0], want)
+        assert g.min() >= 1 and g.max() == len(want)
+        for row, t in zip(g.tolist(), triples):
+            assert O.decode_row(row, dicts, (0, 1, 2)) == tuple(t)
+        gs, ds = O.encode_graph(triples, shared=False)
+        for pos in range(3):
+            col = [t[pos] for t in triples]
+            assert ds[pos] == _first_appearance_ids([[x] for x in col])
+        for row, t in zip(gs.tolist(), triples):
+            assert O.decode_row(row, ds, (0, 1, 2)) == tuple(t)
+    # the Sec. 3 walk-through under one shared dictionary: 'publishes' is
+    # the 4th distinct term, so the key of "ABCPress publishes ?" is (1,4,?)
+    g, dicts = O.encode_graph(gd["triples"], shared=True)
+    key = [dicts[0][t] if t != "?" else 0 for t in gd["query_terms"]]
+    assert key == [1, 4, 0]
+    assert O.decode_row(g[O.scan_flags(g, Pattern(*key)).astype(bool)][0], dicts,
+                        (0, 1, 2)) == ("ABCPress", "publishes", "JournalA")
+    # OS join on strings, by nested loops over the string triples
+    want = sorted({(a[0], b[2]) for a in SUBCLASS_TRIPLES for b in SUBCLASS_TRIPLES
+                   if a[1] == b[1] == "subClassOf" and a[2] == b[0]})
+    g, dicts = O.encode_graph(SUBCLASS_TRIPLES, shared=True)
+    sc = dicts[0]["subClassOf"]
+    n = {}
+    plan = (Plan().scan(pat(f"?x {sc} ?y", n)).scan(pat(f"?y {sc} ?z", n)).join(n["?y"])
+            .project([n["?x"], n["?z"]]).distinct())
+    got = sorted(O.decode_row(r, dicts, (0, 2)) for r in O.query(g, plan).rows.tolist())
+    assert got == want, (got, want)
+    assert len(want) == 6   # Cat, Dog (x2 each), Mammal and Fish two steps up

@@ -151,6 +151,63 @@ def test_load_rejects_reserved_zero(ctx):
     assert ei.value.status == -1
 
 
+@pytest.mark.parametrize("name,n", [("small", 70001), ("medium", 3_000_000)])
+def test_load_histograms(ctx, graphs, name, n):
+    """The per-position counts built at load (one LDS-aggregated pass) equal
+    numpy's bincount of each column, on uniform and on Zipf-skewed columns
+    (hub subjects and objects), for single IDs and ranges."""
+    g = graphs(name, n)
+    G = ctx.load(g)
+    rng = np.random.default_rng(5)
+    for pos in range(3):
+        want = np.bincount(g[:, pos])
+        cdf = np.concatenate([[0], np.cumsum(want)])
+        top = np.argsort(-want, kind="stable")[:50]
+        ids = np.concatenate([top, rng.integers(1, want.size, 50), [want.size, want.size + 7]])
+        for v in ids:
+            v = int(v)
+            assert G.count(pos, v, v + 1) == (int(want[v]) if v < want.size else 0), (pos, v)
+        for _ in range(30):
+            lo, hi = sorted(int(x) for x in rng.integers(0, want.size + 3, 2))
+            w = int(cdf[min(hi, want.size)] - cdf[min(lo, want.size)])
+            assert G.count(pos, lo, hi) == w, (pos, lo, hi)
+        assert G.count(pos, 0, (1 << 32) - 1) == g.shape[0]
+        assert G.count(pos, 9, 9) == 0
+    G.free()
+
+
+def test_load_file(ctx, graphs, tmp_path):
+    """tid_load_file on a raw TripleID file (N x 12 bytes, little-endian)
+    equals tid_load of the same rows; malformed files are refused."""
+    from paper_1807_01409_amd import TidError
+    from paper_1807_01409_amd.tid import tid_load_file
+    from synth import save_tid
+    g = graphs("small", 70001)
+    path = str(tmp_path / "g.tid")
+    save_tid(path, g)
+    G = tid_load_file(ctx, path)
+    assert G.n == g.shape[0]
+    for p in (Pattern(0, 7, 0, 0, -1, 1), Pattern(0, 0, 0, 0, 1, 2)):
+        assert np.array_equal(ctx.scan(G, p).to_numpy(), oracle.scan(g, p).rows)
+    G.free()
+    empty = str(tmp_path / "empty.tid")
+    open(empty, "wb").close()
+    E = tid_load_file(ctx, empty)
+    assert E.n == 0
+    E.free()
+    bad = str(tmp_path / "bad.tid")
+    with open(bad, "wb") as f:
+        f.write(g[:5].tobytes() + b"\x01\x00")
+    zero = str(tmp_path / "zero.tid")
+    z = g[:5].copy()
+    z[3, 2] = 0
+    z.astype("<u4").tofile(zero)
+    for path in (bad, zero, str(tmp_path / "missing.tid")):
+        with pytest.raises(TidError) as ei:
+            tid_load_file(ctx, path)
+        assert ei.value.status == -1
+
+
 def test_invalid_pattern_rejected(ctx, graphs):
     from paper_1807_01409_amd import TidError
     from paper_1807_01409_amd import _lib as L

@@ -3,8 +3,7 @@ equals the same query run alone (byte for byte), and the oracle's."""
 import numpy as np
 import pytest
 
-import oracle
-from synth import CONFIGS, make_graph
+from oracle_threads import oracle_queries
 from synth.batch import PredIndex, batch_queries, poisson_arrivals
 
 pytestmark = pytest.mark.gpu
@@ -17,7 +16,13 @@ def mix(graphs):
     return g, plans, infos
 
 
-def test_batch_mix_equals_alone_and_oracle(ctx, mix):
+@pytest.fixture(scope="module")
+def mix_oracle(mix):
+    g, plans, _ = mix
+    return [o.rows for o in oracle_queries(g, plans)]
+
+
+def test_batch_mix_equals_alone_and_oracle(ctx, mix, mix_oracle):
     g, plans, infos = mix
     G = ctx.load(g)
     batch = ctx.query_batch(G, plans)
@@ -26,13 +31,13 @@ def test_batch_mix_equals_alone_and_oracle(ctx, mix):
         got = t.to_numpy()
         assert np.array_equal(got, alone)
         assert got.shape[0] == info["rows"]          # exact count from the generator
-    for p, t in list(zip(plans, batch))[:32]:
-        o = oracle.query(g, p)
-        assert np.array_equal(t.to_numpy(), o.rows)
+    assert sum(1 for i in infos if i["rows"] > 0) >= len(infos) // 2
+    for t, o in zip(batch, mix_oracle):
+        assert np.array_equal(t.to_numpy(), o)
 
 
 @pytest.mark.parametrize("budget", [64 << 30, 8 << 20])
-def test_served_mix_equals_alone(ctx, mix, budget):
+def test_served_mix_equals_alone_and_oracle(ctx, mix, mix_oracle, budget):
     from paper_1807_01409_amd.serve import Request, Server
     g, plans, infos = mix
     arrivals = poisson_arrivals(240, qps=4000.0, seed=11)
@@ -50,4 +55,5 @@ def test_served_mix_equals_alone(ctx, mix, budget):
         if key not in alone:
             alone[key] = ctx.query(G, r.plan).to_numpy()
         assert np.array_equal(r.result, alone[key]), r.rid
+        assert np.array_equal(r.result, mix_oracle[key]), r.rid
     assert stats.p99_ms >= stats.p50_ms > 0

@@ -1,7 +1,6 @@
 """The serving configuration's full size (1B triples, 12 GB resident): a scan
 byte for byte against the oracle, and a batch of plans, each of which must
-equal the same plan run alone."""
-import os
+equal the same plan run alone and the oracle's result."""
 import sys
 import time
 
@@ -9,14 +8,10 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import CONFIGS, Pattern, Plan, make_graph, pat
+from oracle_threads import oracle_queries
+from synth import Pattern, Plan, pat
 
-pytestmark = [
-    pytest.mark.gpu, pytest.mark.slow,
-    pytest.mark.skipif(os.environ.get("TID_FULL_SIZE") != "1",
-                       reason="full-size graph (minutes of generation and oracle work); "
-                              "set TID_FULL_SIZE=1 to run"),
-]
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 
 def note(msg):
@@ -24,12 +19,8 @@ def note(msg):
 
 
 @pytest.fixture(scope="module")
-def serving(request):
-    # generated before this module asks for the GPU context: graph generation
-    # forks worker processes only while no GPU state exists in this process
-    note("generating 1B triples")
-    g = make_graph(CONFIGS["serving"])
-    ctx = request.getfixturevalue("ctx")
+def serving(ctx, graphs):
+    g = graphs("serving")   # drawn before the GPU was initialised (conftest)
     note("loading")
     G = ctx.load(g)
     note("resident")
@@ -78,5 +69,9 @@ def test_serving_size_batch_equals_alone(serving):
     note("alone")
     alone = [ctx.query(G, q).to_numpy() for q in plans]
     note("batch")
-    for t, a in zip(ctx.query_batch(G, plans), alone):
-        assert np.array_equal(t.to_numpy(), a)
+    batch = [t.to_numpy() for t in ctx.query_batch(G, plans)]
+    for t, a in zip(batch, alone):
+        assert np.array_equal(t, a)
+    note("oracle (one host thread per plan)")
+    for t, o in zip(batch, oracle_queries(g, plans)):
+        assert np.array_equal(t, o.rows)

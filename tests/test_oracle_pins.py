@@ -108,3 +108,7 @@ def test_scan_multi_bruteforce(oracle_lib):
 
 def test_random_plans_sortmerge_joins(oracle_lib):
     P.check_random_plans_sortmerge(oracle_lib)
+
+
+def test_dictionary_encoder(oracle_lib):
+    P.check_encoder(oracle_lib)
