@@ -1,16 +1,31 @@
 """Benchmark of the TripleID-Q query path on one MI355X.
 
-Workload: the medium graph, 50M triples resident in HBM (subjects Zipf(1.0)
-over 5M IDs, predicates Zipf(1.2) over 1000, objects Zipf(1.1) over 10M,
-seed 2).  One step runs every operator of the path once:
-  scan   (?s p ?o) at selectivities near 0.1%, 1% and 10%   3 graph passes
-  star   (?s pA oA) . (?s pB ?o1) . (?s pC ?o2), sorted      1 pass + 2 joins
-  union  8 subqueries (?s p_r ?o), r = 11..18, DISTINCT      1 pass + sort
-  filter (?s ?p ?o) with o in [lo, hi) keeping ~5%           1 pass
-value = graph passes x N / step time (triples/s).
+Default run (prints one JSON line):
+  headline  the large graph, 500M triples (~6 GB) resident in HBM: subjects
+            Zipf(1.0) over 5e7 IDs, predicates Zipf(1.2) over 1000, objects
+            Zipf(1.1) over 1e8 (permuted), seed 3.  One step runs every
+            operator of the path once:
+              scan   (?s p ?o) at selectivities near 0.1%, 1% and 10%
+              chain  (?a p1 ?b).(?b p2 ?c).(?c p3 ?d).(?d p4 ?e), exact
+                     count in [1e6, 1e8]
+              union  8 subqueries (?s p_r ?o), r = 11..18, DISTINCT
+              filter (?s ?p ?o) with o in [lo, hi) keeping ~5%
+            value = scan triples/s: N / (mean duration of the step's four
+            single-pattern scan launches), each launch timed with HIP events
+            on the library's stream after a 1 GiB scratch write that evicts
+            the last-level cache.
+  medium    the same scans on the 50M-triple medium graph.
+  batched   1024 queries (1-6 patterns, star/chain, per-pattern selectivity
+            log-uniform in [1e-6, 1e-1]) on the 200M-triple batched graph:
+            one tid_query_batch call against 1024 tid_query calls.
+  serving   the continuous-batching server on the 1B-triple serving graph,
+            Poisson arrivals at 2000 queries/s for 10 s from a pool of 1024
+            queries of the batched mix: p50/p99 latency, sustained queries/s.
+  cpu_baseline  the oracle on the host over the headline's four scans:
+            single-threaded, and on every host core (one slice per thread).
 
-Prints one JSON line.  --gpus N with N > 1 is refused: this build measures
-one GPU.
+--workload picks one part alone.  --gpus N with N > 1 is refused: this build
+measures one GPU.
 """
 from __future__ import annotations
 
@@ -27,10 +42,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+FLUSH_BYTES = 1 << 30     # scratch written before each timed launch (> 256 MB MALL)
 
 
 def log(msg):
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench] {time.strftime('%H:%M:%S')} {msg}", file=sys.stderr, flush=True)
 
 
 def source_hash(paths):
@@ -41,14 +57,15 @@ def source_hash(paths):
     return h.hexdigest()[:16]
 
 
-SCAN_SOURCES = ["paper_1807_01409_amd/csrc/scan.hip", "paper_1807_01409_amd/csrc/compact.hpp",
+SCAN_SOURCES = ["paper_1807_01409_amd/csrc/scan_common.hpp", "paper_1807_01409_amd/csrc/scan_single.hip",
+                "paper_1807_01409_amd/csrc/compact.hpp",
                 "paper_1807_01409_amd/csrc/device_common.hpp"]
 
 
-def measured_traffic(kernel_hash):
-    """HBM bytes per launch of the scan from the committed rocprofv3 counter
+def measured_traffic(name, kernel_hash):
+    """HBM bytes per launch of the scan from a committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", "scan_medium_counters.json")
+    path = os.path.join(ROOT, "profiles", f"scan_{name}_counters.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -58,87 +75,237 @@ def measured_traffic(kernel_hash):
     return d.get("hbm_bytes_per_launch")
 
 
-def build_workload(g):
-    from synth.queries import (predicate_for_selectivity, range_pattern, star_query,
-                               union_query)
-    from synth import Pattern
-    preds = [predicate_for_selectivity(g, s) for s in (1e-3, 1e-2, 1e-1)]
-    scans = [Pattern(0, p, 0, 0, -1, 1) for p, _ in preds]
-    star, star_info = star_query(g)
-    union, union_info = union_query(g)
-    rng, rng_info = range_pattern(g)
-    return {"preds": preds, "scans": scans, "star": star, "star_info": star_info,
-            "union": union, "union_info": union_info, "range": rng, "range_info": rng_info}
+def host_info():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"nproc": os.cpu_count(), "available": avail, "cpu_model": model}
 
 
-def cpu_baseline(g, w):
-    """The oracle, as it stands, on this host: one full step of the same
-    workload (single-threaded plain C), repeated while under ~20 s."""
-    import oracle
-    oracle.build(force=False)
-    n = g.shape[0]
-    reps, t_total = 0, 0.0
-    per = {}
-    while reps < 3 and t_total < 20.0:
-        t0 = time.perf_counter()
-        for p in w["scans"]:
-            oracle.scan(g, p)
-        t1 = time.perf_counter()
-        oracle.query(g, w["star"])
-        t2 = time.perf_counter()
-        oracle.query(g, w["union"])
-        t3 = time.perf_counter()
-        oracle.scan(g, w["range"])
-        t4 = time.perf_counter()
-        per = {"scans_s": t1 - t0, "star_s": t2 - t1, "union_s": t3 - t2, "filter_s": t4 - t3}
-        t_total += t4 - t0
-        reps += 1
-    step_s = t_total / reps
-    return {"value": 6 * n / step_s, "unit": "triples/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full step on the same 50M-triple graph, {reps} rep(s), "
-                      f"single-threaded plain C (gcc -O2); last rep: "
-                      + ", ".join(f"{k} {v:.2f}" for k, v in per.items())}
+# ---------------------------------------------------------------------------
+# inputs (drawn before any GPU state exists, so generation may fork workers)
+# ---------------------------------------------------------------------------
 
-
-def event_time(torch, stream, fn, reps):
-    """Average seconds per call of fn, with HIP events on `stream`, calls
-    queued back to back.  Each result is released right after its call (in
-    stream order), so the allocator reuses one block and no allocation falls
-    inside the timed region."""
-    fn().free()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    for _ in range(reps):
-        fn().free()
-    ev1.record(stream)
-    ev1.synchronize()
-    return ev0.elapsed_time(ev1) / 1e3 / reps
-
-
-def batched(args):
-    """1024 queries (1-6 patterns, star/chain, per-pattern selectivity
-    log-uniform in [1e-6, 1e-1]) on the 200M-triple batched graph: one
-    tid_query_batch call against 1024 tid_query calls, results compared."""
-    import torch
-    from paper_1807_01409_amd import Context
+def draw_graph(name, n=None):
     from synth import CONFIGS, make_graph
-    from synth.batch import PredIndex, batch_queries
-
-    spec = CONFIGS["batched"] if args.n is None else CONFIGS["batched"].with_n(args.n)
+    spec = CONFIGS[name] if n is None else CONFIGS[name].with_n(n)
     t0 = time.time()
     g = make_graph(spec)
-    log(f"generated {spec.n} triples in {time.time() - t0:.1f}s")
+    log(f"drew the {name} graph: {spec.n} triples in {time.time() - t0:.1f}s")
+    return spec, g
+
+
+def draw_mix(name, spec, g, nq, seed):
+    """The workload's query mix: the stored mix of synth/mixes when it was
+    drawn on this graph (same config, size and seed) with this many queries,
+    else drawn here."""
+    from synth.mixes import make_mixes
+    if os.path.exists(make_mixes.path_of(name)):
+        plans, infos, head = make_mixes.load(name)
+        if head["graph"] == spec.as_dict() and head["queries"] == nq:
+            log(f"{name} mix: {nq} stored queries (drawn on this graph by "
+                f"synth/mixes/make_mixes.py)")
+            return plans, infos
+    from synth.batch import PredIndex, batch_queries
     t0 = time.time()
     idx = PredIndex(g)
-    plans, infos = batch_queries(idx, nq=args.queries, seed=spec.seed)
+    log(f"predicate index in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    plans, infos = batch_queries(idx, nq=nq, seed=seed)
     del idx
     rows = np.array([i["rows"] for i in infos])
-    log(f"{len(plans)} queries in {time.time() - t0:.1f}s; rows p50 {np.median(rows):.0f} "
-        f"max {rows.max()}; patterns {sum(i['k'] for i in infos)}")
+    log(f"{len(plans)} queries in {time.time() - t0:.1f}s; rows p50 {np.median(rows):.0f}, "
+        f"empty {np.mean(rows == 0):.3f}; patterns {sum(i['k'] for i in infos)}")
+    return plans, infos
+
+
+def mix_summary(infos):
+    rows = np.array([i["rows"] for i in infos])
+    ks = np.bincount([i["k"] for i in infos], minlength=7)[1:]
+    return {"queries": len(infos), "patterns": int(sum(i["k"] for i in infos)),
+            "patterns_per_query": [int(x) for x in ks],
+            "stars": int(sum(i["shape"] == "star" for i in infos)),
+            "empty_share": float(np.mean(rows == 0)),
+            "rows_quantiles_p10_p50_p90_p99_max":
+                [int(x) for x in np.quantile(rows, [0.1, 0.5, 0.9, 0.99, 1.0])]}
+
+
+def scan_workload(g, chain=True):
+    from synth import Pattern
+    from synth.queries import (chain_query, predicate_for_selectivity, range_pattern,
+                               union_query)
+    preds = [predicate_for_selectivity(g, s) for s in (1e-3, 1e-2, 1e-1)]
+    w = {"preds": preds, "scans": [Pattern(0, p, 0, 0, -1, 1) for p, _ in preds]}
+    w["range"], w["range_info"] = range_pattern(g)
+    w["union"], w["union_info"] = union_query(g)
+    if chain:
+        t0 = time.time()
+        w["chain"], w["chain_info"] = chain_query(g)
+        log(f"chain {w['chain_info']} chosen in {time.time() - t0:.1f}s")
+    return w
+
+
+# ---------------------------------------------------------------------------
+# timing
+# ---------------------------------------------------------------------------
+
+class Timer:
+    """HIP events on the library's stream (the stream its kernels run on)."""
+
+    def __init__(self, torch, ctx):
+        self.torch = torch
+        self.ctx = ctx
+        self.scratch = torch.empty(FLUSH_BYTES // 4, dtype=torch.int32, device="cuda")
+
+    def flush(self):
+        with self.torch.cuda.stream(self.ctx.stream):
+            self.scratch.fill_(1)
+
+    def launches(self, fn, reps, flush=True):
+        """Durations (s) of `reps` calls of fn, each bracketed by events and,
+        with flush, preceded by the scratch write.  fn returns a table (freed
+        in stream order) or None."""
+        torch = self.torch
+        out = fn()
+        if out is not None:
+            out.free()
+        evs = []
+        for _ in range(reps):
+            if flush:
+                self.flush()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(self.ctx.stream)
+            out = fn()
+            e1.record(self.ctx.stream)
+            if out is not None:
+                out.free()
+            evs.append((e0, e1))
+        self.ctx.synchronize()
+        return [a.elapsed_time(b) / 1e3 for a, b in evs]
+
+
+def scan_measurements(torch, ctx, G, n, w, reps):
+    """Per scan: median launch time over `reps` flushed launches, rows,
+    columns, bytes (12 B per triple read + 4 B per output cell written)."""
+    tm = Timer(torch, ctx)
+    per = []
+    for p in w["scans"] + [w["range"]]:
+        t = ctx.scan(G, p)
+        rows, cols = t.nrows, t.ncols
+        t.free()
+        d = tm.launches(lambda: ctx.scan(G, p), reps)
+        med = float(np.median(d))
+        b = 12.0 * n + 4.0 * cols * rows
+        per.append({"rows": rows, "cols": cols, "us": round(med * 1e6, 2),
+                    "us_p90": round(float(np.percentile(d, 90)) * 1e6, 2),
+                    "GBps": round(b / med / 1e9, 1), "bytes": b})
+    # read ceiling: the same bytes read with the scan's access shape and with
+    # 16-byte loads, nothing else done
+    probe = {}
+    for mode, name in ((0, "dwordx3"), (1, "dwordx4")):
+        d = tm.launches(lambda: ctx.read_probe(G.device_ptr, 12 * n, mode), reps)
+        probe[name] = round(12.0 * n / float(np.median(d)) / 1e9, 1)
+    del tm
+    return per, probe
+
+
+# ---------------------------------------------------------------------------
+# parts
+# ---------------------------------------------------------------------------
+
+def headline(torch, args, spec, g, w):
+    from paper_1807_01409_amd import Context
     ctx = Context(0)
     G = ctx.load(g)
+    ctx.synchronize()
+    log("large graph resident")
+
+    def step():
+        for p in w["scans"]:
+            ctx.scan(G, p).free()
+        ctx.query(G, w["chain"]).free()
+        ctx.query(G, w["union"]).free()
+        ctx.scan(G, w["range"]).free()
+
+    for _ in range(args.warmup):
+        step()
+    ctx.synchronize()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    ctx.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    log(f"{ms_per_step:.3f} ms/step over {args.steps} steps")
+
+    per, probe = scan_measurements(torch, ctx, G, spec.n, w, args.reps)
+    dur = sum(x["us"] for x in per) * 1e-6
+    achieved = sum(x["bytes"] for x in per) / dur / 1e9
+    value = len(per) * spec.n / dur
+    log(f"scans {per}; probe GB/s {probe}")
+    tm = Timer(torch, ctx)
+    breakdown = {}
+    for name in ("chain", "union"):
+        d = tm.launches(lambda: ctx.query(G, w[name]), 3)
+        breakdown[f"{name}_query_ms"] = round(float(np.median(d)) * 1e3, 3)
+        breakdown[f"{name}_rows"] = ctx.query(G, w[name]).nrows
+    del tm
+    log(f"breakdown {breakdown}")
+    khash = source_hash(SCAN_SOURCES)
+    res = {
+        "value": value, "ms_per_step": ms_per_step,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic("large", khash),
+                     "kernel": "single-pattern scan ScanSrc<1> 512x8: compact_kernel "
+                               "(block-ranged) for sparse outputs, chunk_compact_kernel for "
+                               "dense ones",
+                     "read_probe_GBps": probe,
+                     "frac_of_read_probe": achieved / probe["dwordx3"],
+                     "per_launch": [{k: v for k, v in x.items() if k != "bytes"} for x in per]},
+        "breakdown": breakdown,
+    }
+    G.free()
+    ctx.close()
+    return res
+
+
+def medium_part(torch, args, spec, g, w):
+    from paper_1807_01409_amd import Context
+    ctx = Context(0)
+    G = ctx.load(g)
+    per, probe = scan_measurements(torch, ctx, G, spec.n, w, args.reps)
+    dur = sum(x["us"] for x in per) * 1e-6
+    achieved = sum(x["bytes"] for x in per) / dur / 1e9
+    G.free()
+    ctx.close()
+    log(f"medium scans {per}")
+    return {"workload": f"medium graph {spec.n} triples (s Zipf 1.0/5M, p Zipf 1.2/1000, "
+                        "o Zipf 1.1/10M): the same four scans",
+            "value": len(per) * spec.n / dur, "unit": "triples/s",
+            "frac": achieved / HBM_PEAK_GBS, "read_probe_GBps": probe,
+            "frac_of_read_probe": achieved / probe["dwordx3"],
+            "per_launch": [{k: v for k, v in x.items() if k != "bytes"} for x in per]}
+
+
+def batched_part(torch, args, spec, g, plans, infos):
+    from paper_1807_01409_amd import Context
+    ctx = Context(0)
+    G = ctx.load(g)
+    ctx.synchronize()
 
     def serial():
         return [ctx.query(G, p) for p in plans]
@@ -146,73 +313,46 @@ def batched(args):
     def batch():
         return ctx.query_batch(G, plans)
 
-    for t in batch():           # warm-up both paths (allocator, code objects)
+    for t in batch():            # warm-up both paths (allocator, code objects)
         t.free()
     for t in serial()[:64]:
         t.free()
-    torch.cuda.synchronize()
+    ctx.synchronize()
     res = {}
-    for name, fn in (("batched", batch), ("serial", serial)):
+    keep = {}
+    for name, fn, reps in (("batched", batch, args.batch_reps), ("serial", serial, 2)):
         best = None
-        for _ in range(args.steps):
-            torch.cuda.synchronize()
+        for _ in range(reps):
+            ctx.synchronize()
             t0 = time.perf_counter()
             out = fn()
-            torch.cuda.synchronize()
+            ctx.synchronize()
             dt = time.perf_counter() - t0
             best = dt if best is None else min(best, dt)
-            if name == "batched":
-                keep_b = out
-            else:
-                keep_s = out
-        res[name] = {"s": best, "qps": len(plans) / best}
+            if name in keep:
+                for t in keep[name]:
+                    t.free()
+            keep[name] = out
+        res[name] = best
         log(f"{name}: {best * 1e3:.1f} ms, {len(plans) / best:.0f} queries/s")
-    # identity: each query in the batch equals the same query alone
-    mism = 0
-    for a, b in zip(keep_b, keep_s):
-        if not np.array_equal(a.to_numpy(), b.to_numpy()):
-            mism += 1
-    out = {
-        "metric": "batched vs serial queries/s",
-        "value": res["batched"]["qps"], "unit": "queries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": 1, "ms_per_step": res["batched"]["s"] * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"batched graph {spec.n} triples, {len(plans)} queries, 1-6 "
-                               "patterns, star/chain 50/50, selectivity log-U[1e-6,1e-1]",
-                   "n_triples": spec.n, "queries": len(plans),
-                   "patterns": int(sum(i["k"] for i in infos)),
-                   "rows_quantiles": [int(x) for x in np.quantile(rows, [0.5, 0.9, 0.99, 1.0])]},
-        "serial_qps": res["serial"]["qps"],
-        "speedup_vs_serial": res["batched"]["qps"] / res["serial"]["qps"],
-        "batch_equals_alone_mismatches": mism,
-    }
-    print(json.dumps(out), flush=True)
+    mism = sum(0 if np.array_equal(a.to_numpy(), b.to_numpy()) else 1
+               for a, b in zip(keep["batched"], keep["serial"]))
+    G.free()
     ctx.close()
+    return {"metric": "batched vs serial queries/s", "unit": "queries/s",
+            "value": len(plans) / res["batched"], "ms_per_batch": res["batched"] * 1e3,
+            "serial_value": len(plans) / res["serial"], "serial_ms": res["serial"] * 1e3,
+            "speedup_vs_serial": res["serial"] / res["batched"],
+            "batch_equals_alone_mismatches": mism,
+            "workload": f"batched graph {spec.n} triples (s Zipf 1.0/2e7, p Zipf 1.2/1000, "
+                        "o Zipf 1.1/4e7); 1024 queries, 1-6 patterns, star/chain, "
+                        "selectivity log-U[1e-6,1e-1]",
+            "mix": mix_summary(infos)}
 
 
-def serving(args):
-    """Continuous-batching server on the 1B-triple serving graph resident in
-    HBM: Poisson arrivals at --qps drawn from a pool of --queries queries of
-    the batched mix (1-6 patterns, star/chain, selectivity log-U[1e-6,1e-1]),
-    admitted by estimated result bytes against --budget-gb.  Reports p50/p99
-    latency and sustained queries/s, and checks that sampled requests return
-    the same rows as the same query run alone."""
+def serving_part(args, spec, g, plans, infos):
     from paper_1807_01409_amd.serve import Request, Server
-    from synth import CONFIGS, make_graph
-    from synth.batch import PredIndex, batch_queries, poisson_arrivals
-
-    spec = CONFIGS["serving"] if args.n is None else CONFIGS["serving"].with_n(args.n)
-    t0 = time.time()
-    g = make_graph(spec)
-    log(f"generated {spec.n} triples in {time.time() - t0:.1f}s")
-    t0 = time.time()
-    idx = PredIndex(g)
-    log(f"index in {time.time() - t0:.1f}s")
-    t0 = time.time()
-    plans, infos = batch_queries(idx, nq=args.queries, seed=spec.seed)
-    del idx
-    log(f"{len(plans)} queries in {time.time() - t0:.1f}s")
+    from synth.batch import poisson_arrivals
     n_req = int(args.qps * args.duration)
     arrivals = poisson_arrivals(n_req, args.qps, spec.seed)
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([spec.seed, 0x5E7F])))
@@ -220,7 +360,7 @@ def serving(args):
     reqs = [Request(i, plans[int(pick[i])], float(arrivals[i])) for i in range(n_req)]
     srv = Server(g, workers=args.serve_workers, budget_bytes=int(args.budget_gb * (1 << 30)),
                  max_batch=args.max_batch)
-    log("graph resident; warm-up burst")
+    log("serving graph resident; warm-up burst")
     srv.run([Request(-1 - i, plans[i % len(plans)], 0.0) for i in range(2 * args.max_batch)])
     check = set(range(0, n_req, max(1, n_req // 64)))
     st = srv.run(reqs, keep_results=check, warmup_s=args.warmup_s)
@@ -234,40 +374,141 @@ def serving(args):
             if not np.array_equal(t.to_numpy(), r.result):
                 mism += 1
             t.free()
-    rows = np.array([i["rows"] for i in infos])
-    out = {
-        "metric": "serving p50/p99 latency and sustained queries/s",
-        "value": st.qps, "unit": "queries/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": st.wall_s * 1e3, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
-        "config": {"workload": f"serving graph {spec.n} triples resident in HBM; Poisson "
-                               f"arrivals at {args.qps:g} q/s for {args.duration:g}s from a pool "
-                               f"of {len(plans)} batched-mix queries; result budget "
-                               f"{args.budget_gb:g} GiB",
-                   "n_triples": spec.n, "requests": n_req, "offered_qps": args.qps,
-                   "workers": args.serve_workers, "max_batch": args.max_batch,
-                   "warmup_s": args.warmup_s,
-                   "pool_rows_quantiles": [int(x) for x in np.quantile(rows, [0.5, 0.9, 0.99, 1.0])]},
-        "completed_after_warmup": st.completed, "mean_batch": st.mean_batch,
-        "max_queue": st.max_queue, "max_inflight_bytes": st.max_inflight_bytes,
-        "mix_equals_alone_checked": len(check), "mix_equals_alone_mismatches": mism,
-    }
-    print(json.dumps(out), flush=True)
     srv.close()
+    return {"metric": "serving p50/p99 latency and sustained queries/s", "unit": "queries/s",
+            "value": st.qps, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
+            "offered_qps": args.qps, "requests": n_req, "duration_s": args.duration,
+            "warmup_s": args.warmup_s, "completed_after_warmup": st.completed,
+            "mean_batch": st.mean_batch, "max_queue": st.max_queue,
+            "max_inflight_bytes": st.max_inflight_bytes,
+            "budget_gib": args.budget_gb, "workers": args.serve_workers,
+            "mix_equals_alone_checked": len(check), "mix_equals_alone_mismatches": mism,
+            "workload": f"serving graph {spec.n} triples resident in HBM (s Zipf 1.0/1e8, "
+                        "p Zipf 1.2/1000, o Zipf 1.1/2e8); Poisson arrivals from a pool of "
+                        f"{len(plans)} batched-mix queries",
+            "mix": mix_summary(infos)}
+
+
+def cpu_baseline(g, w):
+    """The oracle as it stands, on this host, over the headline's four scans
+    on the same graph: single-threaded, then one contiguous slice per thread
+    on every available core (ctypes releases the interpreter lock for each
+    oracle call; the slices' results concatenated are the whole scan)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    oracle.build(force=False)
+    n = g.shape[0]
+    pats = w["scans"] + [w["range"]]
+    t0 = time.perf_counter()
+    for p in pats:
+        oracle.scan(g, p)
+    single = time.perf_counter() - t0
+    info = host_info()
+    cores = max(1, min(info["available"], 64))
+    bounds = np.linspace(0, n, cores + 1).astype(np.int64)
+    slices = [g[bounds[i]:bounds[i + 1]] for i in range(cores)]
+    with ThreadPoolExecutor(max_workers=cores) as ex:
+        t0 = time.perf_counter()
+        for p in pats:
+            list(ex.map(lambda s: oracle.scan(s, p), slices))
+        multi = time.perf_counter() - t0
+    v1 = len(pats) * n / single
+    vm = len(pats) * n / multi
+    return {"value": vm, "unit": "triples/s", "cores": cores, "kind": "oracle",
+            "single_thread_value": v1,
+            "sample": f"the headline's 4 single-pattern scans over all {n} triples of the "
+                      f"large graph: single-threaded plain C (gcc -O2) {single:.2f} s, and "
+                      f"{cores} threads each running the oracle on one contiguous slice "
+                      f"{multi:.2f} s",
+            **info}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=10, help="flushed launches per timed scan")
+    ap.add_argument("--n", type=int, default=None, help="override the graph size (testing)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="all",
+                    choices=["all", "large", "medium", "batched", "serving", "scan-profile"])
+    ap.add_argument("--profile-graph", default="large", choices=["large", "medium"])
+    ap.add_argument("--queries", type=int, default=1024)
+    ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--qps", type=float, default=2000.0, help="serving: offered load")
+    ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")
+    ap.add_argument("--warmup-s", type=float, default=1.0, help="serving: arrivals not measured")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: result budget")
+    ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--max-batch", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    if args.workload == "scan-profile":
+        scan_profile(args)
+        return
+    parts = ["large", "medium", "batched", "serving"] if args.workload == "all" \
+        else [args.workload]
+
+    # every input is drawn before the GPU is touched
+    inputs = {}
+    for name in parts:
+        spec, g = draw_graph(name, args.n)
+        item = {"spec": spec, "g": g}
+        if name in ("large", "medium"):
+            item["w"] = scan_workload(g, chain=name == "large")
+        else:
+            item["plans"], item["infos"] = draw_mix(name, spec, g, args.queries, spec.seed)
+        inputs[name] = item
+
+    import torch
+    out = {"metric": "scan triples/s (% HBM peak)", "unit": "triples/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic"}
+    if "large" in inputs:
+        it = inputs["large"]
+        w, spec = it["w"], it["spec"]
+        out.update(headline(torch, args, spec, it["g"], w))
+        out["config"] = {
+            "workload": f"large graph: {spec.n} triples (s Zipf 1.0/5e7, p Zipf 1.2/1000, "
+                        "o Zipf 1.1/1e8); step = 3 scans (0.1/1/10%), 4-chain join, 8-way "
+                        "union DISTINCT, 5% object-range filter; value = N / mean launch "
+                        "time of the step's 4 single-pattern scans (flushed, HIP events)",
+            "n_triples": spec.n, "scan_predicates": [p for p, _ in w["preds"]],
+            "scan_selectivity": [round(s, 6) for _, s in w["preds"]],
+            "chain": w["chain_info"], "union": w["union_info"], "range": w["range_info"]}
+        if not args.no_cpu_baseline:
+            out["cpu_baseline"] = cpu_baseline(it["g"], w)
+            log(f"cpu baseline {out['cpu_baseline']}")
+        del inputs["large"]
+    if "medium" in inputs:
+        it = inputs.pop("medium")
+        res = medium_part(torch, args, it["spec"], it["g"], it["w"])
+        if args.workload == "medium":
+            out.update({"value": res["value"], "config": {"workload": res["workload"]},
+                        "roofline": {"bound": "hbm", "frac": res["frac"]}})
+        out["medium"] = res
+    if "batched" in inputs:
+        it = inputs.pop("batched")
+        out["batched"] = batched_part(torch, args, it["spec"], it["g"], it["plans"], it["infos"])
+    if "serving" in inputs:
+        it = inputs.pop("serving")
+        out["serving"] = serving_part(args, it["spec"], it["g"], it["plans"], it["infos"])
+    print(json.dumps(out), flush=True)
 
 
 def scan_profile(args):
-    """Short run for rocprofv3 counter collection: each of the benchmark's
-    four single-pattern scans `--steps` times, then a plain device copy of a
-    graph-sized buffer (the calibration kernel for the byte counters)."""
+    """Short run for rocprofv3 counter collection: each of the headline's
+    four single-pattern scans `--steps` times on the chosen graph, then a
+    plain device copy of a graph-sized buffer (the calibration kernel for the
+    byte counters)."""
+    spec, g = draw_graph(args.profile_graph, args.n)
+    w = scan_workload(g, chain=False)
     import torch
     from paper_1807_01409_amd import Context
-    from synth import CONFIGS, make_graph
-
-    spec = CONFIGS["medium"] if args.n is None else CONFIGS["medium"].with_n(args.n)
-    g = make_graph(spec)
-    w = build_workload(g)
     ctx = Context(0)
     G = ctx.load(g)
     for p in w["scans"] + [w["range"]]:
@@ -282,136 +523,6 @@ def scan_profile(args):
     torch.cuda.synchronize()
     log(f"scan-profile done: {len(w['scans']) + 1} scans x {args.steps}, copy of "
         f"{spec.n * 12} bytes x {args.steps}")
-    ctx.close()
-
-
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--n", type=int, default=None, help="override graph size (testing)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=["medium", "batched", "serving", "scan-profile"],
-                    default="medium")
-    ap.add_argument("--queries", type=int, default=1024)
-    ap.add_argument("--qps", type=float, default=2000.0, help="serving: offered load")
-    ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")
-    ap.add_argument("--warmup-s", type=float, default=1.0, help="serving: arrivals not measured")
-    ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: result budget")
-    ap.add_argument("--serve-workers", type=int, default=2)
-    ap.add_argument("--max-batch", type=int, default=256)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
-    if args.workload == "batched":
-        batched(args)
-        return
-    if args.workload == "serving":
-        serving(args)
-        return
-    if args.workload == "scan-profile":
-        scan_profile(args)
-        return
-
-    import torch
-    from paper_1807_01409_amd import Context
-    from synth import CONFIGS, make_graph
-
-    spec = CONFIGS["medium"] if args.n is None else CONFIGS["medium"].with_n(args.n)
-    t0 = time.time()
-    g = make_graph(spec)
-    log(f"generated {spec.n} triples in {time.time() - t0:.1f}s")
-    w = build_workload(g)
-    log(f"workload: preds {w['preds']} star {w['star_info']} union {w['union_info']} "
-        f"range {w['range_info']}")
-
-    ctx = Context(0)
-    G = ctx.load(g)
-    torch.cuda.synchronize()
-    log("graph resident")
-
-    def step():
-        for p in w["scans"]:
-            ctx.scan(G, p).free()
-        ctx.query(G, w["star"]).free()
-        ctx.query(G, w["union"]).free()
-        ctx.scan(G, w["range"]).free()
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    passes = 6
-    ms_per_step = elapsed / args.steps * 1e3
-    value = passes * spec.n * args.steps / elapsed
-    log(f"{ms_per_step:.3f} ms/step, {value / 1e9:.1f} G triples/s")
-
-    # Dominant kernel: the single-pattern scan.  Average launch duration with
-    # HIP events on the context's stream (the stream its kernels run on).
-    reps = 20
-    alg_bytes = dur_s = 0.0
-    per_launch = []
-    for p in w["scans"] + [w["range"]]:
-        t = ctx.scan(G, p)
-        rows, ncols = t.nrows, t.ncols
-        t.free()
-        d = event_time(torch, ctx.stream, lambda: ctx.scan(G, p), reps)
-        b = 12.0 * spec.n + 4.0 * ncols * rows
-        alg_bytes += b
-        dur_s += d
-        per_launch.append({"rows": rows, "cols": ncols, "us": round(d * 1e6, 2),
-                           "GBps": round(b / d / 1e9, 1)})
-    achieved = alg_bytes / dur_s / 1e9
-    khash = source_hash(SCAN_SOURCES)
-    breakdown = {
-        "star_query_ms": event_time(torch, ctx.stream, lambda: ctx.query(G, w["star"]), 5) * 1e3,
-        "union_query_ms": event_time(torch, ctx.stream, lambda: ctx.query(G, w["union"]), 5) * 1e3,
-        "star_rows": ctx.query(G, w["star"]).nrows,
-        "union_rows": ctx.query(G, w["union"]).nrows,
-    }
-    log(f"scan launches: {per_launch}; {breakdown}")
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(g, w)
-        log(f"cpu baseline {cpu}")
-
-    out = {
-        "metric": "scan triples/s (% HBM peak)",
-        "value": value,
-        "unit": "triples/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"medium graph: {spec.n} triples (s Zipf 1.0/5M, p Zipf 1.2/1000, "
-                               "o Zipf 1.1/10M); step = 3 scans (0.1/1/10%), 3-star join, "
-                               "8-way union DISTINCT, 5% object-range filter",
-                   "n_triples": spec.n, "graph_passes_per_step": passes,
-                   "scan_predicates": [p for p, _ in w["preds"]],
-                   "scan_selectivity": [round(s, 6) for _, s in w["preds"]],
-                   "star": w["star_info"], "union": w["union_info"], "range": w["range_info"]},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(khash),
-                     "kernel": "single-pattern scan, ScanSrc<1> 512x8: compact_kernel "
-                               "(block-ranged) for sparse outputs, chunk_compact_kernel for "
-                               "dense ones",
-                     "per_launch": per_launch},
-        "breakdown": breakdown,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
     ctx.close()
 
 

@@ -259,6 +259,18 @@ tid_status tid_query_batch(tid_ctx *ctx, const tid_graph *g, const tid_plan *con
 tid_status tid_plan_estimate(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan,
                              uint64_t *bytes);
 
+/* ---- measurement ------------------------------------------------------ */
+
+/* Read `bytes` of device memory at `device_ptr` once, as a streaming scan
+   reads the TripleID array (Sec. 3: every triple tested in parallel), and do
+   nothing with the values: the time of this call is the read ceiling a scan
+   of the same bytes is measured against.  mode 0: one 12-byte load per lane
+   per triple, the scan's own access shape; mode 1: one 16-byte load per lane
+   (the pointer must be 16-byte aligned).  A tail shorter than one item is not
+   read.  Asynchronous on the context's stream; writes nothing the caller can
+   observe. */
+tid_status tid_read_probe(tid_ctx *ctx, const void *device_ptr, uint64_t bytes, int32_t mode);
+
 #ifdef __cplusplus
 }
 #endif

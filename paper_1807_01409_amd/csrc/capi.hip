@@ -45,6 +45,7 @@ std::unique_ptr<tid_table> run_query(tid_ctx *, const tid_graph *, const tid_pla
 std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *, const tid_graph *,
                                                   const tid_plan *const *, int);
 uint64_t estimate_plan_bytes(const tid_graph *, const tid_plan *);
+void read_probe(tid_ctx *, const void *, uint64_t, int);
 std::unique_ptr<tid_table> copy_columns(tid_ctx *, const uint32_t *const *, int32_t,
                                         const int32_t *, uint64_t, int);
 }  // namespace tid
@@ -72,8 +73,9 @@ tid_status tid_ctx_create(int device, void *stream, tid_alloc_fn alloc, tid_free
         ctx->alloc_fn = alloc;
         ctx->free_fn = free_fn;
         ctx->user = user;
-        ctx->d_flags = static_cast<uint32_t *>(ctx->alloc(2 * sizeof(uint32_t)));
-        TID_HIP(hipMemsetAsync(ctx->d_flags, 0, 2 * sizeof(uint32_t), ctx->stream));
+        // words 0-1: error and overflow flags; word 2: the read probe's sink
+        ctx->d_flags = static_cast<uint32_t *>(ctx->alloc(4 * sizeof(uint32_t)));
+        TID_HIP(hipMemsetAsync(ctx->d_flags, 0, 4 * sizeof(uint32_t), ctx->stream));
         TID_HIP(hipStreamSynchronize(ctx->stream));
     });
     if (st != TID_OK) {
@@ -89,7 +91,7 @@ void tid_ctx_destroy(tid_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->ep_state) ctx->free(ctx->ep_state, ctx->ep_bytes);
-    if (ctx->d_flags) ctx->free(ctx->d_flags, 2 * sizeof(uint32_t));
+    if (ctx->d_flags) ctx->free(ctx->d_flags, 4 * sizeof(uint32_t));
     if (ctx->rw_dev) ctx->free(ctx->rw_dev, ctx->rw_cap * 16);
     if (ctx->rw_host_ptrs) (void)hipHostFree(ctx->rw_host_ptrs);
     if (ctx->rw_host_vals) (void)hipHostFree(ctx->rw_host_vals);
@@ -243,6 +245,13 @@ tid_status tid_graph_count(const tid_graph *g, int32_t pos, uint32_t lo, uint32_
     if (g->n && g->cdf[pos].empty()) return TID_E_UNSUPPORTED;
     *count = g->n ? g->count_in(pos, lo, hi) : 0;
     return TID_OK;
+}
+
+tid_status tid_read_probe(tid_ctx *ctx, const void *device_ptr, uint64_t bytes, int32_t mode) {
+    return guarded(ctx, [&] {
+        check_ctx(ctx);
+        tid::read_probe(ctx, device_ptr, bytes, mode);
+    });
 }
 
 void tid_graph_free(tid_graph *g) {

@@ -690,6 +690,52 @@ void launch_chunked(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
     TID_HIP(hipGetLastError());
 }
 
+// Block-ranged compaction, in two steps so that callers may bring their own
+// cross-workgroup state: block_ranged_layout lays out the staging areas over
+// `stage_words` words of LDS, fixes the ranges (a.P, a.range, a.k) and
+// returns the state words the launch needs (the ticket and done counters in
+// one word, then k * P count words); block_ranged_launch starts the kernel
+// with that state and a.epoch, and `flags` (2 words: spin limit, overflow).
+template <class Src, int BLOCK, int IPT, int MAXK, int MAXC, bool PREFETCH = false>
+size_t block_ranged_layout(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, int k,
+                           uint32_t stage_words) {
+    constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
+    auto kern = compact_kernel<Src, BLOCK, IPT, MAXK, MAXC, PREFETCH>;
+    const size_t lds = (size_t)stage_words * sizeof(uint32_t);
+    const int blocks_per_cu = resident_blocks((const void *)kern, BLOCK, lds);
+    const uint64_t n = src.n;
+    uint64_t cols_total = 0;
+    for (int j = 0; j < k; ++j) cols_total += (uint64_t)a.out[j].ncols;
+    const uint32_t rows_per = (uint32_t)(stage_words / std::max<uint64_t>(cols_total, 1));
+    uint32_t off = 0;
+    for (int j = 0; j < k; ++j) {
+        a.out[j].stage_off = off;
+        a.out[j].stage_cap = a.out[j].ncols ? rows_per : 0xFFFFFFFFu;
+        off += rows_per * (uint32_t)a.out[j].ncols;
+    }
+    const uint64_t tiles = (n + TILE - 1) / TILE;
+    const uint64_t resident = (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx) *
+                              (uint64_t)std::max<int64_t>(1, ctx->opt.range_factor);
+    uint64_t P = std::max<uint64_t>(1, std::min({tiles, resident, (uint64_t)BLOCK * kPrefixPer}));
+    const uint64_t range = (tiles + P - 1) / P * TILE;
+    P = (n + range - 1) / range;
+    TID_REQUIRE(P < (1ull << 31), TID_E_UNSUPPORTED, "compaction: input too large");
+    a.k = k;
+    a.P = (uint32_t)P;
+    a.range = range;
+    return (size_t)k * P + 1;
+}
+
+template <class Src, int BLOCK, int IPT, int MAXK, int MAXC, bool PREFETCH = false>
+void block_ranged_launch(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a,
+                         uint32_t stage_words, uint64_t *state, uint32_t *flags) {
+    auto kern = compact_kernel<Src, BLOCK, IPT, MAXK, MAXC, PREFETCH>;
+    const size_t lds = (size_t)stage_words * sizeof(uint32_t);
+    hipLaunchKernelGGL(kern, dim3(a.P), dim3(BLOCK), lds, ctx->stream, src, a, state + 1,
+                       reinterpret_cast<uint32_t *>(state), flags);
+    TID_HIP(hipGetLastError());
+}
+
 // Launch the compaction of `n` items over the resident-capacity grid.  The
 // caller fills a.out[0..k) (columns, caps, counts, ncols); staging areas are
 // laid out here over `stage_words` words of LDS.  The context's
@@ -726,28 +772,13 @@ void launch_compact(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
         launch_chunked<Src, BLOCK, IPT, MAXK, MAXC>(ctx, src, a, k, stage_words);
         return;
     }
-    uint32_t off = 0;
-    for (int j = 0; j < k; ++j) {
-        a.out[j].stage_off = off;
-        a.out[j].stage_cap = a.out[j].ncols ? rows_per : 0xFFFFFFFFu;
-        off += rows_per * (uint32_t)a.out[j].ncols;
-    }
-    const uint64_t tiles = (n + TILE - 1) / TILE;
-    const uint64_t resident = (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx) *
-                              (uint64_t)std::max<int64_t>(1, ctx->opt.range_factor);
-    uint64_t P = std::max<uint64_t>(1, std::min({tiles, resident, (uint64_t)BLOCK * kPrefixPer}));
-    const uint64_t range = (tiles + P - 1) / P * TILE;
-    P = (n + range - 1) / range;
-    TID_REQUIRE(P < (1ull << 31), TID_E_UNSUPPORTED, "compaction: input too large");
-    a.k = k;
-    a.P = (uint32_t)P;
-    a.range = range;
     // epoch state: the ticket and done counters (one u64 word), then k * P count words
+    const size_t words = block_ranged_layout<Src, BLOCK, IPT, MAXK, MAXC, PREFETCH>(
+        ctx, src, a, k, stage_words);
     uint64_t *state = nullptr;
-    a.epoch = ctx->next_epoch(((size_t)k * P + 1) * sizeof(uint64_t), &state);
-    hipLaunchKernelGGL(kern, dim3((uint32_t)P), dim3(BLOCK), lds, ctx->stream, src, a, state + 1,
-                       reinterpret_cast<uint32_t *>(state), ctx->d_flags);
-    TID_HIP(hipGetLastError());
+    a.epoch = ctx->next_epoch(words * sizeof(uint64_t), &state);
+    block_ranged_launch<Src, BLOCK, IPT, MAXK, MAXC, PREFETCH>(ctx, src, a, stage_words, state,
+                                                               ctx->d_flags);
 }
 
 }  // namespace tid

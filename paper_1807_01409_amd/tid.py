@@ -164,6 +164,9 @@ class Context:
     def plan_estimate(self, g: "Graph", plan) -> int:
         return tid_plan_estimate(self, g, plan)
 
+    def read_probe(self, device_ptr: int, nbytes: int, mode: int = 0):
+        tid_read_probe(self, device_ptr, nbytes, mode)
+
     def table(self, rows: np.ndarray, vars_: Sequence[int]) -> "Table":
         return tid_table_from_columns(self, rows, vars_)
 
@@ -273,6 +276,11 @@ def tid_load_file(ctx: Context, path: str) -> Graph:
     out = ctypes.c_void_p()
     _check(ctx.ptr, ctx._lib.tid_load_file(ctx.ptr, path.encode(), ctypes.byref(out)))
     return Graph(ctx, out)
+
+
+def tid_read_probe(ctx: Context, device_ptr: int, nbytes: int, mode: int = 0) -> None:
+    _check(ctx.ptr, ctx._lib.tid_read_probe(ctx.ptr, ctypes.c_void_p(int(device_ptr)),
+                                            int(nbytes), int(mode)))
 
 
 def tid_graph_count(g: Graph, pos: int, lo: int, hi: int) -> int:

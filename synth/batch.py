@@ -5,9 +5,10 @@ draws a target selectivity per pattern log-uniformly in [1e-6, 1e-1].  A
 target is met with a predicate whose share of the graph is closest (in log
 scale) or, below the rarest predicate's share, with a (predicate, object)
 pair of about the target count; in a chain only the last pattern may bind an
-object.  A query whose join prefix (in plan order, left to right) would
-exceed `max_rows` rows, or whose result is empty, draws its selectivities
-again (its pattern count and shape are kept).  Sizes are counted from a
+object.  The pattern count and shape of a query are drawn once; its
+selectivities are drawn again while its join prefix (in plan order, left to
+right) would exceed `max_rows` rows, and while its result is empty, up to
+`empty_redraws` times (then an empty result is kept).  Sizes are counted from a
 (predicate, subject)-ordered copy of the graph: counts only, no bindings.
 """
 from __future__ import annotations
@@ -39,8 +40,11 @@ class PredIndex:
         packed = g[order, 0].astype(np.uint64) << np.uint64(32)
         packed |= g[order, 2]
         del order
-        for p in np.nonzero(hist > 1)[0]:
-            packed[self.start[p]:self.start[p + 1]].sort()
+        # numpy's sort releases the interpreter lock: predicates in parallel
+        from concurrent.futures import ThreadPoolExecutor
+        preds = [int(p) for p in np.nonzero(hist > 1)[0]]
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            list(ex.map(lambda p: packed[self.start[p]:self.start[p + 1]].sort(), preds))
         self.s = (packed >> np.uint64(32)).astype(np.uint32)
         self.o = packed.astype(np.uint32)
         del packed
@@ -190,17 +194,24 @@ def _plan(shape: str, terms: List[Term]) -> Plan:
 
 
 def _one_query(idx: PredIndex, q: int, seed: int, lo: float, hi: float, max_rows: int,
-               max_patterns: int) -> Tuple[Plan, Dict]:
+               max_patterns: int, empty_redraws: int = 0) -> Tuple[Plan, Dict]:
     """Query q of the mix, drawn from its own seeded stream (so queries can be
     drawn in any order or process and come out the same)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 0xBA7C, q])))
-    # the pattern count and shape are drawn once, so redraws keep their law;
-    # a count that finds no non-empty query in 250 draws is lowered by one
-    k = k_drawn = int(rng.integers(1, max_patterns + 1))
+    # The pattern count and shape are drawn first and kept, so their laws are
+    # the configured ones; the selectivities are drawn again while the join
+    # prefix exceeds max_rows, and while the result is empty, up to
+    # `empty_redraws` bounded draws (then the last bounded draw is kept, empty
+    # or not).  A count and shape with no bounded draw in 200 tries (a rare
+    # case) are drawn again.
+    bounded = None
+    empties = 0
+    k = int(rng.integers(1, max_patterns + 1))
     shape = "star" if rng.random() < 0.5 else "chain"
-    for attempt in range(250 * max_patterns):
-        if attempt and attempt % 250 == 0 and k > 1:
-            k -= 1
+    for attempt in range(100000):
+        if bounded is None and attempt and attempt % 200 == 0:
+            k = int(rng.integers(1, max_patterns + 1))
+            shape = "star" if rng.random() < 0.5 else "chain"
         sig = 10.0 ** rng.uniform(lo, hi, size=k)
         terms = [_realise(idx, float(s), rng, shape == "star" or i == k - 1)
                  for i, s in enumerate(sig)]
@@ -209,9 +220,13 @@ def _one_query(idx: PredIndex, q: int, seed: int, lo: float, hi: float, max_rows
         else:
             pref = _chain_prefix_counts(idx, terms, max_rows)
         pat_rows = [float(idx.start[t.p + 1] - idx.start[t.p]) for t in terms]
-        if max(pref) <= max_rows and pref[-1] >= 1:
-            break
-    info = {"shape": shape, "k": k, "k_drawn": k_drawn, "sigma": [float(s) for s in sig],
+        if max(pref) <= max_rows:
+            bounded = (k, shape, sig, terms, pref, pat_rows)
+            if pref[-1] >= 1 or empties >= empty_redraws:
+                break
+            empties += 1
+    k, shape, sig, terms, pref, pat_rows = bounded
+    info = {"shape": shape, "k": k, "sigma": [float(s) for s in sig],
             "rows": int(pref[-1]), "prefix_rows": [int(x) for x in pref],
             "pattern_rows_max": int(max(pat_rows)), "attempts": attempt + 1}
     return _plan(shape, terms), info
@@ -226,13 +241,14 @@ def _pool_query(args):
 
 def batch_queries(idx: PredIndex, nq: int = 1024, seed: int = 4, max_rows: int = 1 << 22,
                   sigma_range=(1e-6, 1e-1), max_patterns: int = 6,
-                  workers: int | None = None) -> Tuple[List[Plan], List[Dict]]:
+                  workers: int | None = None, empty_redraws: int = 16
+                  ) -> Tuple[List[Plan], List[Dict]]:
     """nq queries of the mix.  Large mixes are drawn by forked workers unless
     this process has initialised a GPU (then serially); the result does not
     depend on the number of workers."""
     global _POOL_IDX
     lo, hi = np.log10(sigma_range[0]), np.log10(sigma_range[1])
-    jobs = [(q, seed, lo, hi, max_rows, max_patterns) for q in range(nq)]
+    jobs = [(q, seed, lo, hi, max_rows, max_patterns, empty_redraws) for q in range(nq)]
     if workers is None:
         workers = min(16, os.cpu_count() or 1)
     if workers <= 1 or nq < 64 or _gpu_initialised():

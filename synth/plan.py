@@ -133,3 +133,13 @@ class Plan:
     def distinct(self) -> "Plan":
         self.ops += [OP_DISTINCT]
         return self
+
+    # plain-data form (query-mix files) --------------------------------
+    def to_dict(self) -> dict:
+        return {"patterns": [[p.s, p.p, p.o, p.vs, p.vp, p.vo, p.range_pos, p.lo, p.hi]
+                             for p in self.patterns],
+                "ops": [int(x) for x in self.ops]}
+
+    @staticmethod
+    def from_dict(d: dict) -> "Plan":
+        return Plan([Pattern(*map(int, p)) for p in d["patterns"]], [int(x) for x in d["ops"]])

@@ -122,18 +122,22 @@ def range_pattern(g: np.ndarray, keep: float = 0.05) -> Tuple[Pattern, Dict]:
     return p, {"lo": lo, "hi": hi}
 
 
-def chain_count(g: np.ndarray, pids) -> int:
+def chain_count(g: np.ndarray, pids, rows_of=None) -> int:
     """Exact row count of the chain (?x0 p1 ?x1) . (?x1 p2 ?x2) . ... by
     propagating per-value path counts hop by hop (a count, not a result):
     w(v) = number of paths ending in value v; one hop over predicate q maps
-    w to w'(o) = sum over triples (s, q, o) of w(s)."""
-    s, p, o = g[:, 0], g[:, 1], g[:, 2]
-    size = int(max(s.max(), o.max())) + 1 if g.shape[0] else 1
-    sel = p == pids[0]
-    w = np.bincount(o[sel], minlength=size).astype(np.float64)
+    w to w'(o) = sum over triples (s, q, o) of w(s).  rows_of(q), if given,
+    returns the (s, o) columns of predicate q's triples."""
+    if rows_of is None:
+        def rows_of(q):
+            sel = g[:, 1] == q
+            return g[sel, 0], g[sel, 2]
+    size = int(max(g[:, 0].max(), g[:, 2].max())) + 1 if g.shape[0] else 1
+    s, o = rows_of(pids[0])
+    w = np.bincount(o, minlength=size).astype(np.float64)
     for q in pids[1:]:
-        sel = p == q
-        w = np.bincount(o[sel], weights=w[s[sel]], minlength=size)
+        s, o = rows_of(q)
+        w = np.bincount(o, weights=w[s], minlength=size)
     return int(round(w.sum()))
 
 
@@ -151,9 +155,17 @@ def chain_query(g: np.ndarray, start_rank: int = 2, lo: float = 1e6, hi: float =
     nranks = int((hist_p > 0).sum())
     ranks = [start_rank] * length
     tried = {}
+    cols = {}
+
+    def rows_of(q):
+        if q not in cols:
+            sel = g[:, 1] == q
+            cols[q] = (g[sel, 0], g[sel, 2])
+        return cols[q]
+
     while all(1 <= r <= nranks for r in ranks) and tuple(ranks) not in tried:
         pids = [int(order[r - 1]) for r in ranks]
-        c = tried[tuple(ranks)] = chain_count(g, pids)
+        c = tried[tuple(ranks)] = chain_count(g, pids, rows_of)
         if lo <= c <= hi:
             break
         step = -1 if c < lo else 1
