@@ -188,6 +188,25 @@ void tid_table_free(tid_table *t);
    counts matches). */
 tid_status tid_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pattern,
                     tid_table **out);
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the rows
+   tid_scan returns for `pattern`, written into caller buffers, with no device
+   allocation and no host wait.
+     out_cols  ncols device pointers, one per output column (the pattern's
+               distinct variables in s, p, o order; ncols must equal that
+               count; may be NULL when it is 0), each with room for cap_rows
+               uint32 values; rows land in ascending triple position
+     d_count   device pointer to one uint64 that receives the number of
+               matching triples; if it exceeds cap_rows, rows past cap_rows
+               are not written (size cap_rows from tid_graph_count to be safe)
+   The kernel's cross-workgroup state is a fixed device array of the library
+   (one per GPU, 32 KB, held until the process ends; at most 4096 ranges per
+   launch, which every graph size fits).  All calls on one GPU share it:
+   calls that overlap on one GPU (other streams or threads) race and must not
+   be issued.  Asynchronous on the context's stream. */
+tid_status tid_scan_noalloc(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pattern,
+                            uint32_t *const *out_cols, int32_t ncols, uint64_t cap_rows,
+                            uint64_t *d_count);
 /* Sec. 4.1 (keysArray / positionArray[i].query): k <= TID_MAX_MULTI patterns
    answered in one pass over the graph; outs[j] receives exactly what
    tid_scan would return for patterns[j]. */

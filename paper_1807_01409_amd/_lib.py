@@ -56,6 +56,7 @@ SIGNATURES = {
     "tid_graph_count": (_S, [_VP, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, _U64P]),
     "tid_graph_free": (None, [_VP]),
     "tid_read_probe": (_S, [_VP, _VP, ctypes.c_uint64, ctypes.c_int32]),
+    "tid_scan_noalloc": (_S, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_uint64, _VP]),
     "tid_table_info": (_S, [_VP, _VP, _U64P, _I32P, _I32P]),
     "tid_table_column": (_S, [_VP, ctypes.c_int32, _PP]),
     "tid_table_to_host": (_S, [_VP, _VP, _VP, ctypes.c_uint64]),

@@ -46,6 +46,9 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *, const tid_graph *,
                                                   const tid_plan *const *, int);
 uint64_t estimate_plan_bytes(const tid_graph *, const tid_plan *);
 void read_probe(tid_ctx *, const void *, uint64_t, int);
+void noalloc_init(tid_ctx *);
+void scan_noalloc(tid_ctx *, const tid_graph *, const tid_pattern &, uint32_t *const *, int,
+                  uint64_t, uint64_t *);
 std::unique_ptr<tid_table> copy_columns(tid_ctx *, const uint32_t *const *, int32_t,
                                         const int32_t *, uint64_t, int);
 }  // namespace tid
@@ -77,6 +80,8 @@ tid_status tid_ctx_create(int device, void *stream, tid_alloc_fn alloc, tid_free
         ctx->d_flags = static_cast<uint32_t *>(ctx->alloc(4 * sizeof(uint32_t)));
         TID_HIP(hipMemsetAsync(ctx->d_flags, 0, 4 * sizeof(uint32_t), ctx->stream));
         TID_HIP(hipStreamSynchronize(ctx->stream));
+        // once per device: the allocation-free scan's state array
+        tid::noalloc_init(ctx);
     });
     if (st != TID_OK) {
         tid_ctx_destroy(ctx);
@@ -329,6 +334,16 @@ tid_status tid_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pattern
     });
     if (st == TID_OK) *out = t.release();
     return st;
+}
+
+tid_status tid_scan_noalloc(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pattern,
+                            uint32_t *const *out_cols, int32_t ncols, uint64_t cap_rows,
+                            uint64_t *d_count) {
+    return guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(g && pattern, TID_E_INVALID_ARG, "null argument");
+        tid::scan_noalloc(ctx, g, *pattern, out_cols, ncols, cap_rows, d_count);
+    });
 }
 
 tid_status tid_scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *patterns,
