@@ -64,6 +64,8 @@ def _setup(lib):
     lib.or_join_nested.argtypes = [P(_Tab), ctypes.c_int32, P(_Tab), ctypes.c_int32, P(_Tab)]
     lib.or_join_sortmerge.argtypes = [P(_Tab), ctypes.c_int32, P(_Tab), ctypes.c_int32,
                                       P(_Tab)]
+    lib.or_join_outer.argtypes = [P(_Tab), ctypes.c_int32, P(_Tab), ctypes.c_int32,
+                                  ctypes.c_int32, P(_Tab)]
     lib.or_union.argtypes = [P(P(_Tab)), ctypes.c_int32, ctypes.c_int32, P(_Tab)]
     lib.or_sort_rows.argtypes = [P(_Tab)]
     lib.or_distinct.argtypes = [P(_Tab)]
@@ -198,6 +200,19 @@ def join(l: Table, lc: int, r: Table, rc: int, method: str = "nested") -> Table:
     return _from_c(res)
 
 
+JOIN_KINDS = {"inner": 0, "left": 1, "right": 2, "full": 3}
+
+
+def join_outer(l: Table, lc: int, r: Table, rc: int, kind: str = "left") -> Table:
+    """Inner/left/right/full join by nested loops (or_join_outer)."""
+    keep: list = []
+    a, b = _to_c(l, keep), _to_c(r, keep)
+    res = _Tab()
+    _check(_L().or_join_outer(ctypes.byref(a), lc, ctypes.byref(b), rc, JOIN_KINDS[kind],
+                              ctypes.byref(res)), "join_outer")
+    return _from_c(res)
+
+
 def union(ts: Sequence[Table], dedupe: bool) -> Table:
     keep: list = []
     cs = [_to_c(t, keep) for t in ts]
@@ -238,4 +253,4 @@ def query(g, plan) -> Table:
 
 __all__ = ["build", "Table", "OracleError", "scan_flags", "scan_multi", "scan",
            "filter", "join", "union", "sort_rows", "distinct", "query", "encode_graph",
-           "decode_row"]
+           "decode_row", "join_outer", "JOIN_KINDS"]

@@ -248,6 +248,61 @@ int or_join_nested(const or_table *l, int32_t lc, const or_table *r, int32_t rc,
     return or_sort_rows(out);
 }
 
+/* Outer joins by the nested-loop definition: the inner pairs in (L, R)
+   order, then the L rows without a partner (left, full), then the R rows
+   without a partner (right, full); the result is sorted like every join. */
+int or_join_outer(const or_table *l, int32_t lc, const or_table *r, int32_t rc, int32_t kind,
+                  or_table *out)
+{
+    if (lc < 0 || lc >= l->ncols || rc < 0 || rc >= r->ncols) return OR_E_INVALID;
+    if (kind < OR_JOIN_INNER || kind > OR_JOIN_FULL) return OR_E_INVALID;
+    int keep_l = kind == OR_JOIN_LEFT || kind == OR_JOIN_FULL;
+    int keep_r = kind == OR_JOIN_RIGHT || kind == OR_JOIN_FULL;
+    uint64_t cnt = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        uint64_t w = 0;
+        for (uint64_t i = 0; i < l->nrows; ++i) {
+            int matched = 0;
+            for (uint64_t j = 0; j < r->nrows; ++j)
+                if (l->rows[i * l->ncols + lc] == r->rows[j * r->ncols + rc]) {
+                    if (pass) emit_pair(l, i, r, j, rc, out->rows + w * out->ncols);
+                    ++w;
+                    matched = 1;
+                }
+            if (!matched && keep_l) {
+                if (pass) {
+                    uint32_t *dst = out->rows + w * out->ncols;
+                    for (int32_t x = 0; x < out->ncols; ++x)
+                        dst[x] = x < l->ncols ? l->rows[i * l->ncols + x] : 0u;
+                }
+                ++w;
+            }
+        }
+        if (keep_r)
+            for (uint64_t j = 0; j < r->nrows; ++j) {
+                int matched = 0;
+                for (uint64_t i = 0; i < l->nrows && !matched; ++i)
+                    if (l->rows[i * l->ncols + lc] == r->rows[j * r->ncols + rc]) matched = 1;
+                if (matched) continue;
+                if (pass) {
+                    uint32_t *dst = out->rows + w * out->ncols;
+                    const uint32_t *rr = r->rows + j * r->ncols;
+                    int32_t c = 0;
+                    for (int32_t x = 0; x < l->ncols; ++x) dst[c++] = x == lc ? rr[rc] : 0u;
+                    for (int32_t x = 0; x < r->ncols; ++x)
+                        if (x != rc) dst[c++] = rr[x];
+                }
+                ++w;
+            }
+        if (pass == 0) {
+            cnt = w;
+            int st = join_schema(l, lc, r, rc, out, cnt);
+            if (st) return st;
+        }
+    }
+    return or_sort_rows(out);
+}
+
 typedef struct { uint32_t key; uint64_t idx; } key_idx;
 
 static int key_idx_cmp(const void *a, const void *b)
@@ -354,6 +409,7 @@ int or_union(const or_table *const *ts, int32_t k, int32_t dedupe, or_table *out
 #define OP_FILTER 4
 #define OP_PROJECT 5
 #define OP_DISTINCT 6
+#define OP_OPTIONAL 7
 #define OR_STACK 64
 
 static int32_t col_of(const or_table *t, int32_t var)
@@ -497,6 +553,24 @@ int or_query(const uint32_t *g, uint64_t n, const or_pattern *pats, int32_t npat
             if (sp < 2) { st = OR_E_INVALID; goto fail; }
             or_table res;
             st = natural_join(&stack[sp - 2], &stack[sp - 1], var, &res);
+            if (st) goto fail;
+            or_table_free(&stack[sp - 1]);
+            or_table_free(&stack[sp - 2]);
+            sp -= 2;
+            stack[sp++] = res;
+        } else if (op == OP_OPTIONAL) {
+            /* SPARQL OPTIONAL on one shared variable: the left outer join;
+               the two sides may share no other variable */
+            NEED(1);
+            int32_t var = (int32_t)ops[pc++];
+            if (sp < 2) { st = OR_E_INVALID; goto fail; }
+            const or_table *l = &stack[sp - 2], *r = &stack[sp - 1];
+            int32_t lc = col_of(l, var), rc = col_of(r, var);
+            if (lc < 0 || rc < 0) { st = OR_E_SCHEMA; goto fail; }
+            for (int32_t c = 0; c < r->ncols; ++c)
+                if (c != rc && col_of(l, r->vars[c]) >= 0) { st = OR_E_UNSUPPORTED; goto fail; }
+            or_table res;
+            st = or_join_outer(l, lc, r, rc, OR_JOIN_LEFT, &res);
             if (st) goto fail;
             or_table_free(&stack[sp - 1]);
             or_table_free(&stack[sp - 2]);

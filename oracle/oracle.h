@@ -46,6 +46,7 @@ extern "C" {
 #define OR_OK 0
 #define OR_E_INVALID (-1)
 #define OR_E_OOM (-2)
+#define OR_E_UNSUPPORTED (-4)
 #define OR_E_SCHEMA (-5)
 
 typedef struct {
@@ -76,6 +77,18 @@ int or_filter(const or_table *t, int32_t col, uint32_t lo, uint32_t hi, or_table
    merge equal-key runs into index pairs, gather values (Sec. 4.2). */
 int or_join_nested(const or_table *l, int32_t lc, const or_table *r, int32_t rc, or_table *out);
 int or_join_sortmerge(const or_table *l, int32_t lc, const or_table *r, int32_t rc, or_table *out);
+/* outer join kinds (Sec. 4.2: the join library's Left, Right and Outer
+   kinds besides Inner); an unbound cell is 0, as in a union */
+#define OR_JOIN_INNER 0
+#define OR_JOIN_LEFT 1
+#define OR_JOIN_RIGHT 2
+#define OR_JOIN_FULL 3
+/* L join R on L[lc] = R[rc] of the given kind, by nested loops; columns
+   L ++ (R without rc); lexicographic order.  Left/full also keep each L row
+   with no partner, R's columns 0; right/full also keep each R row with no
+   partner, L's columns 0 except lc, which holds the R row's key. */
+int or_join_outer(const or_table *l, int32_t lc, const or_table *r, int32_t rc, int32_t kind,
+                  or_table *out);
 /* outer union over the ordered union of variable ids, unbound cells 0.
    dedupe = 0: concatenation in input order; 1: sorted distinct rows. */
 int or_union(const or_table *const *ts, int32_t k, int32_t dedupe, or_table *out);

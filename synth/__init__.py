@@ -8,10 +8,10 @@ plans.  It computes no scan, join, union, filter or ordering result.
 from .graph import (ColSpec, GraphSpec, CONFIGS, make_graph, zipf_weights,
                     save_tid, load_tid)
 from .plan import (Pattern, Plan, OP_SCAN, OP_JOIN, OP_UNION, OP_FILTER,
-                   OP_PROJECT, OP_DISTINCT, pat)
+                   OP_PROJECT, OP_DISTINCT, OP_OPTIONAL, pat)
 
 __all__ = [
     "ColSpec", "GraphSpec", "CONFIGS", "make_graph", "zipf_weights",
     "save_tid", "load_tid", "Pattern", "Plan", "OP_SCAN", "OP_JOIN",
-    "OP_UNION", "OP_FILTER", "OP_PROJECT", "OP_DISTINCT", "pat",
+    "OP_UNION", "OP_FILTER", "OP_PROJECT", "OP_DISTINCT", "OP_OPTIONAL", "pat",
 ]

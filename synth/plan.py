@@ -16,6 +16,9 @@ A plan is a list of patterns plus a postfix op stream of int32 words:
   OP_FILTER v lo hi       keep rows whose variable v lies in [lo, hi)
   OP_PROJECT n v1 .. vn   keep the listed variables, in that order
   OP_DISTINCT             drop duplicate rows
+  OP_OPTIONAL v           pop R, pop L, push the left outer join of L and R on
+                          variable v (SPARQL OPTIONAL; L and R share no other
+                          variable); R's cells of an L row with no partner are 0
 
 The final result is always returned in lexicographic row order.
 """
@@ -30,6 +33,7 @@ OP_UNION = 3
 OP_FILTER = 4
 OP_PROJECT = 5
 OP_DISTINCT = 6
+OP_OPTIONAL = 7
 
 UINT32_MAX = 0xFFFFFFFF
 
@@ -128,6 +132,10 @@ class Plan:
 
     def project(self, vars_: Sequence[int]) -> "Plan":
         self.ops += [OP_PROJECT, len(vars_), *vars_]
+        return self
+
+    def optional(self, var: int) -> "Plan":
+        self.ops += [OP_OPTIONAL, var]
         return self
 
     def distinct(self) -> "Plan":

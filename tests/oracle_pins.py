@@ -402,3 +402,88 @@ def check_encoder(O):
     got = sorted(O.decode_row(r, dicts, (0, 2)) for r in O.query(g, plan).rows.tolist())
     assert got == want, (got, want)
     assert len(want) == 6   # Cat, Dog (x2 each), Mammal and Fish two steps up
+
+
+# ---------------------------------------------------------------------------
+# outer joins (Sec. 4.2: Left, Right and Outer kinds besides Inner)
+# ---------------------------------------------------------------------------
+
+def _pandas_outer(L, lc, R, rc, how):
+    """The same join by pandas' merge (an independent library routine), with
+    missing cells filled by 0 and the right key column dropped (its value
+    moved into the left key column where the left side is missing)."""
+    import pandas as pd
+    lnames = [f"l{i}" for i in range(L.shape[1])]
+    rnames = [f"r{i}" for i in range(R.shape[1])]
+    dl = pd.DataFrame(L.astype(np.int64), columns=lnames)
+    dr = pd.DataFrame(R.astype(np.int64), columns=rnames)
+    m = dl.merge(dr, left_on=f"l{lc}", right_on=f"r{rc}", how=how)
+    m[f"l{lc}"] = m[f"l{lc}"].fillna(m[f"r{rc}"])
+    m = m.fillna(0)
+    cols = lnames + [c for i, c in enumerate(rnames) if i != rc]
+    out = m[cols].to_numpy().astype(np.uint32) if len(m) else np.zeros((0, len(cols)), np.uint32)
+    return sorted(tuple(int(x) for x in r) for r in out)
+
+
+def check_outer_joins(O):
+    """or_join_outer against pandas' merge on every column pair of small
+    random tables (with repeated keys, keys on one side only, empty sides),
+    plus the identities inner = join, |left| = sum over L rows of
+    max(matches, 1), and right(L, R) = left(R, L) with columns reordered."""
+    rng = np.random.default_rng(31)
+    shapes = [(9, 2, 7, 2), (6, 3, 0, 2), (0, 2, 5, 1), (12, 1, 12, 3), (5, 2, 8, 2)]
+    for nl, kl, nr, kr in shapes:
+        L = rng.integers(1, 6, size=(nl, kl)).astype(np.uint32)
+        R = rng.integers(3, 9, size=(nr, kr)).astype(np.uint32)
+        TL = O.Table(L, list(range(kl)))
+        TR = O.Table(R, list(range(10, 10 + kr)))
+        for lc in range(kl):
+            for rc in range(kr):
+                inner = O.join_outer(TL, lc, TR, rc, "inner")
+                assert _rows(inner) == bf_join([tuple(r) for r in L.tolist()], lc,
+                                               [tuple(r) for r in R.tolist()], rc)
+                for kind, how in (("left", "left"), ("right", "right"), ("full", "outer")):
+                    got = O.join_outer(TL, lc, TR, rc, kind)
+                    assert got.vars == inner.vars
+                    assert _rows(got) == _pandas_outer(L, lc, R, rc, how), (kind, lc, rc)
+                left = O.join_outer(TL, lc, TR, rc, "left")
+                cnt = np.array([np.sum(R[:, rc] == x) for x in L[:, lc]], dtype=np.int64) \
+                    if nr else np.zeros(nl, np.int64)
+                assert left.nrows == int(np.maximum(cnt, 1).sum())
+                # right(L, R) is left(R, L) with the columns put back in order
+                right = O.join_outer(TL, lc, TR, rc, "right")
+                swapped = O.join_outer(TR, rc, TL, lc, "left")
+                perm = []
+                for v in right.vars:
+                    perm.append(swapped.vars.index(v) if v in swapped.vars
+                                else swapped.vars.index(TR.vars[rc]))
+                back = sorted(tuple(int(r[j]) for j in perm) for r in swapped.rows.tolist())
+                assert _rows(right) == back
+
+
+def check_optional_plans(O):
+    """OPTIONAL in a plan: (?s p1 ?a) OPTIONAL (?s p2 ?b) equals the left join
+    of the two scans by brute force; a plan whose sides share a second
+    variable is refused."""
+    g = tiny_graph(41, 40, 5)
+    n = {}
+    plan = Plan().scan(pat("?s 1 ?a", n)).scan(pat("?s 2 ?b", n)).optional(n["?s"])
+    res = O.query(g, plan)
+    A, av = bf_scan(g, pat("?s 1 ?a", dict(n)))
+    B, bv = bf_scan(g, pat("?s 2 ?b", dict(n)))
+    want = []
+    for a in A:
+        hit = [b for b in B if b[0] == a[0]]
+        want += [tuple(a) + (b[1],) for b in hit] or [tuple(a) + (0,)]
+    assert _rows(res) == sorted(want)
+    m = {}
+    bad = (Plan().scan(pat("?s 1 ?a", m)).scan(pat("?s 2 ?a", m)).optional(m["?s"]))
+    try:
+        O.query(g, bad)
+    except Exception as e:  # noqa: BLE001
+        assert getattr(e, "status", None) == -4
+    else:
+        raise AssertionError("OPTIONAL with two shared variables was not refused")
+
+
+ALL_CHECKS += [check_outer_joins, check_optional_plans]

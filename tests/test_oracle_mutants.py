@@ -34,6 +34,10 @@ MUTANTS = [
     ("membership_bit_shifted", "m |= (uint64_t)1 << j;", "m |= (uint64_t)1 << (j + 1) % 64;"),
     ("project_ignores_order", "src[j] = col_of(t, (int32_t)vlist[j]);",
      "src[j] = col_of(t, (int32_t)vlist[j]) >= 0 ? j : -1;"),
+    ("outer_left_drops_unmatched", "if (!matched && keep_l) {", "if (0) {"),
+    ("outer_right_key_not_moved", "dst[c++] = x == lc ? rr[rc] : 0u;", "dst[c++] = 0u;"),
+    ("outer_pads_with_left_value", "dst[x] = x < l->ncols ? l->rows[i * l->ncols + x] : 0u;",
+     "dst[x] = x < l->ncols ? l->rows[i * l->ncols + x] : l->rows[i * l->ncols];"),
 ]
 
 

@@ -112,3 +112,11 @@ def test_random_plans_sortmerge_joins(oracle_lib):
 
 def test_dictionary_encoder(oracle_lib):
     P.check_encoder(oracle_lib)
+
+
+def test_outer_joins(oracle_lib):
+    P.check_outer_joins(oracle_lib)
+
+
+def test_optional_plans(oracle_lib):
+    P.check_optional_plans(oracle_lib)
