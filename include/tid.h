@@ -223,6 +223,21 @@ tid_status tid_filter(tid_ctx *ctx, const tid_table *t, int32_t col, uint32_t lo
    join, 2 sort-merge join (same result).  Synchronises (output size). */
 tid_status tid_join(tid_ctx *ctx, const tid_table *l, int32_t lcol, const tid_table *r,
                     int32_t rcol, int32_t algo, tid_table **out);
+/* Sec. 4.2 (the join library's Left, Right and Outer kinds besides Inner):
+   the join of l and r on l[lcol] = r[rcol] of the given kind, by hash or
+   sort-merge (algo as in tid_join).  Columns and order as in tid_join.
+     TID_JOIN_INNER  the matching pairs (same as tid_join)
+     TID_JOIN_LEFT   also every l row with no partner, r's cells 0
+     TID_JOIN_RIGHT  also every r row with no partner, l's cells 0 except
+                     lcol, which holds the r row's key
+     TID_JOIN_FULL   both
+   Synchronises (output size). */
+#define TID_JOIN_INNER 0
+#define TID_JOIN_LEFT 1
+#define TID_JOIN_RIGHT 2
+#define TID_JOIN_FULL 3
+tid_status tid_join_outer(tid_ctx *ctx, const tid_table *l, int32_t lcol, const tid_table *r,
+                          int32_t rcol, int32_t kind, int32_t algo, tid_table **out);
 /* Sec. 4.1 and Sec. 4.3 (union, DISTINCT): the schema is the ordered union of
    the inputs' variable ids (first appearance first), unbound cells are 0.
    dedupe = 0: the rows of ts[0], then ts[1], ... ; dedupe = 1: the distinct
@@ -244,6 +259,10 @@ tid_status tid_sort(tid_ctx *ctx, const tid_table *t, int32_t distinct, tid_tabl
      TID_OP_FILTER v lo hi      keep rows with lo <= v < hi
      TID_OP_PROJECT n v1..vn    keep variables v1..vn in that order
      TID_OP_DISTINCT            drop repeated rows
+     TID_OP_OPTIONAL v          pop R, pop L; push the left outer join of L and R
+                                on variable v (SPARQL OPTIONAL): L rows with no
+                                partner are kept, R's cells 0; L and R may
+                                share no other variable (TID_E_UNSUPPORTED)
    Exactly one table must remain; it is returned in lexicographic row order. */
 #define TID_OP_SCAN 1
 #define TID_OP_JOIN 2
@@ -251,6 +270,7 @@ tid_status tid_sort(tid_ctx *ctx, const tid_table *t, int32_t distinct, tid_tabl
 #define TID_OP_FILTER 4
 #define TID_OP_PROJECT 5
 #define TID_OP_DISTINCT 6
+#define TID_OP_OPTIONAL 7
 
 typedef struct {
     int32_t n_patterns;

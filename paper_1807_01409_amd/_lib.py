@@ -67,6 +67,8 @@ SIGNATURES = {
     "tid_scan_multi": (_S, [_VP, _VP, ctypes.POINTER(tid_pattern), ctypes.c_int32, _PP]),
     "tid_filter": (_S, [_VP, _VP, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, _PP]),
     "tid_join": (_S, [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32, _PP]),
+    "tid_join_outer": (_S, [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_int32, ctypes.c_int32,
+                            ctypes.c_int32, _PP]),
     "tid_union": (_S, [_VP, _PP, ctypes.c_int32, ctypes.c_int32, _PP]),
     "tid_sort": (_S, [_VP, _VP, ctypes.c_int32, _PP]),
     "tid_query": (_S, [_VP, _VP, ctypes.POINTER(tid_plan), _PP]),

@@ -40,6 +40,8 @@ namespace tid {
 std::unique_ptr<tid_table> join_tables(tid_ctx *, const tid_table *, int, const tid_table *, int,
                                        int);
 std::unique_ptr<tid_table> union_tables(tid_ctx *, const tid_table *const *, int, int);
+std::unique_ptr<tid_table> join_tables_kind(tid_ctx *, const tid_table *, int, const tid_table *,
+                                            int, int, int);
 std::unique_ptr<tid_table> sort_table(tid_ctx *, const tid_table *, int);
 std::unique_ptr<tid_table> run_query(tid_ctx *, const tid_graph *, const tid_plan *);
 std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *, const tid_graph *,
@@ -383,6 +385,19 @@ tid_status tid_join(tid_ctx *ctx, const tid_table *l, int32_t lcol, const tid_ta
         res = tid::join_tables(ctx, l, lcol, r, rcol, algo);
     });
     if (st == TID_OK) *out = res.release();
+    return st;
+}
+
+tid_status tid_join_outer(tid_ctx *ctx, const tid_table *l, int32_t lcol, const tid_table *r,
+                          int32_t rcol, int32_t kind, int32_t algo, tid_table **out) {
+    std::unique_ptr<tid_table> t;
+    tid_status st = guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(l && r && out, TID_E_INVALID_ARG, "null argument");
+        TID_REQUIRE(algo >= 0 && algo <= 2, TID_E_INVALID_ARG, "join: algo must be 0, 1 or 2");
+        t = tid::join_tables_kind(ctx, l, lcol, r, rcol, kind, algo);
+    });
+    if (st == TID_OK) *out = t.release();
     return st;
 }
 

@@ -639,7 +639,9 @@ int device_cus(tid_ctx *ctx);
 // CU; cached per (kernel, lds) and safe to call from several host threads.
 int resident_blocks(const void *kernel, int block, size_t lds);
 
-constexpr uint32_t kMaxBigTiles = 4;  // tiles per chunk before the single-tile tail
+// tiles per chunk before the single-tile tail
+constexpr uint64_t kMinBigTiles = 4;
+constexpr uint64_t kMaxBigTiles = 32;
 
 template <class Src, int BLOCK, int IPT, int MAXK, int MAXC>
 void launch_chunked(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, int k,
@@ -663,10 +665,15 @@ void launch_chunked(tid_ctx *ctx, const Src &src, CompactArgs<MAXK, MAXC> &a, in
     const uint64_t resident = (uint64_t)blocks_per_cu * (uint64_t)device_cus(ctx);
     const uint64_t tiles = (n + TILE - 1) / TILE;
     const uint64_t tail = std::min<uint64_t>(tiles, 2 * resident);
-    // Big chunks as long as the rows the output bounds allow per chunk fit
-    // 80% of a staging buffer: fewer placements for sparse outputs, no
-    // overflow re-reads for dense ones.
-    uint64_t big = kMaxBigTiles;
+    // Chunk length: about an eighth of a workgroup's share of the tiles, so
+    // that every workgroup still takes several chunks (fast ones more), within
+    // [kMinBigTiles, kMaxBigTiles]: each chunk costs one placement round trip
+    // during which only its successor's first tile is in flight, so long
+    // inputs take long chunks.  Then as long as the rows the output bounds
+    // allow per chunk fit 80% of a staging buffer: fewer placements for sparse
+    // outputs, no overflow re-reads for dense ones.
+    uint64_t big = std::min<uint64_t>(kMaxBigTiles,
+                                      std::max<uint64_t>(kMinBigTiles, tiles / (8 * resident)));
     for (int j = 0; j < k; ++j) {
         const OutDesc<MAXC> &o = a.out[j];
         if (o.ncols == 0 || o.cap == 0) continue;

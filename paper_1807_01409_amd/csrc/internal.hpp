@@ -254,14 +254,22 @@ struct PendingJoin {
     DevBuf slots, slot_of, rank, slot_start, rows;  // slots: slot words, then counts
     const uint32_t *qrow = nullptr, *brow = nullptr;
     int probe_is_left = 1;
+    // left outer join (probe side = L): each probe row with no partner still
+    // gives one output row, R's cells 0; `count` then holds max(matches, 1)
+    // and `matches` the true counts
+    bool outer = false;
+    DevBuf matches;
     uint64_t nq = 0;
     uint64_t total = 0;
     bool total_known = false;
     const uint64_t *d_total() const { return off.get<const uint64_t>() + nq; }
 };
+// join kinds (Sec. 4.2: the join library's Inner, Left, Right and Outer)
+constexpr int kJoinInner = 0, kJoinLeft = 1, kJoinRight = 2, kJoinFull = 3;
+// kind: kJoinInner or kJoinLeft (the probe side is then L)
 std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
                                         const tid_table *R, uint64_t nr, int rc, int algo,
-                                        const JoinPlan &jp);
+                                        const JoinPlan &jp, int kind = kJoinInner);
 std::unique_ptr<tid_table> join_finish(tid_ctx *ctx, PendingJoin &pj);
 
 // Read device words (counts, totals) to the host with one copy and one

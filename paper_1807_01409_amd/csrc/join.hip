@@ -336,6 +336,7 @@ struct ExpandArgs {
     const uint32_t *start;  // per probe position: first matching build position
     const uint32_t *qrow;   // probe position -> probe table row (null: identity)
     const uint32_t *brow;   // build position -> build table row
+    const uint32_t *matches;  // left outer join: true match count per probe position
     uint64_t nq, total;
     int probe_is_left;
     const uint32_t *lcol[TID_MAX_COLS];
@@ -354,14 +355,25 @@ __global__ void join_expand(ExpandArgs a) {
             if (a.off[mid] <= o) lo = mid;
             else hi = mid;
         }
-        const uint64_t j = a.start[lo] + (o - a.off[lo]);
         const uint32_t pr = a.qrow ? a.qrow[lo] : (uint32_t)lo;
+        if (a.matches && a.matches[lo] == 0) {  // a left row with no partner
+            for (int c = 0; c < a.nl; ++c) a.out[c][o] = a.lcol[c][pr];
+            for (int c = 0; c < a.nr; ++c) a.out[a.nl + c][o] = 0u;
+            continue;
+        }
+        const uint64_t j = a.start[lo] + (o - a.off[lo]);
         const uint32_t br = a.brow[j];
         const uint32_t lr = a.probe_is_left ? pr : br;
         const uint32_t rr = a.probe_is_left ? br : pr;
         for (int c = 0; c < a.nl; ++c) a.out[c][o] = a.lcol[c][lr];
         for (int c = 0; c < a.nr; ++c) a.out[a.nl + c][o] = a.rcol[c][rr];
     }
+}
+
+__global__ void at_least_one(const uint32_t *in, uint64_t n, uint32_t *out) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = max(in[i], 1u);
 }
 
 // ---------------------------------------------------------------------------
@@ -386,7 +398,7 @@ std::vector<uint32_t> column_maxima(tid_ctx *ctx, const tid_table *t, uint64_t n
 // Count the matches of L[lc] = R[rc] on the device (no synchronisation).
 std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
                                         const tid_table *R, uint64_t nr, int rc, int algo,
-                                        const JoinPlan &jp) {
+                                        const JoinPlan &jp, int kind) {
     auto pj = std::make_unique<PendingJoin>();
     pj->L = L;
     pj->R = R;
@@ -396,11 +408,14 @@ std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64
     for (int c : jp.lkeep) pj->vars.push_back(L->vars[c]);
     for (int c : jp.rkeep) pj->vars.push_back(R->vars[c]);
     TID_REQUIRE(pj->vars.size() <= TID_MAX_COLS, TID_E_SCHEMA, "join: too many output columns");
-    if (nl == 0 || nr == 0) {
+    TID_REQUIRE(kind == kJoinInner || kind == kJoinLeft, TID_E_INTERNAL, "join: bad kind");
+    // an inner join with an empty side is empty; so is any join of an empty L
+    if (nl == 0 || (nr == 0 && kind == kJoinInner)) {
         pj->total = 0;
         pj->total_known = true;
         return pj;
     }
+    if (nr == 0) algo = 1;  // left join of L with nothing: every L row, padded
     TID_REQUIRE(nl < (1ull << 32) && nr < (1ull << 32), TID_E_UNSUPPORTED,
                 "join: inputs of 2^32 rows or more");
     // automatic choice by size: a hash table over the smaller side while its
@@ -447,8 +462,8 @@ std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64
         pj->brow = rv;
         pj->probe_is_left = 1;
     } else {
-        // build on the smaller side
-        const bool build_right = nr <= nl;
+        // build on the smaller side; a left join probes with L
+        const bool build_right = kind == kJoinLeft || nr <= nl;
         const tid_table *B = build_right ? R : L;
         const tid_table *Q = build_right ? L : R;
         const uint64_t nb = build_right ? nr : nl;
@@ -489,6 +504,15 @@ std::unique_ptr<PendingJoin> join_begin(tid_ctx *ctx, const tid_table *L, uint64
         pj->brow = pj->rows.get<uint32_t>();
         pj->probe_is_left = build_right ? 1 : 0;
     }
+    if (kind == kJoinLeft) {
+        // a probe row with no partner still takes one output row
+        pj->outer = true;
+        pj->matches = std::move(pj->count);
+        pj->count = DevBuf(ctx, pj->nq * 4);
+        hipLaunchKernelGGL(at_least_one, dim3(grid_of(pj->nq)), dim3(256), 0, ctx->stream,
+                           pj->matches.get<const uint32_t>(), pj->nq, pj->count.get<uint32_t>());
+        TID_HIP(hipGetLastError());
+    }
     pj->off = DevBuf(ctx, (pj->nq + 1) * 8);
     exclusive_scan_async(ctx, pj->count.get<const uint32_t>(), pj->nq, pj->off.get<uint64_t>());
     return pj;
@@ -513,6 +537,7 @@ std::unique_ptr<tid_table> join_finish(tid_ctx *ctx, PendingJoin &pj) {
         ea.start = pj.start.get<const uint32_t>();
         ea.qrow = pj.qrow;
         ea.brow = pj.brow;
+        ea.matches = pj.outer ? pj.matches.get<const uint32_t>() : nullptr;
         ea.probe_is_left = pj.probe_is_left;
         ea.nq = pj.nq;
         ea.total = total;
@@ -533,13 +558,142 @@ std::unique_ptr<tid_table> join_finish(tid_ctx *ctx, PendingJoin &pj) {
 // followed by the columns rkeep of R.
 std::unique_ptr<tid_table> join_unsorted(tid_ctx *ctx, const tid_table *L, uint64_t nl, int lc,
                                          const tid_table *R, uint64_t nr, int rc, int algo,
-                                         const JoinPlan &jp) {
-    auto pj = join_begin(ctx, L, nl, lc, R, nr, rc, algo, jp);
+                                         const JoinPlan &jp, int kind = kJoinInner) {
+    auto pj = join_begin(ctx, L, nl, lc, R, nr, rc, algo, jp, kind);
     if (!pj->total_known) {
         read_words(ctx, {pj->d_total()}, &pj->total);
         pj->total_known = true;
     }
     return join_finish(ctx, *pj);
+}
+
+// R rows whose key has no partner in L, as rows of the join's schema (L's
+// columns, then R's without rc): L's cells 0 except lc, which takes the R
+// row's key.  `matches` holds, per R row, its partner count.
+struct UnmatchedSrc {
+    const uint32_t *matches;
+    const uint32_t *rkey;
+    const uint32_t *rcol[TID_MAX_COLS];
+    uint64_t n;
+    int nl, lc;
+    using Item = uint32_t;
+    __device__ __forceinline__ Item load(uint64_t i) const { return matches[i]; }
+    __device__ __forceinline__ bool match(int, Item m) const { return m == 0; }
+    __device__ __forceinline__ uint32_t value(int, int c, Item, uint64_t i) const {
+        return c < nl ? (c == lc ? rkey[i] : 0u) : rcol[c - nl][i];
+    }
+};
+
+static std::unique_ptr<tid_table> unmatched_right(tid_ctx *ctx, const tid_table *l, uint64_t nl,
+                                                  int lc, const tid_table *r, uint64_t nr,
+                                                  int rc, const std::vector<int32_t> &vars) {
+    // partner counts of R's rows: a left join of R against L probes R in
+    // row order (hash join, built on L)
+    JoinPlan none;
+    auto pj = join_begin(ctx, r, nr, rc, l, nl, lc, 1, none, kJoinLeft);
+    auto out = make_table(ctx, (int)vars.size(), vars.data(), nr);
+    if (nr == 0) {
+        set_count(ctx, out.get(), 0);
+        return out;
+    }
+    UnmatchedSrc src{};
+    src.matches = pj->matches.get<const uint32_t>();
+    src.rkey = r->col[rc];
+    int k = 0;
+    for (int c = 0; c < r->ncols; ++c)
+        if (c != rc) src.rcol[k++] = r->col[c];
+    src.n = nr;
+    src.nl = l->ncols;
+    src.lc = lc;
+    CompactArgs<1, TID_MAX_COLS> a{};
+    for (int c = 0; c < out->ncols; ++c) a.out[0].col[c] = out->col[c];
+    a.out[0].cap = out->cap;
+    a.out[0].count = out->d_count;
+    a.out[0].ncols = out->ncols;
+    launch_compact<UnmatchedSrc, 256, 16, 1, TID_MAX_COLS>(ctx, src, a, 1, 16384u);
+    return out;
+}
+
+// Outer joins (Sec. 4.2 kinds): rows in lexicographic order over L's columns
+// then R's without rc; an unbound cell is 0.
+std::unique_ptr<tid_table> join_tables_kind(tid_ctx *ctx, const tid_table *l, int lcol,
+                                            const tid_table *r, int rcol, int kind, int algo) {
+    TID_REQUIRE(lcol >= 0 && lcol < l->ncols && rcol >= 0 && rcol < r->ncols, TID_E_INVALID_ARG,
+                "join: column out of range");
+    TID_REQUIRE(l->ncols + r->ncols - 1 <= TID_MAX_COLS, TID_E_SCHEMA, "join: too many columns");
+    TID_REQUIRE(kind >= kJoinInner && kind <= kJoinFull, TID_E_INVALID_ARG, "join: bad kind");
+    tid_table *both[2] = {const_cast<tid_table *>(l), const_cast<tid_table *>(r)};
+    resolve_counts(ctx, both, 2);
+    JoinPlan jp;
+    for (int c = 0; c < l->ncols; ++c) jp.lkeep.push_back(c);
+    for (int c = 0; c < r->ncols; ++c)
+        if (c != rcol) jp.rkeep.push_back(c);
+    std::vector<int32_t> vars;
+    for (int c : jp.lkeep) vars.push_back(l->vars[c]);
+    for (int c : jp.rkeep) vars.push_back(r->vars[c]);
+    std::unique_ptr<tid_table> raw;
+    if (kind == kJoinRight) {
+        // the left join of R with L, its columns put back in this join's order
+        JoinPlan sw;
+        for (int c = 0; c < r->ncols; ++c) sw.lkeep.push_back(c);
+        for (int c = 0; c < l->ncols; ++c)
+            if (c != lcol) sw.rkeep.push_back(c);
+        auto t = join_unsorted(ctx, r, r->nrows, rcol, l, l->nrows, lcol, algo, sw, kJoinLeft);
+        // position in t of each output column
+        std::vector<int> from;
+        for (int c = 0; c < l->ncols; ++c) {
+            if (c == lcol) {
+                from.push_back(rcol);
+            } else {
+                const int at = (int)(std::find(sw.rkeep.begin(), sw.rkeep.end(), c) -
+                                     sw.rkeep.begin());
+                from.push_back(r->ncols + at);
+            }
+        }
+        for (int c : jp.rkeep) from.push_back(c);
+        raw = std::make_unique<tid_table>();
+        raw->ctx = ctx;
+        raw->ncols = (int)from.size();
+        raw->cap = t->cap;
+        raw->nrows = t->nrows;
+        raw->count_known = t->count_known;
+        raw->d_count = t->d_count;
+        raw->maxv_known = t->maxv_known;
+        for (int c = 0; c < raw->ncols; ++c) {
+            raw->vars[c] = vars[c];
+            raw->col[c] = t->col[from[c]];
+            raw->maxv[c] = t->maxv[from[c]];
+        }
+        raw->block = std::move(t->block);
+    } else {
+        raw = join_unsorted(ctx, l, l->nrows, lcol, r, r->nrows, rcol, algo, jp,
+                            kind == kJoinInner ? kJoinInner : kJoinLeft);
+        if (kind == kJoinFull) {
+            auto un = unmatched_right(ctx, l, l->nrows, lcol, r, r->nrows, rcol, vars);
+            if (raw->maxv_known) copy_bounds(un.get(), raw.get(), nullptr, raw->ncols);
+            un->maxv_known = raw->maxv_known;
+            // rows of both parts, one schema (which may name a variable twice,
+            // so this is a plain concatenation, not a union over variables)
+            tid_table *parts[2] = {raw.get(), un.get()};
+            resolve_counts(ctx, parts, 2);
+            auto both = make_table(ctx, raw->ncols, raw->vars, raw->nrows + un->nrows);
+            both->maxv_known = raw->maxv_known;
+            copy_bounds(both.get(), raw.get(), nullptr, raw->ncols);
+            for (int c = 0; c < raw->ncols; ++c) {
+                if (raw->nrows)
+                    TID_HIP(hipMemcpyAsync(both->col[c], raw->col[c], raw->nrows * 4,
+                                           hipMemcpyDeviceToDevice, ctx->stream));
+                if (un->nrows)
+                    TID_HIP(hipMemcpyAsync(both->col[c] + raw->nrows, un->col[c], un->nrows * 4,
+                                           hipMemcpyDeviceToDevice, ctx->stream));
+            }
+            set_count(ctx, both.get(), raw->nrows + un->nrows);
+            raw = std::move(both);
+        }
+    }
+    tid_table *rp = raw.get();
+    resolve_counts(ctx, &rp, 1);
+    return sort_rows(ctx, raw.get(), raw->nrows, 0);
 }
 
 std::unique_ptr<tid_table> join_tables(tid_ctx *ctx, const tid_table *l, int lcol,

@@ -236,6 +236,11 @@ static void compile_plan(const tid_plan *plan, PlanRun &r) {
             TID_REQUIRE(depth >= 2, TID_E_INVALID_ARG, "plan: JOIN needs two tables");
             --depth;
             pc += 2;
+        } else if (op == TID_OP_OPTIONAL) {
+            need(2);
+            TID_REQUIRE(depth >= 2, TID_E_INVALID_ARG, "plan: OPTIONAL needs two tables");
+            --depth;
+            pc += 2;
         } else if (op == TID_OP_UNION) {
             need(3);
             const uint32_t k = ops[pc + 1];
@@ -272,17 +277,21 @@ static void compile_plan(const tid_plan *plan, PlanRun &r) {
     for (int pc = 0; pc < nops;) {
         const uint32_t op = ops[pc];
         if (op == TID_OP_JOIN) last_join = pc;
-        pc += op == TID_OP_SCAN || op == TID_OP_JOIN ? 2 : op == TID_OP_UNION ? 3
-            : op == TID_OP_FILTER ? 4 : op == TID_OP_PROJECT ? 2 + (int)ops[pc + 1] : 1;
+        pc += op == TID_OP_SCAN || op == TID_OP_JOIN || op == TID_OP_OPTIONAL ? 2
+            : op == TID_OP_UNION ? 3 : op == TID_OP_FILTER ? 4
+            : op == TID_OP_PROJECT ? 2 + (int)ops[pc + 1] : 1;
     }
+    // an OPTIONAL keeps rows without a partner: such a plan is not the natural
+    // join of its scans, and no scan of it is filtered by another
     bool conj = last_join >= 0;
     for (int pc = 0; pc < nops && conj;) {
         const uint32_t op = ops[pc];
-        if (op == TID_OP_UNION) conj = false;
+        if (op == TID_OP_UNION || op == TID_OP_OPTIONAL) conj = false;
         if (pc < last_join && op != TID_OP_SCAN && op != TID_OP_JOIN && op != TID_OP_FILTER)
             conj = false;
-        pc += op == TID_OP_SCAN || op == TID_OP_JOIN ? 2 : op == TID_OP_UNION ? 3
-            : op == TID_OP_FILTER ? 4 : op == TID_OP_PROJECT ? 2 + (int)ops[pc + 1] : 1;
+        pc += op == TID_OP_SCAN || op == TID_OP_JOIN || op == TID_OP_OPTIONAL ? 2
+            : op == TID_OP_UNION ? 3 : op == TID_OP_FILTER ? 4
+            : op == TID_OP_PROJECT ? 2 + (int)ops[pc + 1] : 1;
     }
     r.conjunctive = conj;
 }
@@ -462,6 +471,32 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
                     r.pj_keep.push_back(out_col);
             }
             r.pj = join_begin(ctx, L, L->nrows, lc, R, R->nrows, rc, 0, jp);
+            r.pj->own_r = std::move(r.st.back().t);
+            r.st.pop_back();
+            r.pj->own_l = std::move(r.st.back().t);
+            r.st.pop_back();
+            r.pc += 2;
+        } else if (op == TID_OP_OPTIONAL) {
+            // SPARQL OPTIONAL: the left outer join on one shared variable
+            tid_table *L = r.st[r.st.size() - 2].t.get();
+            tid_table *R = r.st.back().t.get();
+            const bool wl = need_count(L, needs), wr = need_count(R, needs);
+            if (wl || wr) return;
+            const int32_t v = (int32_t)ops[pc + 1];
+            const int lc = col_of(L, v), rc = col_of(R, v);
+            TID_REQUIRE(lc >= 0 && rc >= 0, TID_E_SCHEMA,
+                        "optional: variable not bound on both sides");
+            JoinPlan jp;
+            for (int c = 0; c < L->ncols; ++c) jp.lkeep.push_back(c);
+            for (int c = 0; c < R->ncols; ++c) {
+                if (c == rc) continue;
+                TID_REQUIRE(col_of(L, R->vars[c]) < 0, TID_E_UNSUPPORTED,
+                            "optional: the two sides share a second variable");
+                jp.rkeep.push_back(c);
+            }
+            r.pj_eq.clear();
+            r.pj_keep.clear();
+            r.pj = join_begin(ctx, L, L->nrows, lc, R, R->nrows, rc, 0, jp, kJoinLeft);
             r.pj->own_r = std::move(r.st.back().t);
             r.st.pop_back();
             r.pj->own_l = std::move(r.st.back().t);

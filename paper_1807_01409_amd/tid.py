@@ -149,6 +149,10 @@ class Context:
     def join(self, l: "Table", lcol: int, r: "Table", rcol: int, algo: int = 0) -> "Table":
         return tid_join(self, l, lcol, r, rcol, algo)
 
+    def join_outer(self, l: "Table", lcol: int, r: "Table", rcol: int, kind: str = "left",
+                   algo: int = 0) -> "Table":
+        return tid_join_outer(self, l, lcol, r, rcol, kind, algo)
+
     def union(self, ts: Sequence["Table"], dedupe: bool) -> "Table":
         return tid_union(self, ts, dedupe)
 
@@ -316,6 +320,18 @@ def tid_join(ctx: Context, l: Table, lcol: int, r: Table, rcol: int, algo: int =
     out = ctypes.c_void_p()
     _check(ctx.ptr, ctx._lib.tid_join(ctx.ptr, l._p, int(lcol), r._p, int(rcol), int(algo),
                                       ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+JOIN_KINDS = {"inner": 0, "left": 1, "right": 2, "full": 3}
+
+
+def tid_join_outer(ctx: Context, l: Table, lcol: int, r: Table, rcol: int, kind="left",
+                   algo: int = 0) -> Table:
+    out = ctypes.c_void_p()
+    k = JOIN_KINDS[kind] if isinstance(kind, str) else int(kind)
+    _check(ctx.ptr, ctx._lib.tid_join_outer(ctx.ptr, l._p, int(lcol), r._p, int(rcol), k,
+                                            int(algo), ctypes.byref(out)))
     return Table(ctx, out)
 
 
