@@ -66,6 +66,9 @@ def _setup(lib):
                                       P(_Tab)]
     lib.or_join_outer.argtypes = [P(_Tab), ctypes.c_int32, P(_Tab), ctypes.c_int32,
                                   ctypes.c_int32, P(_Tab)]
+    lib.or_scan_keyed.argtypes = [u32p, ctypes.c_uint64, P(_Pat), ctypes.c_int32, u32p,
+                                  ctypes.c_uint64, P(_Tab)]
+    lib.or_entail.argtypes = [u32p, ctypes.c_uint64, ctypes.c_int32, u32p, P(_Tab)]
     lib.or_union.argtypes = [P(P(_Tab)), ctypes.c_int32, ctypes.c_int32, P(_Tab)]
     lib.or_sort_rows.argtypes = [P(_Tab)]
     lib.or_distinct.argtypes = [P(_Tab)]
@@ -200,6 +203,33 @@ def join(l: Table, lc: int, r: Table, rc: int, method: str = "nested") -> Table:
     return _from_c(res)
 
 
+def scan_keyed(g, p, pos: int, keys) -> Table:
+    """Bindings of the triples matching p whose value at `pos` is in keys."""
+    g = _graph(g)
+    k = np.ascontiguousarray(np.asarray(keys, dtype=np.uint32).ravel())
+    q = _pat(p)
+    res = _Tab()
+    _check(_L().or_scan_keyed(_u32p(g), g.shape[0], ctypes.byref(q), int(pos),
+                              _u32p(k) if k.size else ctypes.POINTER(ctypes.c_uint32)(),
+                              k.size, ctypes.byref(res)), "scan_keyed")
+    return _from_c(res)
+
+
+RDFS_VOCAB = ("type", "subClassOf", "subPropertyOf", "domain", "range")
+
+
+def entail(g, rule: int, vocab) -> Table:
+    """Triples derived by RDFS rule 2, 3, 5, 7, 9 or 11; vocab = IDs of
+    rdf:type, rdfs:subClassOf, rdfs:subPropertyOf, rdfs:domain, rdfs:range."""
+    g = _graph(g)
+    v = np.ascontiguousarray(np.asarray(vocab, dtype=np.uint32))
+    assert v.size == 5
+    res = _Tab()
+    _check(_L().or_entail(_u32p(g), g.shape[0], int(rule), _u32p(v), ctypes.byref(res)),
+           "entail")
+    return _from_c(res)
+
+
 JOIN_KINDS = {"inner": 0, "left": 1, "right": 2, "full": 3}
 
 
@@ -253,4 +283,4 @@ def query(g, plan) -> Table:
 
 __all__ = ["build", "Table", "OracleError", "scan_flags", "scan_multi", "scan",
            "filter", "join", "union", "sort_rows", "distinct", "query", "encode_graph",
-           "decode_row", "join_outer", "JOIN_KINDS"]
+           "decode_row", "join_outer", "JOIN_KINDS", "scan_keyed", "entail", "RDFS_VOCAB"]

@@ -17,6 +17,8 @@
 /* helpers                                                             */
 /* ------------------------------------------------------------------ */
 
+static int32_t col_of(const or_table *t, int32_t var);
+
 static int table_alloc(or_table *t, uint64_t nrows, int32_t ncols)
 {
     t->nrows = nrows;
@@ -170,6 +172,133 @@ int or_scan(const uint32_t *g, uint64_t n, const or_pattern *q, or_table *out)
         ++r;
     }
     return OR_OK;
+}
+
+static int u32_cmp(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : (x > y);
+}
+
+int or_scan_keyed(const uint32_t *g, uint64_t n, const or_pattern *q, int32_t pos,
+                  const uint32_t *keys, uint64_t nkeys, or_table *out)
+{
+    if (!pattern_ok(q) || pos < 0 || pos > 2 || q->c[pos] != 0) return OR_E_INVALID;
+    uint32_t *sorted = (uint32_t *)malloc((nkeys ? nkeys : 1) * sizeof(uint32_t));
+    if (!sorted) return OR_E_OOM;
+    if (nkeys) memcpy(sorted, keys, nkeys * sizeof(uint32_t));
+    qsort(sorted, (size_t)nkeys, sizeof(uint32_t), u32_cmp);
+    int32_t vars[3], src[3];
+    int32_t k = pattern_schema(q, vars, src);
+    uint64_t cnt = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        uint64_t r = 0;
+        for (uint64_t i = 0; i < n; ++i) {
+            const uint32_t *t = g + 3 * i;
+            if (!triple_matches(t, q)) continue;
+            if (!bsearch(&t[pos], sorted, (size_t)nkeys, sizeof(uint32_t), u32_cmp)) continue;
+            if (pass)
+                for (int32_t c = 0; c < k; ++c) out->rows[r * k + c] = t[src[c]];
+            ++r;
+        }
+        if (!pass) {
+            cnt = r;
+            int st = table_alloc(out, cnt, k);
+            if (st) { free(sorted); return st; }
+            for (int32_t c = 0; c < k; ++c) out->vars[c] = vars[c];
+        }
+    }
+    free(sorted);
+    return OR_OK;
+}
+
+/* The rules of the entailment table as two patterns: A, the rule's schema
+   triple, searched first; B, the data triple, searched with the distinct
+   values A bound to the shared variable as keys at position key_pos.  Variable
+   ids: 0..3 name the rule's letters in the order given below; the derived
+   triple takes (subject var or constant, predicate, object var). */
+typedef struct {
+    or_pattern a, b;
+    int32_t shared, key_pos;        /* shared variable; its position in B */
+    int32_t out_s, out_o;           /* variables of the derived subject / object */
+    uint32_t out_p;                 /* constant predicate, or 0: variable out_pv */
+    int32_t out_pv;
+} rule_plan;
+
+static or_pattern mkpat(uint32_t s, uint32_t p, uint32_t o, int32_t vs, int32_t vp, int32_t vo)
+{
+    or_pattern q;
+    memset(&q, 0, sizeof q);
+    q.c[0] = s; q.c[1] = p; q.c[2] = o;
+    q.v[0] = vs; q.v[1] = vp; q.v[2] = vo;
+    q.range_pos = -1;
+    return q;
+}
+
+static int rule_of(int32_t rule, const uint32_t *voc, rule_plan *r)
+{
+    const uint32_t type = voc[0], sc = voc[1], spo = voc[2], dom = voc[3], rng = voc[4];
+    memset(r, 0, sizeof *r);
+    r->out_pv = -1;
+    switch (rule) {
+    case 2:   /* s p o && p domain D  =>  s type D      vars: p 0, D 1, s 2 */
+        r->a = mkpat(0, dom, 0, 0, -1, 1); r->b = mkpat(0, 0, 0, 2, 0, -1);
+        r->shared = 0; r->key_pos = 1; r->out_s = 2; r->out_p = type; r->out_o = 1; break;
+    case 3:   /* s p o && p range R  =>  o type R       vars: p 0, R 1, o 2 */
+        r->a = mkpat(0, rng, 0, 0, -1, 1); r->b = mkpat(0, 0, 0, -1, 0, 2);
+        r->shared = 0; r->key_pos = 1; r->out_s = 2; r->out_p = type; r->out_o = 1; break;
+    case 5:   /* p spo q && q spo r  =>  p spo r        vars: p 0, q 1, r 2 */
+        r->a = mkpat(0, spo, 0, 0, -1, 1); r->b = mkpat(0, spo, 0, 1, -1, 2);
+        r->shared = 1; r->key_pos = 0; r->out_s = 0; r->out_p = spo; r->out_o = 2; break;
+    case 7:   /* s p o && p spo q  =>  s q o            vars: p 0, q 1, s 2, o 3 */
+        r->a = mkpat(0, spo, 0, 0, -1, 1); r->b = mkpat(0, 0, 0, 2, 0, 3);
+        r->shared = 0; r->key_pos = 1; r->out_s = 2; r->out_p = 0; r->out_pv = 1;
+        r->out_o = 3; break;
+    case 9:   /* s type x && x sc y  =>  s type y       vars: x 0, y 1, s 2 */
+        r->a = mkpat(0, sc, 0, 0, -1, 1); r->b = mkpat(0, type, 0, 2, -1, 0);
+        r->shared = 0; r->key_pos = 2; r->out_s = 2; r->out_p = type; r->out_o = 1; break;
+    case 11:  /* x sc y && y sc z  =>  x sc z           vars: x 0, y 1, z 2 */
+        r->a = mkpat(0, sc, 0, 0, -1, 1); r->b = mkpat(0, sc, 0, 1, -1, 2);
+        r->shared = 1; r->key_pos = 0; r->out_s = 0; r->out_p = sc; r->out_o = 2; break;
+    default:
+        return OR_E_INVALID;
+    }
+    return OR_OK;
+}
+
+int or_entail(const uint32_t *g, uint64_t n, int32_t rule, const uint32_t *vocab, or_table *out)
+{
+    rule_plan r;
+    int st = rule_of(rule, vocab, &r);
+    if (st) return st;
+    or_table ta, tb, tj;
+    st = or_scan(g, n, &r.a, &ta);
+    if (st) return st;
+    /* keysArray: the values the first search bound to the shared variable */
+    int32_t ka = col_of(&ta, r.shared);
+    uint32_t *keys = (uint32_t *)malloc((ta.nrows ? ta.nrows : 1) * sizeof(uint32_t));
+    if (!keys) { or_table_free(&ta); return OR_E_OOM; }
+    for (uint64_t i = 0; i < ta.nrows; ++i) keys[i] = ta.rows[i * ta.ncols + ka];
+    st = or_scan_keyed(g, n, &r.b, r.key_pos, keys, ta.nrows, &tb);
+    free(keys);
+    if (st) { or_table_free(&ta); return st; }
+    st = or_join_sortmerge(&ta, ka, &tb, col_of(&tb, r.shared), &tj);
+    or_table_free(&ta);
+    or_table_free(&tb);
+    if (st) return st;
+    st = table_alloc(out, tj.nrows, 3);
+    if (st) { or_table_free(&tj); return st; }
+    out->vars[0] = 0; out->vars[1] = 1; out->vars[2] = 2;
+    int32_t cs = col_of(&tj, r.out_s), co = col_of(&tj, r.out_o);
+    int32_t cp = r.out_p ? -1 : col_of(&tj, r.out_pv);
+    for (uint64_t i = 0; i < tj.nrows; ++i) {
+        const uint32_t *row = tj.rows + i * tj.ncols;
+        out->rows[3 * i] = row[cs];
+        out->rows[3 * i + 1] = r.out_p ? r.out_p : row[cp];
+        out->rows[3 * i + 2] = row[co];
+    }
+    or_table_free(&tj);
+    return or_distinct(out);
 }
 
 /* ------------------------------------------------------------------ */

@@ -70,6 +70,19 @@ int or_scan_multi(const uint32_t *g, uint64_t n, const or_pattern *qs, int32_t k
                   uint64_t *member);
 /* bindings of matching triples, ascending triple position */
 int or_scan(const uint32_t *g, uint64_t n, const or_pattern *q, or_table *out);
+/* multi-key search (Sec. 4.1 keysArray; Sec. 5.7, the second search of an
+   entailment rule): the bindings of the triples matching q whose value at
+   position pos (0 s, 1 p, 2 o; a free position of q) is one of
+   keys[0..nkeys); ascending triple position */
+int or_scan_keyed(const uint32_t *g, uint64_t n, const or_pattern *q, int32_t pos,
+                  const uint32_t *keys, uint64_t nkeys, or_table *out);
+/* RDFS entailment (Sec. 5.7, the table of rules 2, 3, 5, 7, 9, 11): the
+   triples the rule derives, as (s, p, o) rows (vars 0, 1, 2), distinct, in
+   lexicographic order.  vocab = IDs of rdf:type, rdfs:subClassOf,
+   rdfs:subPropertyOf, rdfs:domain, rdfs:range.  Two searches as in the
+   paper: the rule's schema pattern, then the data pattern keyed by the
+   distinct values the first bound to the shared variable; then their join. */
+int or_entail(const uint32_t *g, uint64_t n, int32_t rule, const uint32_t *vocab, or_table *out);
 /* rows with lo <= row[col] < hi, input order */
 int or_filter(const or_table *t, int32_t col, uint32_t lo, uint32_t hi, or_table *out);
 /* L join R on L[lc] = R[rc]; columns L ++ (R without rc); lexicographic order.

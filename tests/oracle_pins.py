@@ -487,3 +487,71 @@ def check_optional_plans(O):
 
 
 ALL_CHECKS += [check_outer_joins, check_optional_plans]
+
+
+# ---------------------------------------------------------------------------
+# multi-key search and RDFS entailment (Sec. 4.1 keysArray; Sec. 5.7)
+# ---------------------------------------------------------------------------
+
+def bf_entail(g, rule, voc):
+    """The rule table by brute force: every pair of triples (t1, t2) meeting
+    the rule's two conditions gives one derived triple (a set)."""
+    T, SC, SPO, DOM, RNG = voc
+    rows = [tuple(int(x) for x in r) for r in g.tolist()]
+    out = set()
+    for a in rows:
+        for b in rows:
+            if rule == 2 and b[1] == DOM and a[1] == b[0]:
+                out.add((a[0], T, b[2]))
+            elif rule == 3 and b[1] == RNG and a[1] == b[0]:
+                out.add((a[2], T, b[2]))
+            elif rule == 5 and a[1] == SPO and b[1] == SPO and a[2] == b[0]:
+                out.add((a[0], SPO, b[2]))
+            elif rule == 7 and b[1] == SPO and a[1] == b[0]:
+                out.add((a[0], b[2], a[2]))
+            elif rule == 9 and a[1] == T and b[1] == SC and a[2] == b[0]:
+                out.add((a[0], T, b[2]))
+            elif rule == 11 and a[1] == SC and b[1] == SC and a[2] == b[0]:
+                out.add((a[0], SC, b[2]))
+    return sorted(out)
+
+
+def check_entailment(O):
+    """Rule 11's worked example (Sec. 5.7): step-1 keys {56, 77, 78}, step-2
+    positionArray {0,0,1,1,0}, derived {(76,78), (76,77)}; every rule against
+    brute force over pairs of triples on small RDFS graphs; the keyed scan
+    against brute-force membership."""
+    gd = _gold("rule11_example.json")
+    g = np.array(gd["data"], dtype=np.uint32)
+    voc = [1, 84, 3, 4, 5]
+    keys = [k[0] for k in gd["step2_keysArray"]]
+    t2 = O.scan_keyed(g, Pattern(0, 84, 0, 0, -1, 1), 0, keys)
+    flags = [int(any((r == list(x)) for x in t2.rows.tolist())) for r in
+             [[int(v[0]), int(v[2])] for v in g.tolist()]]
+    assert flags == gd["step2_positionArray"], flags
+    res = O.entail(g, 11, voc)
+    assert sorted((r[0], r[2]) for r in _rows(res)) == sorted(tuple(x) for x in gd["result_x_z"])
+    assert all(r[1] == 84 for r in _rows(res))
+    from synth.rdfs import VOCAB, RdfsSpec, make_rdfs_graph
+    for seed in (1, 2):
+        g = make_rdfs_graph(RdfsSpec(n_data=120, n_classes=14, n_props=9, n_resources=25,
+                                     seed=seed))
+        for rule in (2, 3, 5, 7, 9, 11):
+            got = O.entail(g, rule, VOCAB)
+            assert got.vars == [0, 1, 2]
+            assert _rows(got) == bf_entail(g, rule, VOCAB), (seed, rule)
+    rng = np.random.default_rng(3)
+    g = tiny_graph(5, 60, 6)
+    for pos in range(3):
+        for keys in ([], [2], [1, 3, 3, 5], list(range(1, 7))):
+            q = _layout_pattern([0, 0, 0], (0, 1, 2))
+            got = O.scan_keyed(g, q, pos, keys)
+            want = [tuple(int(x) for x in r) for r in g.tolist() if r[pos] in keys]
+            assert _rows(got) == want, (pos, keys)
+        q = Pattern(0, 2, 0, 0, -1, 1)
+        got = O.scan_keyed(g, q, 0, [1, 4])
+        assert _rows(got) == [(int(r[0]), int(r[2])) for r in g.tolist()
+                              if r[1] == 2 and r[0] in (1, 4)]
+
+
+ALL_CHECKS += [check_entailment]

@@ -34,6 +34,11 @@ MUTANTS = [
     ("membership_bit_shifted", "m |= (uint64_t)1 << j;", "m |= (uint64_t)1 << (j + 1) % 64;"),
     ("project_ignores_order", "src[j] = col_of(t, (int32_t)vlist[j]);",
      "src[j] = col_of(t, (int32_t)vlist[j]) >= 0 ? j : -1;"),
+    ("keyed_scan_ignores_keys", "if (!bsearch(&t[pos], sorted,", "if (0 && !bsearch(&t[pos], sorted,"),
+    ("rule9_keys_on_subject", "r->shared = 0; r->key_pos = 2; r->out_s = 2; r->out_p = type;",
+     "r->shared = 0; r->key_pos = 0; r->out_s = 2; r->out_p = type;"),
+    ("rule3_derives_subject", "r->a = mkpat(0, rng, 0, 0, -1, 1); r->b = mkpat(0, 0, 0, -1, 0, 2);",
+     "r->a = mkpat(0, rng, 0, 0, -1, 1); r->b = mkpat(0, 0, 0, 2, 0, -1);"),
     ("outer_left_drops_unmatched", "if (!matched && keep_l) {", "if (0) {"),
     ("outer_right_key_not_moved", "dst[c++] = x == lc ? rr[rc] : 0u;", "dst[c++] = 0u;"),
     ("outer_pads_with_left_value", "dst[x] = x < l->ncols ? l->rows[i * l->ncols + x] : 0u;",

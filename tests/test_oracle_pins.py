@@ -120,3 +120,7 @@ def test_outer_joins(oracle_lib):
 
 def test_optional_plans(oracle_lib):
     P.check_optional_plans(oracle_lib)
+
+
+def test_entailment(oracle_lib):
+    P.check_entailment(oracle_lib)
