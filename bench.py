@@ -315,12 +315,16 @@ def batched_part(torch, args, spec, g, plans, infos):
 
     for t in batch():            # warm-up both paths (allocator, code objects)
         t.free()
-    for t in serial()[:64]:
-        t.free()
+    if args.serial_reps:
+        for t in serial()[:64]:
+            t.free()
     ctx.synchronize()
     res = {}
     keep = {}
-    for name, fn, reps in (("batched", batch, args.batch_reps), ("serial", serial, 2)):
+    for name, fn, reps in (("batched", batch, args.batch_reps),
+                           ("serial", serial, args.serial_reps)):
+        if reps == 0:
+            continue
         best = None
         for _ in range(reps):
             ctx.synchronize()
@@ -335,6 +339,11 @@ def batched_part(torch, args, spec, g, plans, infos):
             keep[name] = out
         res[name] = best
         log(f"{name}: {best * 1e3:.1f} ms, {len(plans) / best:.0f} queries/s")
+    if "serial" not in res:      # profiling runs: the batch alone
+        G.free()
+        ctx.close()
+        return {"metric": "batched queries/s", "unit": "queries/s",
+                "value": len(plans) / res["batched"], "ms_per_batch": res["batched"] * 1e3}
     mism = sum(0 if np.array_equal(a.to_numpy(), b.to_numpy()) else 1
                for a, b in zip(keep["batched"], keep["serial"]))
     G.free()
@@ -437,6 +446,7 @@ def main():
     ap.add_argument("--profile-graph", default="large", choices=["large", "medium"])
     ap.add_argument("--queries", type=int, default=1024)
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--serial-reps", type=int, default=2, help="0: time the batch alone")
     ap.add_argument("--qps", type=float, default=2000.0, help="serving: offered load")
     ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")
     ap.add_argument("--warmup-s", type=float, default=1.0, help="serving: arrivals not measured")

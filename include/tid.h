@@ -51,6 +51,7 @@ typedef int32_t tid_status;
 typedef struct tid_ctx tid_ctx;
 typedef struct tid_graph tid_graph;
 typedef struct tid_table tid_table;
+typedef struct tid_dict tid_dict;
 
 /* Device-memory callbacks.  alloc returns a device pointer of at least
    `bytes` usable in stream order on `stream`, or NULL; free releases it.  Pass
@@ -117,7 +118,10 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           predicate's patterns (same tables); 0: every pattern
                           is tested in the graph pass
      "slice_rows"         triples a predicate needs to be sliced (0 = default:
-                          the larger of 65536 and 1/4096 of the graph) */
+                          the larger of 65536 and 1/4096 of the graph)
+     "layout"             1 (default): scans use a graph's predicate-partitioned
+                          layout when it is built (tid_graph_partition) and
+                          pays; 0: scans always read the TripleID array */
 tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value);
 tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value);
 
@@ -142,6 +146,15 @@ tid_status tid_graph_info(const tid_graph *g, uint64_t *n, const uint32_t **devi
    graph holds 2^32 triples or more). */
 tid_status tid_graph_count(const tid_graph *g, int32_t pos, uint32_t lo, uint32_t hi,
                            uint64_t *count);
+/* Layout variant (the paper's ID assignment for pruning a search, Sec. 4.3):
+   enable = 1 builds, beside the TripleID array, the triples stably sorted by
+   predicate as two device columns (subject, object), 8 B per triple more;
+   enable = 0 drops it.  While it exists (and the context option "layout" is
+   1), scans whose patterns all have a constant predicate and whose slices
+   add up to less than one read of the array read only those predicates'
+   slices; results are identical (ascending triple position).  Needs the
+   predicate histogram (TID_E_UNSUPPORTED otherwise).  Synchronises. */
+tid_status tid_graph_partition(tid_ctx *ctx, tid_graph *g, int32_t enable);
 void tid_graph_free(tid_graph *g);
 
 /* ---- triple pattern (Sec. 3: key with 0 as "?") ----------------------- */
@@ -212,6 +225,24 @@ tid_status tid_scan_noalloc(tid_ctx *ctx, const tid_graph *g, const tid_pattern 
    tid_scan would return for patterns[j]. */
 tid_status tid_scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *patterns,
                           int32_t k, tid_table **outs);
+/* Sec. 4.1 (keysArray) and Sec. 5.7 (the second search of an entailment
+   rule): tid_scan of `pattern`, keeping only triples whose value at position
+   key_pos (0 s, 1 p, 2 o; a free position of the pattern) is one of the
+   values in column key_col of `keys` (repeats allowed; the multi-key search
+   of the paper's keysArray built from an earlier result).  Exact: no false
+   positives.  Rows in ascending triple position. */
+tid_status tid_scan_keyed(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pattern,
+                          int32_t key_pos, const tid_table *keys, int32_t key_col,
+                          tid_table **out);
+/* Sec. 5.7 (RDFS entailment, the rule table): the triples rule 2, 3, 5, 7, 9
+   or 11 derives from the graph, as distinct (s, p, o) rows (variable ids 0, 1,
+   2) in lexicographic order.  vocab[0..5) are the IDs of rdf:type,
+   rdfs:subClassOf, rdfs:subPropertyOf, rdfs:domain and rdfs:range.  Two
+   searches as in the paper: the rule's schema pattern, then the data pattern
+   keyed by the values the first bound to the shared variable; then their
+   join.  Synchronises. */
+tid_status tid_entail(tid_ctx *ctx, const tid_graph *g, int32_t rule, const uint32_t *vocab,
+                      tid_table **out);
 /* Sec. 4.3 (FILTER, here on an ID range): the rows with lo <= row[col] < hi,
    in input order.  lo >= hi gives an empty table. */
 tid_status tid_filter(tid_ctx *ctx, const tid_table *t, int32_t col, uint32_t lo, uint32_t hi,
@@ -297,6 +328,32 @@ tid_status tid_query_batch(tid_ctx *ctx, const tid_graph *g, const tid_plan *con
    work; used to admit queries against a memory budget. */
 tid_status tid_plan_estimate(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan,
                              uint64_t *bytes);
+
+/* ---- dictionary (Sec. 3: conversion of RDF terms into TripleID rows) ---- */
+
+/* Encode n triples of terms into TripleID rows on the GPU.  Term t (t < 3n) is
+   bytes[offsets[t] .. offsets[t+1]); term 3i + x is position x (s, p, o) of
+   triple i.  bytes, offsets (3n + 1 uint64, non-decreasing, within nbytes)
+   are host (on_device = 0) or device (1) buffers.  One dictionary for all
+   positions; IDs are handed out from 1 in order of first appearance, reading
+   the terms s, p, o of triple 0, then triple 1, and so on.  rows_out (device,
+   3n uint32) receives the rows (row-major, the tid_load layout); *dict the
+   dictionary (device resident).  TID_E_UNSUPPORTED if two different terms
+   share a 64-bit hash (checked, never merged).  Synchronises. */
+tid_status tid_encode(tid_ctx *ctx, const uint8_t *bytes, uint64_t nbytes,
+                      const uint64_t *offsets, uint64_t n, int on_device, uint32_t *rows_out,
+                      tid_dict **dict);
+/* Number of distinct terms (= the largest ID) and their total bytes. */
+tid_status tid_dict_info(const tid_dict *dict, uint64_t *n_terms, uint64_t *n_bytes);
+/* Decode n IDs (host or device buffer) to their terms, into host buffers:
+   offsets_out (n + 1 uint64) always receives the offsets of the terms in the
+   output; bytes_out receives the bytes if they fit cap_bytes, otherwise the
+   call returns TID_E_CAPACITY with the needed size in offsets_out[n].  An ID
+   of 0 or above the dictionary's size is TID_E_INVALID_ARG.  Synchronises. */
+tid_status tid_decode(tid_ctx *ctx, const tid_dict *dict, const uint32_t *ids, uint64_t n,
+                      int on_device, uint64_t *offsets_out, uint8_t *bytes_out,
+                      uint64_t cap_bytes);
+void tid_dict_free(tid_dict *dict);
 
 /* ---- measurement ------------------------------------------------------ */
 

@@ -56,6 +56,15 @@ SIGNATURES = {
     "tid_graph_count": (_S, [_VP, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint32, _U64P]),
     "tid_graph_free": (None, [_VP]),
     "tid_read_probe": (_S, [_VP, _VP, ctypes.c_uint64, ctypes.c_int32]),
+    "tid_scan_keyed": (_S, [_VP, _VP, _VP, ctypes.c_int32, _VP, ctypes.c_int32, _PP]),
+    "tid_entail": (_S, [_VP, _VP, ctypes.c_int32, _VP, _PP]),
+    "tid_graph_partition": (_S, [_VP, _VP, ctypes.c_int32]),
+    "tid_encode": (_S, [_VP, _VP, ctypes.c_uint64, _VP, ctypes.c_uint64, ctypes.c_int, _VP,
+                        _PP]),
+    "tid_dict_info": (_S, [_VP, _U64P, _U64P]),
+    "tid_decode": (_S, [_VP, _VP, _VP, ctypes.c_uint64, ctypes.c_int, _VP, _VP,
+                        ctypes.c_uint64]),
+    "tid_dict_free": (None, [_VP]),
     "tid_scan_noalloc": (_S, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_uint64, _VP]),
     "tid_table_info": (_S, [_VP, _VP, _U64P, _I32P, _I32P]),
     "tid_table_column": (_S, [_VP, ctypes.c_int32, _PP]),

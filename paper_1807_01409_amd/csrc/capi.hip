@@ -40,6 +40,14 @@ namespace tid {
 std::unique_ptr<tid_table> join_tables(tid_ctx *, const tid_table *, int, const tid_table *, int,
                                        int);
 std::unique_ptr<tid_table> union_tables(tid_ctx *, const tid_table *const *, int, int);
+std::unique_ptr<tid_table> scan_keyed(tid_ctx *, const tid_graph *, const tid_pattern &, int,
+                                      const uint32_t *, uint64_t);
+std::unique_ptr<tid_table> entail(tid_ctx *, const tid_graph *, int, const uint32_t *);
+void partition_graph(tid_ctx *, tid_graph *, bool);
+std::unique_ptr<tid_dict> encode(tid_ctx *, const uint8_t *, uint64_t, const uint64_t *, uint64_t,
+                                 int, uint32_t *);
+void decode(tid_ctx *, const tid_dict *, const uint32_t *, uint64_t, int, uint64_t *, uint8_t *,
+            uint64_t);
 std::unique_ptr<tid_table> join_tables_kind(tid_ctx *, const tid_table *, int, const tid_table *,
                                             int, int, int);
 std::unique_ptr<tid_table> sort_table(tid_ctx *, const tid_table *, int);
@@ -149,6 +157,9 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
         } else if (k == "slice_rows") {
             TID_REQUIRE(value >= 0, TID_E_INVALID_ARG, "slice_rows must be >= 0");
             ctx->opt.slice_rows = value;
+        } else if (k == "layout") {
+            TID_REQUIRE(value == 0 || value == 1, TID_E_INVALID_ARG, "layout must be 0 or 1");
+            ctx->opt.layout = value;
         } else if (k == "chunk_epoch") {
             TID_REQUIRE(value >= 0 && value <= (int64_t)tid::kEpochMax, TID_E_INVALID_ARG,
                         "chunk_epoch is 0..2^23-1");
@@ -192,6 +203,7 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "semijoin_min") *value = ctx->opt.semijoin_min;
         else if (k == "wide_slice") *value = ctx->opt.wide_slice;
         else if (k == "slice_rows") *value = ctx->opt.slice_rows;
+        else if (k == "layout") *value = ctx->opt.layout;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });
 }
@@ -252,6 +264,50 @@ tid_status tid_graph_count(const tid_graph *g, int32_t pos, uint32_t lo, uint32_
     if (g->n && g->cdf[pos].empty()) return TID_E_UNSUPPORTED;
     *count = g->n ? g->count_in(pos, lo, hi) : 0;
     return TID_OK;
+}
+
+tid_status tid_graph_partition(tid_ctx *ctx, tid_graph *g, int32_t enable) {
+    return guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(g, TID_E_INVALID_ARG, "null graph");
+        tid::partition_graph(ctx, g, enable != 0);
+    });
+}
+
+tid_status tid_encode(tid_ctx *ctx, const uint8_t *bytes, uint64_t nbytes,
+                      const uint64_t *offsets, uint64_t n, int on_device, uint32_t *rows_out,
+                      tid_dict **dict) {
+    std::unique_ptr<tid_dict> d;
+    tid_status st = guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(dict, TID_E_INVALID_ARG, "null output");
+        d = tid::encode(ctx, bytes, nbytes, offsets, n, on_device, rows_out);
+    });
+    if (st == TID_OK) *dict = d.release();
+    return st;
+}
+
+tid_status tid_dict_info(const tid_dict *dict, uint64_t *n_terms, uint64_t *n_bytes) {
+    if (!dict) return TID_E_INVALID_ARG;
+    if (n_terms) *n_terms = dict->n_terms;
+    if (n_bytes) *n_bytes = dict->n_bytes;
+    return TID_OK;
+}
+
+tid_status tid_decode(tid_ctx *ctx, const tid_dict *dict, const uint32_t *ids, uint64_t n,
+                      int on_device, uint64_t *offsets_out, uint8_t *bytes_out,
+                      uint64_t cap_bytes) {
+    return guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(dict, TID_E_INVALID_ARG, "null dictionary");
+        tid::decode(ctx, dict, ids, n, on_device, offsets_out, bytes_out, cap_bytes);
+    });
+}
+
+void tid_dict_free(tid_dict *dict) {
+    if (!dict) return;
+    (void)hipSetDevice(dict->ctx->device);
+    delete dict;
 }
 
 tid_status tid_read_probe(tid_ctx *ctx, const void *device_ptr, uint64_t bytes, int32_t mode) {
@@ -346,6 +402,34 @@ tid_status tid_scan_noalloc(tid_ctx *ctx, const tid_graph *g, const tid_pattern 
         TID_REQUIRE(g && pattern, TID_E_INVALID_ARG, "null argument");
         tid::scan_noalloc(ctx, g, *pattern, out_cols, ncols, cap_rows, d_count);
     });
+}
+
+tid_status tid_scan_keyed(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pattern,
+                          int32_t key_pos, const tid_table *keys, int32_t key_col,
+                          tid_table **out) {
+    std::unique_ptr<tid_table> t;
+    tid_status st = guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(g && pattern && keys && out, TID_E_INVALID_ARG, "null argument");
+        TID_REQUIRE(key_col >= 0 && key_col < keys->ncols, TID_E_INVALID_ARG,
+                    "keyed scan: key column out of range");
+        const uint64_t nk = const_cast<tid_table *>(keys)->rows();
+        t = tid::scan_keyed(ctx, g, *pattern, key_pos, keys->col[key_col], nk);
+    });
+    if (st == TID_OK) *out = t.release();
+    return st;
+}
+
+tid_status tid_entail(tid_ctx *ctx, const tid_graph *g, int32_t rule, const uint32_t *vocab,
+                      tid_table **out) {
+    std::unique_ptr<tid_table> t;
+    tid_status st = guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(g && vocab && out, TID_E_INVALID_ARG, "null argument");
+        t = tid::entail(ctx, g, rule, vocab);
+    });
+    if (st == TID_OK) *out = t.release();
+    return st;
 }
 
 tid_status tid_scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *patterns,

@@ -67,6 +67,7 @@ struct Options {
     int64_t semijoin_min = 1 << 16;  // rows a scan's bound needs before it is filtered
     int64_t wide_slice = 1;      // wide passes slice predicates shared by patterns
     int64_t slice_rows = 0;      // rows a predicate needs to be sliced (0 = default)
+    int64_t layout = 1;          // 1: scans use a graph's partitioned layout if built; 0: never
 };
 
 }  // namespace tid
@@ -160,8 +161,24 @@ struct tid_graph {
     tid::DevBuf data;                 // n*12 bytes (+ padding), AoS s,p,o
     std::vector<uint64_t> cdf[3];     // empty if the position's max ID is too large
     uint32_t max_id[3] = {0, 0, 0};
+    // Optional layout variant: the triples stably sorted by predicate, as two
+    // columns (subject, object); predicate p's triples are rows
+    // [cdf[1][p], cdf[1][p + 1]) in ascending triple position.  Scans with a
+    // constant predicate then read only that slice (8 B per triple of p).
+    tid::DevBuf part_s, part_o;
+    bool partitioned = false;
     // number of triples with lo <= position value < hi (n if no histogram)
     uint64_t count_in(int pos, uint64_t lo, uint64_t hi) const;
+};
+
+// A term dictionary on the device: term ID k (1-based) is bytes
+// [offsets[k-1], offsets[k]).
+struct tid_dict {
+    tid_ctx *ctx = nullptr;
+    uint64_t n_terms = 0;        // distinct terms = the largest ID
+    uint64_t n_bytes = 0;
+    tid::DevBuf offsets;         // n_terms + 1 uint64
+    tid::DevBuf bytes;
 };
 
 struct tid_table {
@@ -216,10 +233,15 @@ struct PatternSet {
 // binds to the variable at that position.  A row whose value is not in it
 // cannot take part in the plan's join; a false positive only keeps a row that
 // the join then drops.
+//
+// With exact = 1 the filter is instead a bitmap over IDs 0..mask (one bit per
+// ID, set for the members): a multi-key search (Sec. 4.1 keysArray; Sec. 5.7,
+// the second search of an entailment rule) with no false positives.
 struct ScanFilter {
     const uint32_t *bits = nullptr;
     uint32_t mask = 0;
     int32_t pos = -1;  // -1: none
+    int32_t exact = 0;
 };
 
 // Scan: fill `outs[j]` for k patterns in one pass.  Tables are allocated here.

@@ -281,6 +281,7 @@ DevPattern compile_pattern(const tid_pattern &p, const PatternSet *set,
         d.fbits = filter->bits;
         d.fmask = filter->mask;
         d.fpos = filter->pos;
+        d.fexact = filter->exact;
     }
     int32_t vars[3], src[3];
     d.ncols = pattern_schema(p, vars, src);
@@ -376,9 +377,31 @@ static void launch_multi(tid_ctx *ctx, const tid_graph *g, MultiArgs &a, int k, 
 // between block-ranged and chunked placement, and measure 2.5x faster for
 // eight patterns of ~1% selectivity.  multi_shape 0 is 512 threads x 8
 // triples for both.
+void scan_slice(tid_ctx *ctx, const tid_graph *g, const tid_pattern &p, tid_table *out,
+                const ScanFilter *filter);
+
+// With the predicate-partitioned layout built, patterns that all have a
+// constant predicate (and no value set) read only their predicates' slices,
+// one pass per pattern, when those slices (8 B per triple) add up to less
+// than one read of the TripleID array (12 B per triple).
+static bool use_slices(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+                       const PatternSet *sets) {
+    if (!g->partitioned || ctx->opt.layout == 0) return false;
+    uint64_t rows = 0;
+    for (int j = 0; j < k; ++j) {
+        if (pats[j].p == 0 || (sets && sets[j].pos >= 0)) return false;
+        rows += g->count_in(1, pats[j].p, (uint64_t)pats[j].p + 1);
+    }
+    return 8 * rows < 12 * g->n;
+}
+
 static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                          tid_table *const *outs, const PatternSet *sets,
                          const ScanFilter *filters) {
+    if (use_slices(ctx, g, pats, k, sets)) {
+        for (int j = 0; j < k; ++j) scan_slice(ctx, g, pats[j], outs[j], filters ? &filters[j] : nullptr);
+        return;
+    }
     if (k == 1) {
         run_scan1(ctx, g, pats, k, outs, sets, filters);
         return;

@@ -39,8 +39,9 @@ struct DevPattern {
     int32_t nset;
     uint32_t set[kMaxSet];
     const uint32_t *fbits;  // membership filter on position fpos (-1: none)
-    uint32_t fmask;
+    uint32_t fmask;         // Bloom: bits - 1; exact: largest ID in the bitmap
     int32_t fpos;
+    int32_t fexact;         // 1: fbits is an exact bitmap over IDs 0..fmask
 };
 
 // EXT false: no pattern of the pass has a value set or a membership filter,
@@ -83,7 +84,11 @@ __device__ __forceinline__ bool match_pattern(const DevPattern &q, const Tri &t)
         for (int i = 0; i < kMaxSet; ++i) in |= i < q.nset && x == q.set[i];
         ok &= in;
     }
-    if (ok && q.fpos >= 0) ok = dev::bloom_has(q.fbits, q.fmask, pick(t, q.fpos));
+    if (ok && q.fpos >= 0) {
+        const uint32_t x = pick(t, q.fpos);
+        ok = q.fexact ? x <= q.fmask && ((q.fbits[x >> 5] >> (x & 31u)) & 1u) != 0
+                      : dev::bloom_has(q.fbits, q.fmask, x);
+    }
     return ok;
 }
 

@@ -345,6 +345,7 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
         wp[j] = compile_wide(pats[j]);
         if (filters && filters[j].pos >= 0) {
             wp[j].flags |= kWideFiltered | ((uint32_t)filters[j].pos << 15);
+            TID_REQUIRE(!filters[j].exact, TID_E_INTERNAL, "wide pass: exact filters go to scans");
             wp[j].fbits = filters[j].bits;
             wp[j].fmask = filters[j].mask;
         }

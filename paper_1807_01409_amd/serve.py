@@ -20,7 +20,7 @@ from typing import Callable, List, Optional, Sequence
 
 import numpy as np
 
-from .tid import Context, Graph
+from .tid import Context, Graph, TidError
 
 
 @dataclass
@@ -33,6 +33,7 @@ class Request:
     done: float = -1.0
     rows: int = -1
     result: Optional[np.ndarray] = None
+    error: str = ""             # set when the request failed (it is not retried again)
 
 
 @dataclass
@@ -46,6 +47,7 @@ class ServeStats:
     max_inflight_bytes: int
     max_queue: int
     latencies_ms: List[float] = field(default_factory=list)
+    failed: int = 0             # requests that failed alone after their group failed
 
 
 class Server:
@@ -84,6 +86,23 @@ class Server:
                         r.rows = t.nrows
                     t.free()
                 err = None
+            except TidError as e:
+                # A group that ran out of device memory (or hit another library
+                # error) is retried one request at a time, so that one large
+                # request fails alone and the others are still served.
+                err = None
+                for r in batch:
+                    try:
+                        t = ctx.query(self.graph, r.plan)
+                        if self._keep is True or (self._keep and r.rid in self._keep):
+                            r.result = t.to_numpy()
+                            r.rows = r.result.shape[0]
+                        else:
+                            r.rows = t.nrows
+                        t.free()
+                    except TidError as e1:
+                        r.error = str(e1)
+                        r.rows = -1
             except Exception as e:  # noqa: BLE001 - reported to the dispatcher
                 err = e
             now = time.perf_counter() - self._t0
@@ -170,5 +189,5 @@ class Server:
                           p99_ms=float(np.percentile(lat, 99)),
                           mean_batch=float(np.mean(batches)) if batches else 0.0,
                           max_inflight_bytes=int(max_inflight), max_queue=int(max_queue),
-                          latencies_ms=lat.tolist())
+                          latencies_ms=lat.tolist(), failed=sum(1 for r in reqs if r.error))
 

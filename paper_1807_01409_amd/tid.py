@@ -168,6 +168,15 @@ class Context:
     def plan_estimate(self, g: "Graph", plan) -> int:
         return tid_plan_estimate(self, g, plan)
 
+    def scan_keyed(self, g: "Graph", pattern, pos: int, keys: "Table", col: int = 0) -> "Table":
+        return tid_scan_keyed(self, g, pattern, pos, keys, col)
+
+    def entail(self, g: "Graph", rule: int, vocab) -> "Table":
+        return tid_entail(self, g, rule, vocab)
+
+    def encode(self, triples):
+        return tid_encode(self, triples)
+
     def read_probe(self, device_ptr: int, nbytes: int, mode: int = 0):
         tid_read_probe(self, device_ptr, nbytes, mode)
 
@@ -184,6 +193,10 @@ class Graph:
         _check(ctx.ptr, ctx._lib.tid_graph_info(ptr, ctypes.byref(n), ctypes.byref(d)))
         self.n = int(n.value)
         self.device_ptr = int(d.value or 0)
+
+    def partition(self, enable: bool = True):
+        _check(self.ctx.ptr, self.ctx._lib.tid_graph_partition(self.ctx.ptr, self._p,
+                                                               int(bool(enable))))
 
     def count(self, pos: int, lo: int, hi: int) -> int:
         return tid_graph_count(self, pos, lo, hi)
@@ -307,6 +320,91 @@ def tid_scan_multi(ctx: Context, g: Graph, patterns) -> List[Table]:
     outs = (ctypes.c_void_p * k)()
     _check(ctx.ptr, ctx._lib.tid_scan_multi(ctx.ptr, g._p, arr, k, outs))
     return [Table(ctx, ctypes.c_void_p(outs[j])) for j in range(k)]
+
+
+def tid_scan_keyed(ctx: Context, g: Graph, pattern, pos: int, keys: Table, col: int = 0) -> Table:
+    out = ctypes.c_void_p()
+    q = _pattern(pattern)
+    _check(ctx.ptr, ctx._lib.tid_scan_keyed(ctx.ptr, g._p, ctypes.byref(q), int(pos), keys._p,
+                                            int(col), ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+def tid_entail(ctx: Context, g: Graph, rule: int, vocab) -> Table:
+    v = (ctypes.c_uint32 * 5)(*[int(x) for x in vocab])
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_entail(ctx.ptr, g._p, int(rule), v, ctypes.byref(out)))
+    return Table(ctx, out)
+
+
+class Dict:
+    """A term dictionary on the device (tid_encode's output)."""
+
+    def __init__(self, ctx: Context, ptr):
+        self.ctx = ctx
+        self._p = ptr
+
+    def info(self):
+        n, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(self.ctx.ptr, self.ctx._lib.tid_dict_info(self._p, ctypes.byref(n), ctypes.byref(b)))
+        return int(n.value), int(b.value)
+
+    def decode(self, ids) -> List[str]:
+        return tid_decode(self.ctx, self, ids)
+
+    def free(self):
+        if self._p:
+            self.ctx._lib.tid_dict_free(self._p)
+            self._p = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            if self._p and self.ctx._p:
+                self.free()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+def tid_encode(ctx: Context, triples):
+    """Encode string triples on the GPU; returns ((n, 3) uint32 rows, Dict).
+    Marshalling only: the terms are UTF-8 encoded and laid out as bytes and
+    3n + 1 offsets."""
+    torch = ctx._torch
+    terms = [str(x).encode("utf-8") for t in triples for x in t]
+    if len(terms) % 3:
+        raise ValueError("triples must have three terms each")
+    n = len(terms) // 3
+    blob = b"".join(terms)
+    off = np.zeros(len(terms) + 1, dtype=np.uint64)
+    if terms:
+        off[1:] = np.cumsum([len(x) for x in terms], dtype=np.uint64)
+    buf = np.frombuffer(blob, dtype=np.uint8) if blob else np.zeros(1, np.uint8)
+    rows = torch.empty(max(1, 3 * n), dtype=torch.int32, device=f"cuda:{ctx.device}")
+    out = ctypes.c_void_p()
+    _check(ctx.ptr, ctx._lib.tid_encode(ctx.ptr, buf.ctypes.data_as(ctypes.c_void_p), len(blob),
+                                        off.ctypes.data_as(ctypes.c_void_p), n, 0,
+                                        ctypes.c_void_p(rows.data_ptr()), ctypes.byref(out)))
+    ctx.synchronize()
+    r = rows[:3 * n].cpu().numpy().view(np.uint32).reshape(n, 3)
+    return r, Dict(ctx, out)
+
+
+def tid_decode(ctx: Context, d: Dict, ids) -> List[str]:
+    a = np.ascontiguousarray(np.asarray(ids, dtype=np.uint32).ravel())
+    n = a.size
+    off = np.zeros(n + 1, dtype=np.uint64)
+    st = ctx._lib.tid_decode(ctx.ptr, d._p, a.ctypes.data_as(ctypes.c_void_p), n, 0,
+                             off.ctypes.data_as(ctypes.c_void_p), None, 0)
+    total = int(off[n]) if st in (0, -3) else 0
+    if st not in (0, -3):
+        _check(ctx.ptr, st)
+    buf = np.zeros(max(1, total), dtype=np.uint8)
+    if total:
+        _check(ctx.ptr, ctx._lib.tid_decode(ctx.ptr, d._p, a.ctypes.data_as(ctypes.c_void_p), n,
+                                            0, off.ctypes.data_as(ctypes.c_void_p),
+                                            buf.ctypes.data_as(ctypes.c_void_p), total))
+    raw = buf.tobytes()
+    return [raw[int(off[i]):int(off[i + 1])].decode("utf-8") for i in range(n)]
 
 
 def tid_filter(ctx: Context, t: Table, col: int, lo: int, hi: int) -> Table:

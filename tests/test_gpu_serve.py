@@ -57,3 +57,27 @@ def test_served_mix_equals_alone_and_oracle(ctx, mix, mix_oracle, budget):
         assert np.array_equal(r.result, alone[key]), r.rid
         assert np.array_equal(r.result, mix_oracle[key]), r.rid
     assert stats.p99_ms >= stats.p50_ms > 0
+
+
+def test_served_group_failure_is_contained(ctx, mix):
+    """A group whose batch call fails (forced here from the host: every scan
+    output capped at one row with retries off, so scans with more rows fail
+    with TID_E_CAPACITY) is retried request by request; requests that still
+    fail are reported, the others served, and the server does not abort."""
+    from paper_1807_01409_amd.serve import Request, Server
+    g, plans, infos = mix
+    reqs = [Request(i, plans[i % len(plans)], 0.0) for i in range(40)]
+    srv = Server(g, workers=2, budget_bytes=64 << 30, max_batch=16)
+    try:
+        for c in srv.ctxs:
+            c.set_option("capacity_override", 1)
+            c.set_option("retry", 0)
+        stats = srv.run(reqs, keep_results=True)
+    finally:
+        srv.close()
+    failed = [r for r in reqs if r.error]
+    assert stats.failed == len(failed) > 0
+    assert all("CAPACITY" in r.error for r in failed)
+    for r in reqs:
+        if not r.error:
+            assert r.result.shape[0] <= 1
