@@ -68,6 +68,7 @@ struct Options {
     int64_t wide_slice = 1;      // wide passes slice predicates shared by patterns
     int64_t slice_rows = 0;      // rows a predicate needs to be sliced (0 = default)
     int64_t layout = 1;          // 1: scans use a graph's partitioned layout if built; 0: never
+    int64_t batch_small = 1;     // 1: small joins and final sorts of plans batched per round
 };
 
 }  // namespace tid
@@ -284,7 +285,15 @@ struct PendingJoin {
     uint64_t nq = 0;
     uint64_t total = 0;
     bool total_known = false;
-    const uint64_t *d_total() const { return off.get<const uint64_t>() + nq; }
+    // a small join of a batch (batch.hip): counted and expanded as one job
+    // of a round's launch; sj_off holds its L rows' output offsets, sj_total
+    // its size, small_result its rows once expanded
+    bool small = false;
+    DevBuf sj_off, sj_total;
+    std::unique_ptr<tid_table> small_result;
+    const uint64_t *d_total() const {
+        return small ? sj_total.get<const uint64_t>() : off.get<const uint64_t>() + nq;
+    }
 };
 // join kinds (Sec. 4.2: the join library's Inner, Left, Right and Outer)
 constexpr int kJoinInner = 0, kJoinLeft = 1, kJoinRight = 2, kJoinFull = 3;

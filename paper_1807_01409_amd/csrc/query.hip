@@ -5,6 +5,7 @@
 // results, followed by unions, projections and DISTINCT; every result is
 // returned in lexicographic row order.  A batch of plans advances in
 // lockstep, so the host waits for the device once per round for all plans.
+#include "batch.hpp"
 #include "compact.hpp"
 
 #include <map>
@@ -125,6 +126,7 @@ struct PlanRun {
     int pc = 0;
     std::vector<Entry> st;
     std::unique_ptr<PendingJoin> pj;
+    JoinJob sj{};                  // the job of pj when it is a small join
     std::vector<std::pair<int, int>> pj_eq;
     std::vector<int> pj_keep;
     std::unique_ptr<tid_table> result;
@@ -411,7 +413,7 @@ static bool need_count(tid_table *t, Needs &needs) {
 }
 
 // Run the plan's ops until one needs a value that is still on the device.
-static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
+static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
     const uint32_t *ops = r.plan->ops;
     const int nops = r.plan->n_ops;
     while (!r.done) {
@@ -419,6 +421,13 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
             if (!r.pj->total_known) {
                 needs.joins.push_back(r.pj.get());
                 return;
+            }
+            if (r.pj->small) {  // expanded by the round's batched launch
+                TID_REQUIRE(r.pj->small_result, TID_E_INTERNAL, "batched join not expanded");
+                auto t = std::move(r.pj->small_result);
+                r.pj.reset();
+                r.st.push_back({std::move(t), false});
+                continue;
             }
             auto raw = join_finish(ctx, *r.pj);
             r.pj.reset();  // inputs go back to the allocator in stream order
@@ -436,6 +445,30 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
                 return;
             }
             if (need_count(top.t.get(), needs)) return;
+            const tid_table *T = top.t.get();
+            if (bs && ctx->opt.batch_small && T->ncols > 0 && T->ncols <= kSortCols &&
+                T->nrows > 1 && T->nrows <= kSortRows &&
+                T->nrows * (uint64_t)T->ncols <= kSortWords) {
+                // one job of the round's batched sort; the input stays alive
+                // in the batch state until the round's wait
+                auto out = make_table(ctx, T->ncols, T->vars, T->nrows);
+                out->maxv_known = T->maxv_known;
+                copy_bounds(out.get(), T, nullptr, T->ncols);
+                SortJob j{};
+                for (int c = 0; c < T->ncols; ++c) {
+                    j.in[c] = T->col[c];
+                    j.out[c] = out->col[c];
+                }
+                j.n = (uint32_t)T->nrows;
+                j.ncols = T->ncols;
+                j.distinct = 0;
+                j.count = out->d_count;
+                bs->sort_jobs.push_back(j);
+                bs->keep_tables.push_back(std::move(top.t));
+                r.result = std::move(out);
+                r.done = true;
+                return;
+            }
             r.result = sort_rows(ctx, top.t.get(), top.t->nrows, 0);
             r.done = true;
             return;
@@ -469,6 +502,49 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs) {
                     r.pj_eq.emplace_back(lmatch, out_col);
                 else
                     r.pj_keep.push_back(out_col);
+            }
+            const int nkeep = (int)r.pj_keep.size() - L->ncols;
+            if (bs && ctx->opt.batch_small && L->nrows > 0 && R->nrows > 0 &&
+                L->nrows <= kSmallRows && R->nrows <= kSmallRows && L->ncols <= kSmallCols &&
+                nkeep <= kSmallCols && (int)r.pj_eq.size() <= kSmallEq) {
+                // a job of this round's batched count; expanded next round
+                auto pj = std::make_unique<PendingJoin>();
+                pj->small = true;
+                pj->L = L;
+                pj->R = R;
+                pj->sj_off = DevBuf(ctx, (L->nrows + 1) * 4);
+                pj->sj_total = DevBuf(ctx, 8);
+                JoinJob &j = r.sj;
+                j = JoinJob{};
+                j.lkey = L->col[lc];
+                j.rkey = R->col[rc];
+                j.nl = (uint32_t)L->nrows;
+                j.nr = (uint32_t)R->nrows;
+                j.neq = (int)r.pj_eq.size();
+                for (int e = 0; e < j.neq; ++e) {
+                    j.eq_l[e] = L->col[r.pj_eq[e].first];
+                    // the pair names an output column: L's columns, then R's kept ones
+                    j.eq_r[e] = R->col[jp.rkeep[r.pj_eq[e].second - L->ncols]];
+                }
+                j.nlc = L->ncols;
+                for (int c = 0; c < L->ncols; ++c) j.lcol[c] = L->col[c];
+                j.nrc = 0;
+                for (size_t k = L->ncols; k < r.pj_keep.size(); ++k)
+                    j.rcol[j.nrc++] = R->col[jp.rkeep[r.pj_keep[k] - L->ncols]];
+                j.off = pj->sj_off.get<uint32_t>();
+                j.total = pj->sj_total.get<uint64_t>();
+                for (int c = 0; c < L->ncols; ++c) pj->vars.push_back(L->vars[c]);
+                for (int c = 0; c < j.nrc; ++c)
+                    pj->vars.push_back(R->vars[jp.rkeep[r.pj_keep[L->ncols + c] - L->ncols]]);
+                bs->count_jobs.push_back(j);
+                r.pj = std::move(pj);
+                r.pj_eq.clear();
+                r.pj->own_r = std::move(r.st.back().t);
+                r.st.pop_back();
+                r.pj->own_l = std::move(r.st.back().t);
+                r.st.pop_back();
+                r.pc += 2;
+                continue;
             }
             r.pj = join_begin(ctx, L, L->nrows, lc, R, R->nrows, rc, 0, jp);
             r.pj->own_r = std::move(r.st.back().t);
@@ -637,13 +713,37 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
         for (size_t j = 0; j < all.size(); ++j)
             runs[where[j].first].scanned[where[j].second] = alias_table(outs[rep[j]].get(), all[j]);
     }
+    BatchState bs;
     for (;;) {
+        // expand the small joins whose sizes reached the host: one launch
+        for (auto &r : runs) {
+            if (!r.pj || !r.pj->small || !r.pj->total_known || r.pj->small_result) continue;
+            auto t = make_table(ctx, (int)r.pj->vars.size(), r.pj->vars.data(), r.pj->total);
+            const tid_table *L = r.pj->own_l.get(), *R = r.pj->own_r.get();
+            t->maxv_known = L->maxv_known && R->maxv_known;
+            if (t->maxv_known) {
+                for (int c = 0; c < r.sj.nlc; ++c) t->maxv[c] = L->maxv[c];
+                for (int c = 0; c < r.sj.nrc; ++c)
+                    for (int x = 0; x < R->ncols; ++x)
+                        if (R->col[x] == r.sj.rcol[c]) t->maxv[r.sj.nlc + c] = R->maxv[x];
+            }
+            if (r.pj->total) {
+                JoinJob j = r.sj;
+                for (int c = 0; c < t->ncols; ++c) j.out[c] = t->col[c];
+                bs.expand_jobs.push_back(j);
+            }
+            set_count(ctx, t.get(), r.pj->total);
+            r.pj->small_result = std::move(t);
+        }
+        flush_join_jobs(ctx, bs, true);
         Needs needs;
         bool all_done = true;
         for (auto &r : runs) {
-            if (!r.done) advance(ctx, r, needs);
+            if (!r.done) advance(ctx, r, needs, &bs);
             all_done &= r.done;
         }
+        flush_join_jobs(ctx, bs, false);
+        flush_sort_jobs(ctx, bs);
         if (all_done) break;
         std::vector<const uint64_t *> src;
         for (tid_table *t : needs.tables) src.push_back(t->d_count);
@@ -651,6 +751,9 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
         TID_REQUIRE(!src.empty(), TID_E_INTERNAL, "query: no progress");
         std::vector<uint64_t> v(src.size());
         read_words(ctx, src, v.data());
+        bs.keep.clear();         // the round's launches have completed
+        bs.host_keep.clear();
+        bs.keep_tables.clear();
         size_t at = 0;
         for (tid_table *t : needs.tables) {
             t->nrows = v[at++];
@@ -661,6 +764,9 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
             j->total_known = true;
         }
     }
+    // the last round's batched sorts read tables kept in `bs`: wait for them
+    // before those go back to the pool
+    if (!bs.keep.empty() || !bs.keep_tables.empty()) ctx->sync();
     std::vector<std::unique_ptr<tid_table>> out(nq);
     for (int i = 0; i < nq; ++i) out[i] = std::move(runs[i].result);
     return out;
