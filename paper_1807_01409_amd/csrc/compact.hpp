@@ -271,7 +271,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
             const uint64_t dst = pre + r;
             if (dst < o.cap) {
                 TID_FOR_COLS(MAXC, c, o.ncols)
-                    o.col[c][dst] = stage[o.stage_off + (uint32_t)c * o.stage_cap + r];
+                    dev::put(&o.col[c][dst], stage[o.stage_off + (uint32_t)c * o.stage_cap + r]);
             } else {
                 atomicOr(&flags[1], 1u);
             }
@@ -301,7 +301,8 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
                     const uint64_t dst = base + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
                     const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
                     if (dst < o.cap) {
-                        TID_FOR_COLS(MAXC, c, o.ncols) o.col[c][dst] = src.value(j, c, item[it], i);
+                        TID_FOR_COLS(MAXC, c, o.ncols)
+                            dev::put(&o.col[c][dst], src.value(j, c, item[it], i));
                     } else {
                         atomicOr(&flags[1], 1u);
                     }
@@ -470,7 +471,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
                 const uint64_t dst = pre + r;
                 if (dst < o.cap) {
                     TID_FOR_COLS(MAXC, c, o.ncols)
-                        o.col[c][dst] = pb[o.stage_off + (uint32_t)c * o.stage_cap + r];
+                        dev::put(&o.col[c][dst], pb[o.stage_off + (uint32_t)c * o.stage_cap + r]);
                 } else {
                     atomicOr(&flags[1], 1u);
                 }
@@ -502,7 +503,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
                         const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
                         if (dst < o.cap) {
                             TID_FOR_COLS(MAXC, c, o.ncols)
-                                o.col[c][dst] = src.value(j, c, item[it], i);
+                                dev::put(&o.col[c][dst], src.value(j, c, item[it], i));
                         } else {
                             atomicOr(&flags[1], 1u);
                         }

@@ -57,6 +57,11 @@ __device__ __forceinline__ void bloom_add(uint32_t *bits, uint32_t mask, uint32_
     atomicOr(&bits[(hash32(x) & mask) >> 5], bloom_word_bits(x));
 }
 
+// Output rows of a compaction are written once and read by a later kernel:
+// non-temporal stores, so they stream to memory instead of taking L2 lines
+// that the graph's next tiles would use.
+__device__ __forceinline__ void put(uint32_t *p, uint32_t v) { __builtin_nontemporal_store(v, p); }
+
 // inclusive prefix sum across the wave
 template <class T>
 __device__ __forceinline__ T wave_inclusive_sum(T v) {
