@@ -296,3 +296,330 @@ void flush_sort_jobs(tid_ctx *ctx, BatchState &bs) {
 }
 
 }  // namespace tid
+
+// ---------------------------------------------------------------------------
+// larger joins of a batch
+// ---------------------------------------------------------------------------
+
+namespace tid {
+
+void exclusive_scan_async(tid_ctx *ctx, const uint32_t *in, uint64_t n, uint64_t *out);
+int device_cus(tid_ctx *ctx);
+
+namespace {
+
+constexpr int kBigBlock = 256;
+constexpr int kBigIPT = 4;
+constexpr uint64_t kBigTile = (uint64_t)kBigBlock * kBigIPT;
+constexpr int kBigLds = 2048;       // LDS rank table entries (> rows per tile)
+constexpr uint32_t kNoSlot32 = 0xFFFFFFFFu;
+
+// index j with base[j] <= x < base[j + 1] (base non-decreasing, base[0] = 0)
+__device__ __forceinline__ int job_of(const uint64_t *base, int J, uint64_t x) {
+    int lo = 0, hi = J;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Build: R rows, tile by tile from a work counter (tiles of all joins
+// concatenated; tbase = tile prefix per join).  Each row finds or claims its
+// key's slot; ranks within a slot are reserved per tile through an LDS table
+// (one global atomic per slot present in the tile, not per row).
+__global__ __launch_bounds__(kBigBlock) void big_insert(const BigCount *jobs, int J,
+                                                        const uint64_t *tbase, uint64_t ntiles,
+                                                        uint32_t *work, uint64_t *slots,
+                                                        uint32_t *cnt, uint32_t *slot_of,
+                                                        uint32_t *rank_of) {
+    __shared__ uint32_t s_slot[kBigLds], s_cnt[kBigLds], s_base[kBigLds];
+    __shared__ uint64_t s_tile;
+    for (int x = threadIdx.x; x < kBigLds; x += kBigBlock) {
+        s_slot[x] = kNoSlot32;
+        s_cnt[x] = 0;
+    }
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_tile = atomicAdd(work, 1u);
+        __syncthreads();
+        const uint64_t t = s_tile;
+        if (t >= ntiles) break;
+        const int j = job_of(tbase, J, t);
+        const BigCount &b = jobs[j];
+        const uint64_t r0 = (t - tbase[j]) * kBigTile;
+        uint32_t h[kBigIPT], e[kBigIPT], local[kBigIPT];
+#pragma unroll
+        for (int u = 0; u < kBigIPT; ++u) {
+            const uint64_t r = r0 + (uint64_t)u * kBigBlock + threadIdx.x;
+            if (r >= b.nr) continue;
+            const uint32_t key = b.rkey[r];
+            const uint64_t want = (uint64_t)key + 1ull;
+            uint32_t hh = dev::hash32(key) & b.mask;
+            for (uint32_t probe = 0; probe <= b.mask; ++probe) {  // ends: free slots remain
+                unsigned long long *w = (unsigned long long *)&slots[b.sbase + hh];
+                unsigned long long cur = *w;
+                if (cur == 0ull) cur = atomicCAS(w, 0ull, (unsigned long long)want);
+                if (cur == 0ull || cur == want) break;
+                hh = (hh + 1) & b.mask;
+            }
+            const uint32_t gs = (uint32_t)(b.sbase + hh);
+            uint32_t ee = gs & (kBigLds - 1);
+            for (;;) {  // ends: fewer distinct slots per tile than entries
+                const uint32_t prev = atomicCAS(&s_slot[ee], kNoSlot32, gs);
+                if (prev == kNoSlot32 || prev == gs) break;
+                ee = (ee + 1) & (kBigLds - 1);
+            }
+            h[u] = gs;
+            e[u] = ee;
+            local[u] = atomicAdd(&s_cnt[ee], 1u);
+        }
+        __syncthreads();
+        for (int x = threadIdx.x; x < kBigLds; x += kBigBlock) {
+            const uint32_t sl = s_slot[x];
+            if (sl != kNoSlot32) {
+                s_base[x] = atomicAdd(&cnt[sl], s_cnt[x]);
+                s_slot[x] = kNoSlot32;
+                s_cnt[x] = 0;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kBigIPT; ++u) {
+            const uint64_t r = r0 + (uint64_t)u * kBigBlock + threadIdx.x;
+            if (r >= b.nr) continue;
+            slot_of[b.rbase + r] = h[u];
+            rank_of[b.rbase + r] = s_base[e[u]] + local[u];
+        }
+    }
+}
+
+__global__ void big_fill(const BigCount *jobs, int J, const uint64_t *rbase, uint64_t nrows,
+                         const uint32_t *slot_of, const uint32_t *rank_of, const uint64_t *start,
+                         uint32_t *rows) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nrows; g += stride) {
+        const int j = job_of(rbase, J, g);
+        rows[start[slot_of[g]] + rank_of[g]] = (uint32_t)(g - jobs[j].rbase);
+    }
+}
+
+__device__ __forceinline__ bool big_agree(const uint32_t *const *el, const uint32_t *const *er,
+                                          int neq, uint64_t l, uint32_t r) {
+    bool ok = true;
+    for (int e = 0; e < neq; ++e) ok &= el[e][l] == er[e][r];
+    return ok;
+}
+
+__global__ void big_probe(const BigCount *jobs, int J, const uint64_t *lbase, uint64_t nrows,
+                          const uint64_t *slots, const uint32_t *cnt, const uint64_t *start,
+                          const uint32_t *rows, uint32_t *lslot, uint32_t *lcount) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < nrows; g += stride) {
+        const int j = job_of(lbase, J, g);
+        const BigCount &b = jobs[j];
+        const uint64_t l = g - b.lbase;
+        const uint32_t key = b.lkey[l];
+        const uint64_t want = (uint64_t)key + 1ull;
+        uint32_t h = dev::hash32(key) & b.mask;
+        uint32_t slot = kNoSlot32, c = 0;
+        for (uint32_t probe = 0; probe <= b.mask; ++probe) {
+            const uint64_t cur = slots[b.sbase + h];
+            if (cur == want) {
+                slot = (uint32_t)(b.sbase + h);
+                break;
+            }
+            if (cur == 0ull) break;
+            h = (h + 1) & b.mask;
+        }
+        if (slot != kNoSlot32) {
+            if (b.neq == 0) {
+                c = cnt[slot];
+            } else {
+                const uint64_t a = start[slot];
+                for (uint32_t m = 0; m < cnt[slot]; ++m)
+                    c += big_agree(b.eq_l, b.eq_r, b.neq, l, rows[a + m]);
+            }
+        }
+        lslot[g] = slot;
+        lcount[g] = c;
+    }
+}
+
+__global__ void big_totals(const BigCount *jobs, int J, const uint64_t *loff, uint64_t *tot) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < J; j += gridDim.x * blockDim.x)
+        tot[j] = loff[jobs[j].lbase + jobs[j].nl] - loff[jobs[j].lbase];
+}
+
+// one output row per thread: its join, its L row (binary search over the
+// join's slice of the offsets), the k-th partner in the L row's slot
+__global__ void big_expand(const BigExpand *jobs, int J, const uint64_t *obase, uint64_t ntotal,
+                           const uint64_t *loff, const uint32_t *lslot, const uint32_t *cnt,
+                           const uint64_t *start, const uint32_t *rows) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ntotal; g += stride) {
+        const int j = job_of(obase, J, g);
+        const BigExpand &b = jobs[j];
+        const uint64_t o = g - b.obase;
+        const uint64_t base = loff[b.lbase];
+        uint64_t lo = 0, hi = b.nl;  // last L row i with loff[i] - base <= o
+        while (hi - lo > 1) {
+            const uint64_t mid = (lo + hi) >> 1;
+            if (loff[b.lbase + mid] - base <= o) lo = mid;
+            else hi = mid;
+        }
+        const uint64_t i = lo;
+        uint64_t k = o - (loff[b.lbase + i] - base);
+        const uint32_t slot = lslot[b.lbase + i];
+        const uint64_t a = start[slot];
+        uint32_t r;
+        if (b.neq == 0) {
+            r = rows[a + k];
+        } else {  // the k-th partner that also agrees on the other shared variables
+            uint32_t m = 0;
+            for (;; ++m) {
+                r = rows[a + m];
+                if (big_agree(b.eq_l, b.eq_r, b.neq, i, r)) {
+                    if (k == 0) break;
+                    --k;
+                }
+            }
+        }
+        // the probe side is L or R; output columns are L's, then R's kept ones
+        const uint64_t li = b.probe_is_left ? i : r, ri = b.probe_is_left ? r : i;
+        for (int c = 0; c < b.nlc; ++c) b.out[c][o] = b.lcol[c][li];
+        for (int c = 0; c < b.nrc; ++c) b.out[b.nlc + c][o] = b.rcol[c][ri];
+    }
+}
+
+unsigned grid_cap(uint64_t n, uint64_t cap = 16384) {
+    return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, cap));
+}
+
+}  // namespace
+
+void flush_big_count(tid_ctx *ctx, std::vector<BigJoinReq> &reqs,
+                     std::shared_ptr<BigArena> *arena_out) {
+    if (reqs.empty()) return;
+    const int J = (int)reqs.size();
+    std::vector<BigCount> jobs(J);
+    std::vector<uint64_t> tbase(J + 1, 0), rbase(J + 1, 0), lbase(J + 1, 0);
+    uint64_t S = 0;
+    for (int j = 0; j < J; ++j) {
+        BigCount &b = jobs[j];
+        b = reqs[j].c;
+        uint64_t cap = 64;
+        while (cap < 2 * b.nr) cap <<= 1;
+        b.mask = (uint32_t)(cap - 1);
+        b.sbase = S;
+        S += cap;
+        b.rbase = rbase[j];
+        b.lbase = lbase[j];
+        rbase[j + 1] = rbase[j] + b.nr;
+        lbase[j + 1] = lbase[j] + b.nl;
+        tbase[j + 1] = tbase[j] + (b.nr + kBigTile - 1) / kBigTile;
+    }
+    const uint64_t NR = rbase[J], NL = lbase[J], T = tbase[J];
+    TID_REQUIRE(S < (1ull << 32) && NR < (1ull << 32), TID_E_UNSUPPORTED,
+                "batched joins: too many build rows in one round");
+    // one arena: job table and prefixes, then the per-slot and per-row arrays
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off += align_up(std::max<size_t>(bytes, 8));
+        return at;
+    };
+    const size_t o_jobs = take(J * sizeof(BigCount)), o_tb = take((J + 1) * 8),
+                 o_rb = take((J + 1) * 8), o_lb = take((J + 1) * 8), o_work = take(8),
+                 o_slots = take(S * 8), o_cnt = take(S * 4), o_start = take((S + 1) * 8),
+                 o_slotof = take(NR * 4), o_rank = take(NR * 4), o_rows = take(NR * 4),
+                 o_lslot = take(NL * 4), o_lcnt = take(NL * 4), o_loff = take((NL + 1) * 8),
+                 o_tot = take(J * 8);
+    auto arena = std::make_shared<BigArena>();
+    arena->buf = DevBuf(ctx, off);
+    char *base = arena->buf.get<char>();
+    arena->slots = reinterpret_cast<uint64_t *>(base + o_slots);
+    arena->cnt = reinterpret_cast<uint32_t *>(base + o_cnt);
+    arena->start = reinterpret_cast<uint64_t *>(base + o_start);
+    arena->rows = reinterpret_cast<uint32_t *>(base + o_rows);
+    arena->lslot = reinterpret_cast<uint32_t *>(base + o_lslot);
+    arena->loff = reinterpret_cast<uint64_t *>(base + o_loff);
+    arena->tot = reinterpret_cast<uint64_t *>(base + o_tot);
+    // host tables: one staging copy, then one upload
+    std::vector<char> host(o_slots);
+    std::memcpy(host.data() + o_jobs, jobs.data(), J * sizeof(BigCount));
+    std::memcpy(host.data() + o_tb, tbase.data(), (J + 1) * 8);
+    std::memcpy(host.data() + o_rb, rbase.data(), (J + 1) * 8);
+    std::memcpy(host.data() + o_lb, lbase.data(), (J + 1) * 8);
+    std::memset(host.data() + o_work, 0, 8);
+    TID_HIP(hipMemcpyAsync(base, host.data(), o_slots, hipMemcpyHostToDevice, ctx->stream));
+    // slot words and counts start at zero (one clear of the contiguous run)
+    TID_HIP(hipMemsetAsync(base + o_slots, 0, o_start - o_slots, ctx->stream));
+    const BigCount *dj = reinterpret_cast<const BigCount *>(base + o_jobs);
+    const uint64_t *dtb = reinterpret_cast<const uint64_t *>(base + o_tb);
+    const uint64_t *drb = reinterpret_cast<const uint64_t *>(base + o_rb);
+    const uint64_t *dlb = reinterpret_cast<const uint64_t *>(base + o_lb);
+    uint32_t *slot_of = reinterpret_cast<uint32_t *>(base + o_slotof);
+    uint32_t *rank_of = reinterpret_cast<uint32_t *>(base + o_rank);
+    uint32_t *lcount = reinterpret_cast<uint32_t *>(base + o_lcnt);
+    const unsigned workers = (unsigned)std::max<uint64_t>(
+        1, std::min<uint64_t>(T, 4ull * (uint64_t)device_cus(ctx)));
+    if (T)
+        hipLaunchKernelGGL(big_insert, dim3(workers), dim3(kBigBlock), 0, ctx->stream, dj, J,
+                           dtb, T, reinterpret_cast<uint32_t *>(base + o_work), arena->slots,
+                           arena->cnt, slot_of, rank_of);
+    TID_HIP(hipGetLastError());
+    exclusive_scan_async(ctx, arena->cnt, S, arena->start);
+    if (NR)
+        hipLaunchKernelGGL(big_fill, dim3(grid_cap(NR)), dim3(256), 0, ctx->stream, dj, J, drb,
+                           NR, slot_of, rank_of, arena->start, arena->rows);
+    TID_HIP(hipGetLastError());
+    if (NL)
+        hipLaunchKernelGGL(big_probe, dim3(grid_cap(NL)), dim3(256), 0, ctx->stream, dj, J, dlb,
+                           NL, arena->slots, arena->cnt, arena->start, arena->rows, arena->lslot,
+                           lcount);
+    TID_HIP(hipGetLastError());
+    exclusive_scan_async(ctx, lcount, NL, arena->loff);
+    hipLaunchKernelGGL(big_totals, dim3(grid_cap(J)), dim3(256), 0, ctx->stream, dj, J,
+                       arena->loff, arena->tot);
+    TID_HIP(hipGetLastError());
+    for (int j = 0; j < J; ++j) {
+        reqs[j].pj->total_ptr = arena->tot + j;
+        reqs[j].pj->big_lbase = lbase[j];
+        reqs[j].pj->big_arena = arena;
+    }
+    reqs.clear();
+    *arena_out = arena;
+}
+
+void flush_big_expand(tid_ctx *ctx, const BigArena &arena, std::vector<BigExpand> &jobs,
+                      BatchState &bs) {
+    if (jobs.empty()) return;
+    const int J = (int)jobs.size();
+    // jobs arrive with obase = their output's first row in the concatenated
+    // output space; bs.big_out_total is that space's size
+    std::vector<uint64_t> obase(J + 1, 0);
+    for (int j = 0; j < J; ++j) obase[j] = jobs[j].obase;
+    const uint64_t total = bs.big_out_total;
+    obase[J] = total;
+    const size_t bytes_jobs = align_up(J * sizeof(BigExpand));
+    std::vector<char> host(bytes_jobs + (J + 1) * 8);
+    std::memcpy(host.data(), jobs.data(), J * sizeof(BigExpand));
+    std::memcpy(host.data() + bytes_jobs, obase.data(), (J + 1) * 8);
+    bs.host_keep.push_back(std::move(host));
+    bs.keep.emplace_back(ctx, bs.host_keep.back().size());
+    char *d = bs.keep.back().get<char>();
+    TID_HIP(hipMemcpyAsync(d, bs.host_keep.back().data(), bs.host_keep.back().size(),
+                           hipMemcpyHostToDevice, ctx->stream));
+    if (total)
+        hipLaunchKernelGGL(big_expand, dim3(grid_cap(total)), dim3(256), 0, ctx->stream,
+                           reinterpret_cast<const BigExpand *>(d), J,
+                           reinterpret_cast<const uint64_t *>(d + bytes_jobs), total, arena.loff,
+                           arena.lslot, arena.cnt, arena.start, arena.rows);
+    TID_HIP(hipGetLastError());
+    jobs.clear();
+    bs.big_out_total = 0;
+}
+
+}  // namespace tid

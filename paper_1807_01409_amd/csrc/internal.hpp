@@ -291,7 +291,14 @@ struct PendingJoin {
     bool small = false;
     DevBuf sj_off, sj_total;
     std::unique_ptr<tid_table> small_result;
+    // a larger join of a batch (batch.hip): counted with the round's other
+    // larger joins in one arena; total_ptr is its size word there
+    bool big = false;
+    std::shared_ptr<void> big_arena;
+    const uint64_t *total_ptr = nullptr;
+    uint64_t big_lbase = 0;
     const uint64_t *d_total() const {
+        if (total_ptr) return total_ptr;
         return small ? sj_total.get<const uint64_t>() : off.get<const uint64_t>() + nq;
     }
 };

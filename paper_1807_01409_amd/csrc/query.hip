@@ -127,6 +127,7 @@ struct PlanRun {
     std::vector<Entry> st;
     std::unique_ptr<PendingJoin> pj;
     JoinJob sj{};                  // the job of pj when it is a small join
+    BigExpand bx{};                // the expansion of pj when it is a larger batched join
     std::vector<std::pair<int, int>> pj_eq;
     std::vector<int> pj_keep;
     std::unique_ptr<tid_table> result;
@@ -422,7 +423,7 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
                 needs.joins.push_back(r.pj.get());
                 return;
             }
-            if (r.pj->small) {  // expanded by the round's batched launch
+            if (r.pj->small || r.pj->big) {  // expanded by the round's batched launch
                 TID_REQUIRE(r.pj->small_result, TID_E_INTERNAL, "batched join not expanded");
                 auto t = std::move(r.pj->small_result);
                 r.pj.reset();
@@ -537,6 +538,56 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
                 for (int c = 0; c < j.nrc; ++c)
                     pj->vars.push_back(R->vars[jp.rkeep[r.pj_keep[L->ncols + c] - L->ncols]]);
                 bs->count_jobs.push_back(j);
+                r.pj = std::move(pj);
+                r.pj_eq.clear();
+                r.pj->own_r = std::move(r.st.back().t);
+                r.st.pop_back();
+                r.pj->own_l = std::move(r.st.back().t);
+                r.st.pop_back();
+                r.pc += 2;
+                continue;
+            }
+            if (bs && ctx->opt.batch_small && L->nrows > 0 && R->nrows > 0 &&
+                std::min(L->nrows, R->nrows) <= kBigBuildMax &&
+                (int)r.pj_eq.size() <= kSmallEq && L->ncols + nkeep <= kBigCols) {
+                // counted with this round's other larger joins, expanded next round;
+                // the hash is built on the smaller side
+                auto pj = std::make_unique<PendingJoin>();
+                pj->big = true;
+                pj->L = L;
+                pj->R = R;
+                const bool probe_left = R->nrows <= L->nrows;
+                BigJoinReq q{};
+                BigCount &c = q.c;
+                c.lkey = probe_left ? L->col[lc] : R->col[rc];
+                c.rkey = probe_left ? R->col[rc] : L->col[lc];
+                c.nl = probe_left ? L->nrows : R->nrows;
+                c.nr = probe_left ? R->nrows : L->nrows;
+                c.neq = (int)r.pj_eq.size();
+                BigExpand &x = r.bx;
+                x = BigExpand{};
+                x.nl = c.nl;
+                x.neq = c.neq;
+                x.probe_is_left = probe_left ? 1 : 0;
+                for (int e = 0; e < c.neq; ++e) {
+                    const uint32_t *lcol_e = L->col[r.pj_eq[e].first];
+                    const uint32_t *rcol_e = R->col[jp.rkeep[r.pj_eq[e].second - L->ncols]];
+                    c.eq_l[e] = x.eq_l[e] = probe_left ? lcol_e : rcol_e;
+                    c.eq_r[e] = x.eq_r[e] = probe_left ? rcol_e : lcol_e;
+                }
+                x.nlc = L->ncols;
+                for (int cc = 0; cc < L->ncols; ++cc) {
+                    x.lcol[cc] = L->col[cc];
+                    pj->vars.push_back(L->vars[cc]);
+                }
+                x.nrc = 0;
+                for (size_t k = L->ncols; k < r.pj_keep.size(); ++k) {
+                    const int rcx = jp.rkeep[r.pj_keep[k] - L->ncols];
+                    x.rcol[x.nrc++] = R->col[rcx];
+                    pj->vars.push_back(R->vars[rcx]);
+                }
+                q.pj = pj.get();
+                bs->big_reqs.push_back(q);
                 r.pj = std::move(pj);
                 r.pj_eq.clear();
                 r.pj->own_r = std::move(r.st.back().t);
@@ -736,6 +787,34 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
             r.pj->small_result = std::move(t);
         }
         flush_join_jobs(ctx, bs, true);
+        // expand the larger joins whose sizes reached the host: one launch
+        // (all were counted in the previous round, in one arena)
+        std::shared_ptr<BigArena> arena;
+        for (auto &r : runs) {
+            if (!r.pj || !r.pj->big || !r.pj->total_known || r.pj->small_result) continue;
+            arena = std::static_pointer_cast<BigArena>(r.pj->big_arena);
+            auto t = make_table(ctx, (int)r.pj->vars.size(), r.pj->vars.data(), r.pj->total);
+            const tid_table *L = r.pj->own_l.get(), *R = r.pj->own_r.get();
+            t->maxv_known = L->maxv_known && R->maxv_known;
+            if (t->maxv_known) {
+                for (int c = 0; c < r.bx.nlc; ++c) t->maxv[c] = L->maxv[c];
+                for (int c = 0; c < r.bx.nrc; ++c)
+                    for (int x = 0; x < R->ncols; ++x)
+                        if (R->col[x] == r.bx.rcol[c]) t->maxv[r.bx.nlc + c] = R->maxv[x];
+            }
+            if (r.pj->total) {
+                TID_REQUIRE(r.pj->total < (1ull << 40), TID_E_UNSUPPORTED, "join: output too large");
+                BigExpand x = r.bx;
+                x.lbase = r.pj->big_lbase;
+                x.obase = bs.big_out_total;
+                for (int c = 0; c < t->ncols; ++c) x.out[c] = t->col[c];
+                bs.big_out_total += r.pj->total;
+                bs.big_expand_jobs.push_back(x);
+            }
+            set_count(ctx, t.get(), r.pj->total);
+            r.pj->small_result = std::move(t);
+        }
+        if (arena) flush_big_expand(ctx, *arena, bs.big_expand_jobs, bs);
         Needs needs;
         bool all_done = true;
         for (auto &r : runs) {
@@ -744,6 +823,8 @@ std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph 
         }
         flush_join_jobs(ctx, bs, false);
         flush_sort_jobs(ctx, bs);
+        std::shared_ptr<BigArena> fresh;
+        flush_big_count(ctx, bs.big_reqs, &fresh);
         if (all_done) break;
         std::vector<const uint64_t *> src;
         for (tid_table *t : needs.tables) src.push_back(t->d_count);
