@@ -36,7 +36,6 @@ __global__ void fill_words(uint64_t *p, uint64_t n, uint64_t v) {
 namespace {
 struct NoAllocDevice {
     uint64_t *ptr = nullptr;  // the device address of `scratch` on this device
-    uint32_t epoch = 0;
 };
 std::mutex g_noalloc_mu;
 std::map<int, NoAllocDevice> g_noalloc;
@@ -69,29 +68,17 @@ void scan_noalloc(tid_ctx *ctx, const tid_graph *g, const tid_pattern &p,
     for (int c = 0; c < nc; ++c)
         TID_REQUIRE(cols && cols[c], TID_E_INVALID_ARG, "scan_noalloc: null output column");
     uint64_t *base = nullptr;
-    uint32_t epoch = 0;
-    bool wrap = false;
     {
         std::lock_guard<std::mutex> lock(g_noalloc_mu);
         auto it = g_noalloc.find(ctx->device);
         TID_REQUIRE(it != g_noalloc.end() && it->second.ptr, TID_E_INTERNAL,
                     "scan_noalloc: scratch not set up on this device");
         base = it->second.ptr;
-        if (++it->second.epoch > kEpochMax) {
-            it->second.epoch = 1;
-            wrap = true;
-        }
-        epoch = it->second.epoch;
     }
     if (g->n == 0) {
         hipLaunchKernelGGL(fill_words, dim3(1), dim3(64), 0, ctx->stream, d_count, 1ull, 0ull);
         TID_HIP(hipGetLastError());
         return;
-    }
-    if (wrap) {  // stamps restart: old count words must not look current
-        hipLaunchKernelGGL(fill_words, dim3(8), dim3(256), 0, ctx->stream, base,
-                           (uint64_t)kNoAllocWords, 0ull);
-        TID_HIP(hipGetLastError());
     }
     ScanSrc<1, false> sc{};
     CompactArgs<1, 3> a{};
@@ -107,7 +94,13 @@ void scan_noalloc(tid_ctx *ctx, const tid_graph *g, const tid_pattern &p,
                                                                                      sw);
     TID_REQUIRE(words <= kNoAllocFlagWord, TID_E_CAPACITY,
                 "scan_noalloc: the launch needs more ranges than the scratch array holds");
-    a.epoch = epoch;
+    // Every call clears the words its launch uses (a fill kernel, not a
+    // memset) and stamps them with epoch 1: the same launch sequence is then
+    // correct when recorded once in a HIP graph and replayed, whatever ran on
+    // the device in between.
+    hipLaunchKernelGGL(fill_words, dim3(8), dim3(256), 0, ctx->stream, base, (uint64_t)words, 0ull);
+    TID_HIP(hipGetLastError());
+    a.epoch = 1;
     block_ranged_launch<ScanSrc<1, false>, 512, 8, 1, 3, true>(
         ctx, sc, a, sw, base, reinterpret_cast<uint32_t *>(base + kNoAllocFlagWord));
 }

@@ -71,3 +71,57 @@ def test_noalloc_count_only_capacity_and_empty(ctx, graphs):
     got, n = scan_noalloc(ctx, E, p, 10)
     assert n == 0 and got.shape == (0, 2)
     E.free()
+
+
+def test_noalloc_scans_replayed_from_a_hip_graph(ctx, graphs):
+    """The allocation-free scan is the fixed-shape part of the path a caller
+    can record in a HIP graph: three scans into caller buffers are captured
+    once and replayed five times, with other scans (eager, other patterns) run
+    between the replays; every replay equals tid_scan's rows."""
+    import torch
+    from paper_1807_01409_amd.tid import _check, _pattern
+    g = graphs("medium", 3_000_000)
+    G = ctx.load(g)
+    pats = [Pattern(0, 2, 0, 0, -1, 1), Pattern(0, 14, 0, 0, -1, 1),
+            Pattern(0, 0, 0, 0, 1, 2, range_pos=2, lo=1000, hi=90000)]
+    want = [ctx.scan(G, p).to_numpy() for p in pats]
+    bufs = []
+    for p, w in zip(pats, want):
+        cap = w.shape[0] + 16
+        cols = [torch.zeros(cap, dtype=torch.int32, device="cuda") for _ in range(w.shape[1])]
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        bufs.append((p, cols, cnt, cap))
+    keep = []
+
+    def enqueue():
+        for p, cols, cnt, cap in bufs:
+            ptrs = (ctypes.c_void_p * len(cols))(*[c.data_ptr() for c in cols])
+            q = _pattern(p)
+            keep.append((ptrs, q))
+            _check(ctx.ptr, ctx._lib.tid_scan_noalloc(ctx.ptr, G._p, ctypes.byref(q), ptrs,
+                                                      len(cols), cap,
+                                                      ctypes.c_void_p(cnt.data_ptr())))
+
+    enqueue()                     # warm-up outside the capture
+    ctx.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=ctx.stream, capture_error_mode="relaxed"):
+        enqueue()
+    other = Pattern(0, 7, 0, 0, -1, 1)
+    for rep in range(5):
+        for _, cols, cnt, _ in bufs:
+            for c in cols:
+                c.fill_(-1)
+            cnt.fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for (p, cols, cnt, cap), w in zip(bufs, want):
+            n = int(cnt.item())
+            assert n == w.shape[0], (rep, p)
+            got = np.stack([c[:n].cpu().numpy().view(np.uint32) for c in cols], axis=1)
+            assert np.array_equal(got, w), (rep, p)
+        ctx.scan(G, other).free()                   # eager work between replays
+        scan_noalloc(ctx, G, other, G.count(1, 7, 8))
+        ctx.synchronize()
+    G.free()
