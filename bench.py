@@ -360,17 +360,24 @@ def batched_part(torch, args, spec, g, plans, infos):
 
 
 def serving_part(args, spec, g, plans, infos):
-    from paper_1807_01409_amd.serve import Request, Server
+    from paper_1807_01409_amd.serve import CircularServer, Request, Server
     from synth.batch import poisson_arrivals
     n_req = int(args.qps * args.duration)
     arrivals = poisson_arrivals(n_req, args.qps, spec.seed)
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([spec.seed, 0x5E7F])))
     pick = rng.integers(0, len(plans), size=n_req)
     reqs = [Request(i, plans[int(pick[i])], float(arrivals[i])) for i in range(n_req)]
-    srv = Server(g, workers=args.serve_workers, budget_bytes=int(args.budget_gb * (1 << 30)),
-                 max_batch=args.max_batch)
-    log("serving graph resident; warm-up burst")
-    srv.run([Request(-1 - i, plans[i % len(plans)], 0.0) for i in range(2 * args.max_batch)])
+    if args.serve_mode == "circular":
+        srv = CircularServer(g, chunks=args.chunks, slots=args.slots,
+                             budget_bytes=int(args.budget_gb * (1 << 30)))
+        srv.ctxs = [srv.ctx]
+        warm = 2 * args.slots
+    else:
+        srv = Server(g, workers=args.serve_workers, budget_bytes=int(args.budget_gb * (1 << 30)),
+                     max_batch=args.max_batch)
+        warm = 2 * args.max_batch
+    log(f"serving graph resident ({args.serve_mode}); warm-up burst")
+    srv.run([Request(-1 - i, plans[i % len(plans)], 0.0) for i in range(warm)])
     check = set(range(0, n_req, max(1, n_req // 64)))
     st = srv.run(reqs, keep_results=check, warmup_s=args.warmup_s)
     log(f"served {n_req} requests in {st.wall_s:.2f}s: p50 {st.p50_ms:.2f} ms p99 "
@@ -384,13 +391,18 @@ def serving_part(args, spec, g, plans, infos):
                 mism += 1
             t.free()
     srv.close()
+    mode = ({"mode": "circular chunked shared scan", "chunks": args.chunks, "slots": args.slots}
+            if args.serve_mode == "circular" else
+            {"mode": "groups of arrivals on worker streams", "workers": args.serve_workers,
+             "max_batch": args.max_batch})
     return {"metric": "serving p50/p99 latency and sustained queries/s", "unit": "queries/s",
-            "value": st.qps, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
+            "value": st.qps, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms, "server": mode,
+            "failed": st.failed,
             "offered_qps": args.qps, "requests": n_req, "duration_s": args.duration,
             "warmup_s": args.warmup_s, "completed_after_warmup": st.completed,
             "mean_batch": st.mean_batch, "max_queue": st.max_queue,
             "max_inflight_bytes": st.max_inflight_bytes,
-            "budget_gib": args.budget_gb, "workers": args.serve_workers,
+            "budget_gib": args.budget_gb,
             "mix_equals_alone_checked": len(check), "mix_equals_alone_mismatches": mism,
             "workload": f"serving graph {spec.n} triples resident in HBM (s Zipf 1.0/1e8, "
                         "p Zipf 1.2/1000, o Zipf 1.1/2e8); Poisson arrivals from a pool of "
@@ -452,6 +464,9 @@ def main():
     ap.add_argument("--warmup-s", type=float, default=1.0, help="serving: arrivals not measured")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: result budget")
     ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--serve-mode", choices=["circular", "groups"], default="circular")
+    ap.add_argument("--chunks", type=int, default=16, help="serving: chunks of the revolution")
+    ap.add_argument("--slots", type=int, default=512, help="serving: query slots")
     ap.add_argument("--max-batch", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:

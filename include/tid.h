@@ -52,6 +52,7 @@ typedef struct tid_ctx tid_ctx;
 typedef struct tid_graph tid_graph;
 typedef struct tid_table tid_table;
 typedef struct tid_dict tid_dict;
+typedef struct tid_server tid_server;
 
 /* Device-memory callbacks.  alloc returns a device pointer of at least
    `bytes` usable in stream order on `stream`, or NULL; free releases it.  Pass
@@ -328,6 +329,37 @@ tid_status tid_query_batch(tid_ctx *ctx, const tid_graph *g, const tid_plan *con
    work; used to admit queries against a memory budget. */
 tid_status tid_plan_estimate(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan,
                              uint64_t *bytes);
+
+/* ---- serving: a circular chunked shared scan --------------------------- */
+/* The paper keeps the TripleID array resident and answers every query with a
+   full search of it (Sec. 3, Algorithm 1, which loops over chunks of the
+   array).  A server cuts the resident graph into `chunks` contiguous chunks
+   and scans them one after another, round and round; each step scans the
+   next chunk once for every admitted query.  A submitted query is admitted
+   at the next chunk boundary into one of `slots` slots and has seen the whole
+   graph one revolution later; its per-chunk results are then joined end to
+   end in chunk order, so its scans equal scans of the whole graph, and its
+   remaining ops (joins, unions, filters, projections, DISTINCT, OPTIONAL) run
+   together with those of the other queries finishing at that step.  Every
+   result equals tid_query's.  One host thread at a time per server; the
+   server uses its context's stream.  tid_serve_open synchronises (it counts
+   each chunk's predicates). */
+tid_status tid_serve_open(tid_ctx *ctx, const tid_graph *g, int32_t chunks, int32_t slots,
+                          tid_server **out);
+/* Queue a plan (copied); *ticket names its result.  Checks the plan. */
+tid_status tid_serve_submit(tid_server *s, const tid_plan *plan, uint64_t *ticket);
+/* One step: admit waiting queries into free slots, scan the next chunk for all
+   admitted queries, finish those that have seen every chunk.  Their tickets go
+   to done[0..*n_done) (cap must be at least the slot count).  Synchronises. */
+tid_status tid_serve_step(tid_server *s, uint64_t *done, int32_t cap, int32_t *n_done);
+/* The result of a finished ticket (the caller frees the table), or the
+   status its query failed with; TID_E_INVALID_ARG for a ticket that is not
+   finished or was already taken. */
+tid_status tid_serve_result(tid_server *s, uint64_t ticket, tid_table **out);
+/* Queries waiting for a slot, queries in slots, the next chunk to scan. */
+tid_status tid_serve_info(const tid_server *s, int32_t *waiting, int32_t *active,
+                          int32_t *next_chunk);
+void tid_serve_close(tid_server *s);
 
 /* ---- dictionary (Sec. 3: conversion of RDF terms into TripleID rows) ---- */
 

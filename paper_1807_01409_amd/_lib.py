@@ -65,6 +65,12 @@ SIGNATURES = {
     "tid_decode": (_S, [_VP, _VP, _VP, ctypes.c_uint64, ctypes.c_int, _VP, _VP,
                         ctypes.c_uint64]),
     "tid_dict_free": (None, [_VP]),
+    "tid_serve_open": (_S, [_VP, _VP, ctypes.c_int32, ctypes.c_int32, _PP]),
+    "tid_serve_submit": (_S, [_VP, _VP, _U64P]),
+    "tid_serve_step": (_S, [_VP, _U64P, ctypes.c_int32, _I32P]),
+    "tid_serve_result": (_S, [_VP, ctypes.c_uint64, _PP]),
+    "tid_serve_info": (_S, [_VP, _I32P, _I32P, _I32P]),
+    "tid_serve_close": (None, [_VP]),
     "tid_scan_noalloc": (_S, [_VP, _VP, _VP, _VP, ctypes.c_int32, ctypes.c_uint64, _VP]),
     "tid_table_info": (_S, [_VP, _VP, _U64P, _I32P, _I32P]),
     "tid_table_column": (_S, [_VP, ctypes.c_int32, _PP]),

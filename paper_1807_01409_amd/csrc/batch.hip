@@ -623,3 +623,42 @@ void flush_big_expand(tid_ctx *ctx, const BigArena &arena, std::vector<BigExpand
 }
 
 }  // namespace tid
+
+namespace tid {
+
+namespace {
+__global__ void batch_copy_kernel(const CopyJob *jobs, const uint64_t *base, int J,
+                                  uint64_t total) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+        const int j = job_of(base, J, g);
+        const uint64_t i = g - base[j];
+        jobs[j].dst[i] = jobs[j].src[i];
+    }
+}
+}  // namespace
+
+void batch_copy(tid_ctx *ctx, const std::vector<CopyJob> &jobs, BatchState &bs) {
+    std::vector<CopyJob> nz;
+    for (const CopyJob &c : jobs)
+        if (c.n) nz.push_back(c);
+    if (nz.empty()) return;
+    const int J = (int)nz.size();
+    std::vector<uint64_t> base(J + 1, 0);
+    for (int j = 0; j < J; ++j) base[j + 1] = base[j] + nz[j].n;
+    const size_t bj = align_up(J * sizeof(CopyJob));
+    std::vector<char> host(bj + (J + 1) * 8);
+    std::memcpy(host.data(), nz.data(), J * sizeof(CopyJob));
+    std::memcpy(host.data() + bj, base.data(), (J + 1) * 8);
+    bs.host_keep.push_back(std::move(host));
+    bs.keep.emplace_back(ctx, bs.host_keep.back().size());
+    char *d = bs.keep.back().get<char>();
+    TID_HIP(hipMemcpyAsync(d, bs.host_keep.back().data(), bs.host_keep.back().size(),
+                           hipMemcpyHostToDevice, ctx->stream));
+    hipLaunchKernelGGL(batch_copy_kernel, dim3(grid_cap(base[J])), dim3(256), 0, ctx->stream,
+                       reinterpret_cast<const CopyJob *>(d),
+                       reinterpret_cast<const uint64_t *>(d + bj), J, base[J]);
+    TID_HIP(hipGetLastError());
+}
+
+}  // namespace tid

@@ -115,3 +115,15 @@ void flush_big_expand(tid_ctx *ctx, const BigArena &arena, std::vector<BigExpand
                       BatchState &bs);
 
 }  // namespace tid
+
+namespace tid {
+
+// Many device-to-device copies of uint32 runs in one launch.
+struct CopyJob {
+    const uint32_t *src;
+    uint32_t *dst;
+    uint64_t n;
+};
+void batch_copy(tid_ctx *ctx, const std::vector<CopyJob> &jobs, BatchState &bs);
+
+}  // namespace tid

@@ -44,6 +44,14 @@ std::unique_ptr<tid_table> scan_keyed(tid_ctx *, const tid_graph *, const tid_pa
                                       const uint32_t *, uint64_t);
 std::unique_ptr<tid_table> entail(tid_ctx *, const tid_graph *, int, const uint32_t *);
 void partition_graph(tid_ctx *, tid_graph *, bool);
+tid_server *serve_open(tid_ctx *, const tid_graph *, uint32_t, uint32_t);
+uint64_t serve_submit(tid_server *, const tid_plan *);
+std::vector<uint64_t> serve_step(tid_server *);
+void serve_free(tid_server *);
+tid_ctx *serve_ctx(const tid_server *);
+uint32_t serve_slots(const tid_server *);
+void serve_info(const tid_server *, int32_t *, int32_t *, int32_t *);
+tid_status serve_take(tid_server *, uint64_t, tid_table **, std::string *);
 std::unique_ptr<tid_dict> encode(tid_ctx *, const uint8_t *, uint64_t, const uint64_t *, uint64_t,
                                  int, uint32_t *);
 void decode(tid_ctx *, const tid_dict *, const uint32_t *, uint64_t, int, uint64_t *, uint8_t *,
@@ -52,8 +60,9 @@ std::unique_ptr<tid_table> join_tables_kind(tid_ctx *, const tid_table *, int, c
                                             int, int, int);
 std::unique_ptr<tid_table> sort_table(tid_ctx *, const tid_table *, int);
 std::unique_ptr<tid_table> run_query(tid_ctx *, const tid_graph *, const tid_plan *);
-std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *, const tid_graph *,
-                                                  const tid_plan *const *, int);
+std::vector<std::unique_ptr<tid_table>> run_plans(
+    tid_ctx *, const tid_graph *, const tid_plan *const *, int,
+    std::vector<std::vector<std::unique_ptr<tid_table>>> * = nullptr);
 uint64_t estimate_plan_bytes(const tid_graph *, const tid_plan *);
 void read_probe(tid_ctx *, const void *, uint64_t, int);
 void noalloc_init(tid_ctx *);
@@ -272,6 +281,64 @@ tid_status tid_graph_partition(tid_ctx *ctx, tid_graph *g, int32_t enable) {
         TID_REQUIRE(g, TID_E_INVALID_ARG, "null graph");
         tid::partition_graph(ctx, g, enable != 0);
     });
+}
+
+tid_status tid_serve_open(tid_ctx *ctx, const tid_graph *g, int32_t chunks, int32_t slots,
+                          tid_server **out) {
+    tid_server *sv = nullptr;
+    tid_status st = guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(g && out, TID_E_INVALID_ARG, "null argument");
+        TID_REQUIRE(chunks >= 1 && slots >= 1, TID_E_INVALID_ARG, "serve: chunks, slots >= 1");
+        sv = tid::serve_open(ctx, g, (uint32_t)chunks, (uint32_t)slots);
+    });
+    if (st == TID_OK) *out = sv;
+    return st;
+}
+
+tid_status tid_serve_submit(tid_server *s, const tid_plan *plan, uint64_t *ticket) {
+    if (!s || !ticket) return TID_E_INVALID_ARG;
+    tid_ctx *ctx = tid::serve_ctx(s);
+    return guarded(ctx, [&] {
+        check_ctx(ctx);
+        *ticket = tid::serve_submit(s, plan);
+    });
+}
+
+tid_status tid_serve_step(tid_server *s, uint64_t *done, int32_t cap, int32_t *n_done) {
+    if (!s || !n_done || (cap > 0 && !done)) return TID_E_INVALID_ARG;
+    tid_ctx *ctx = tid::serve_ctx(s);
+    return guarded(ctx, [&] {
+        check_ctx(ctx);
+        TID_REQUIRE(cap >= (int32_t)tid::serve_slots(s), TID_E_INVALID_ARG,
+                    "serve: cap must be at least the slot count");
+        const auto fin = tid::serve_step(s);
+        for (size_t i = 0; i < fin.size(); ++i) done[i] = fin[i];
+        *n_done = (int32_t)fin.size();
+    });
+}
+
+tid_status tid_serve_result(tid_server *s, uint64_t ticket, tid_table **out) {
+    if (!s || !out) return TID_E_INVALID_ARG;
+    std::string msg;
+    const tid_status st = tid::serve_take(s, ticket, out, &msg);
+    if (st != TID_OK) tid::serve_ctx(s)->last_error = msg;
+    return st;
+}
+
+tid_status tid_serve_info(const tid_server *s, int32_t *waiting, int32_t *active,
+                          int32_t *next_chunk) {
+    if (!s) return TID_E_INVALID_ARG;
+    tid::serve_info(s, waiting, active, next_chunk);
+    return TID_OK;
+}
+
+void tid_serve_close(tid_server *s) {
+    if (!s) return;
+    tid_ctx *ctx = tid::serve_ctx(s);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    tid::serve_free(s);
 }
 
 tid_status tid_encode(tid_ctx *ctx, const uint8_t *bytes, uint64_t nbytes,

@@ -168,6 +168,12 @@ struct tid_graph {
     // constant predicate then read only that slice (8 B per triple of p).
     tid::DevBuf part_s, part_o;
     bool partitioned = false;
+    // A chunk of another graph (circular serving scan): `view` is its first
+    // triple (not owned); positions without a histogram here take their
+    // bounds from `bounds_from`.
+    const uint32_t *view = nullptr;
+    const tid_graph *bounds_from = nullptr;
+    const uint32_t *triples() const { return view ? view : data.get<const uint32_t>(); }
     // number of triples with lo <= position value < hi (n if no histogram)
     uint64_t count_in(int pos, uint64_t lo, uint64_t hi) const;
 };

@@ -80,7 +80,7 @@ void partition_graph(tid_ctx *ctx, tid_graph *g, bool enable) {
     if (n) {
         DevBuf k0(ctx, n * 8), k1(ctx, n * 8), v0(ctx, n * 4), v1(ctx, n * 4);
         hipLaunchKernelGGL(predicate_keys, dim3(grid_of(n)), dim3(256), 0, ctx->stream,
-                           g->data.get<const uint32_t>(), n, k0.get<uint64_t>(),
+                           g->triples(), n, k0.get<uint64_t>(),
                            v0.get<uint32_t>());
         TID_HIP(hipGetLastError());
         const int bits = 32 - __builtin_clz(std::max<uint32_t>(g->max_id[1], 1));
@@ -88,7 +88,7 @@ void partition_graph(tid_ctx *ctx, tid_graph *g, bool enable) {
                                             k1.get<uint64_t>(), v1.get<uint32_t>(), n, bits);
         const uint32_t *perm = moved ? v1.get<const uint32_t>() : v0.get<const uint32_t>();
         hipLaunchKernelGGL(gather_so, dim3(grid_of(n)), dim3(256), 0, ctx->stream,
-                           g->data.get<const uint32_t>(), perm, n, s.get<uint32_t>(),
+                           g->triples(), perm, n, s.get<uint32_t>(),
                            o.get<uint32_t>());
         TID_HIP(hipGetLastError());
         TID_HIP(hipStreamSynchronize(ctx->stream));  // the sort buffers go back to the pool

@@ -6,6 +6,8 @@
 // returned in lexicographic row order.  A batch of plans advances in
 // lockstep, so the host waits for the device once per round for all plans.
 #include "batch.hpp"
+
+#include <deque>
 #include "compact.hpp"
 
 #include <map>
@@ -672,12 +674,22 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
 // Evaluate nq plans together: all their patterns in shared multi-pattern
 // passes over the graph, then their remaining ops in lockstep, every round
 // of device reads shared by all plans.
-std::vector<std::unique_ptr<tid_table>> run_plans(tid_ctx *ctx, const tid_graph *g,
-                                                  const tid_plan *const *plans, int nq) {
+// pre (may be null): per plan, the tables of its compiled scans, already
+// found (the circular serving scan); the plans then skip their scan rounds.
+std::vector<std::unique_ptr<tid_table>> run_plans(
+    tid_ctx *ctx, const tid_graph *g, const tid_plan *const *plans, int nq,
+    std::vector<std::vector<std::unique_ptr<tid_table>>> *pre = nullptr) {
     std::vector<PlanRun> runs(nq);
-    int nrounds = 1;
+    int nrounds = pre ? 0 : 1;
     for (int i = 0; i < nq; ++i) {
         compile_plan(plans[i], runs[i]);
+        if (pre) {
+            TID_REQUIRE((*pre)[i].size() == runs[i].scans.size(), TID_E_INTERNAL,
+                        "prescanned plan: scan count differs");
+            for (size_t k = 0; k < runs[i].scans.size(); ++k)
+                runs[i].scanned[k] = std::move((*pre)[i][k]);
+            continue;
+        }
         if (ctx->opt.semijoin) plan_rounds(g, runs[i], (uint64_t)ctx->opt.semijoin_min);
         for (const ScanRound &sr : runs[i].rounds) nrounds = std::max(nrounds, sr.round + 1);
     }
@@ -871,6 +883,212 @@ uint64_t estimate_plan_bytes(const tid_graph *g, const tid_plan *plan) {
 std::unique_ptr<tid_table> run_query(tid_ctx *ctx, const tid_graph *g, const tid_plan *plan) {
     auto v = run_plans(ctx, g, &plan, 1);
     return std::move(v[0]);
+}
+
+// ---------------------------------------------------------------------------
+// Serving with a circular chunked shared scan.  The graph is cut into C
+// contiguous chunks; one step scans the next chunk for the compiled scans of
+// every admitted query (one shared pass, as a batch's scans share passes).  A
+// query is admitted at a chunk boundary, into a free slot, and has seen the
+// whole graph one revolution later; its per-chunk tables are then joined end
+// to end in chunk order (so its scans equal a scan of the whole graph, rows
+// in ascending triple position), and its remaining ops run with those of the
+// other queries completing at the same step, in lockstep (run_plans).
+// ---------------------------------------------------------------------------
+
+void chunk_stats(tid_ctx *ctx, tid_graph *v);
+void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+               std::unique_ptr<tid_table> *outs, const PatternSet *sets,
+               const ScanFilter *filters);
+
+struct ServeQuery {
+    uint64_t ticket = 0;
+    std::vector<tid_pattern> pats;
+    std::vector<uint32_t> ops;
+    tid_plan plan{};
+    PlanRun pr;
+    uint32_t seen = 0;
+    std::vector<std::vector<std::unique_ptr<tid_table>>> parts;  // [scan][chunk]
+};
+
+}  // namespace tid
+
+struct tid_server {
+    tid_ctx *ctx = nullptr;
+    const tid_graph *g = nullptr;
+    uint32_t C = 1, slots = 1, next_chunk = 0;
+    std::vector<std::unique_ptr<tid_graph>> views;
+    std::deque<std::unique_ptr<tid::ServeQuery>> waiting;
+    std::vector<std::unique_ptr<tid::ServeQuery>> active;
+    std::map<uint64_t, std::unique_ptr<tid_table>> done;
+    std::map<uint64_t, std::pair<tid_status, std::string>> failed;
+    uint64_t next_ticket = 1;
+};
+
+namespace tid {
+
+tid_server *serve_open(tid_ctx *ctx, const tid_graph *g, uint32_t chunks, uint32_t slots) {
+    TID_REQUIRE(chunks >= 1 && chunks <= 4096, TID_E_INVALID_ARG, "serve: 1..4096 chunks");
+    TID_REQUIRE(slots >= 1, TID_E_INVALID_ARG, "serve: at least one slot");
+    auto s = std::make_unique<tid_server>();
+    s->ctx = ctx;
+    s->g = g;
+    s->C = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(chunks, std::max<uint64_t>(g->n, 1)));
+    s->slots = slots;
+    for (uint32_t k = 0; k < s->C; ++k) {
+        const uint64_t a = g->n * k / s->C, b = g->n * (k + 1) / s->C;
+        auto v = std::make_unique<tid_graph>();
+        v->ctx = ctx;
+        v->n = b - a;
+        v->view = g->triples() + 3 * a;
+        v->bounds_from = g;
+        for (int x = 0; x < 3; ++x) v->max_id[x] = g->max_id[x];
+        chunk_stats(ctx, v.get());
+        s->views.push_back(std::move(v));
+    }
+    return s.release();
+}
+
+void serve_free(tid_server *s) { delete s; }
+tid_ctx *serve_ctx(const tid_server *s) { return s->ctx; }
+uint32_t serve_slots(const tid_server *s) { return s->slots; }
+
+void serve_info(const tid_server *s, int32_t *waiting, int32_t *active, int32_t *next_chunk) {
+    if (waiting) *waiting = (int32_t)s->waiting.size();
+    if (active) *active = (int32_t)s->active.size();
+    if (next_chunk) *next_chunk = (int32_t)s->next_chunk;
+}
+
+// The result of a finished ticket, or the status its query failed with.
+tid_status serve_take(tid_server *s, uint64_t ticket, tid_table **out, std::string *msg) {
+    auto f = s->failed.find(ticket);
+    if (f != s->failed.end()) {
+        const tid_status code = f->second.first;
+        *msg = f->second.second;
+        s->failed.erase(f);
+        return code;
+    }
+    auto it = s->done.find(ticket);
+    if (it == s->done.end()) {
+        *msg = "serve: ticket not finished or already taken";
+        return TID_E_INVALID_ARG;
+    }
+    *out = it->second.release();
+    s->done.erase(it);
+    return TID_OK;
+}
+
+uint64_t serve_submit(tid_server *s, const tid_plan *plan) {
+    auto q = std::make_unique<ServeQuery>();
+    TID_REQUIRE(plan && plan->n_patterns >= 0 && plan->n_ops > 0 && plan->ops, TID_E_INVALID_ARG,
+                "serve: bad plan");
+    q->pats.assign(plan->patterns, plan->patterns + plan->n_patterns);
+    q->ops.assign(plan->ops, plan->ops + plan->n_ops);
+    q->plan.n_patterns = plan->n_patterns;
+    q->plan.patterns = q->pats.data();
+    q->plan.n_ops = plan->n_ops;
+    q->plan.ops = q->ops.data();
+    compile_plan(&q->plan, q->pr);  // checks the plan; lists its scans
+    q->ticket = s->next_ticket++;
+    const uint64_t t = q->ticket;
+    s->waiting.push_back(std::move(q));
+    return t;
+}
+
+// One step: admit into free slots, scan the next chunk for every admitted
+// query, finish the queries that have seen every chunk.  Returns their tickets.
+std::vector<uint64_t> serve_step(tid_server *s) {
+    tid_ctx *ctx = s->ctx;
+    while (!s->waiting.empty() && s->active.size() < s->slots) {
+        auto q = std::move(s->waiting.front());
+        s->waiting.pop_front();
+        q->parts.clear();
+        q->parts.resize(q->pr.scans.size());
+        for (auto &per : q->parts) per.resize(s->C);
+        s->active.push_back(std::move(q));
+    }
+    std::vector<uint64_t> finished;
+    if (s->active.empty()) return finished;
+    const uint32_t k = s->next_chunk;
+    const tid_graph *view = s->views[k].get();
+    // the chunk pass: identical scans across queries run once
+    std::vector<tid_pattern> all;
+    std::vector<PatternSet> sets;
+    std::vector<std::pair<ServeQuery *, size_t>> where;
+    std::map<std::string, size_t> uniq;
+    std::vector<size_t> rep;
+    for (auto &q : s->active)
+        for (size_t j = 0; j < q->pr.scans.size(); ++j) {
+            const auto ins = uniq.emplace(scan_key(q->pr.scans[j], q->pr.sets[j], ScanFilter{}),
+                                          all.size());
+            if (ins.second) {
+                all.push_back(q->pr.scans[j]);
+                sets.push_back(q->pr.sets[j]);
+            }
+            rep.push_back(ins.first->second);
+            where.emplace_back(q.get(), j);
+        }
+    std::vector<std::unique_ptr<tid_table>> outs(all.size());
+    if (!all.empty()) scan_many(ctx, view, all.data(), (int)all.size(), outs.data(), sets.data(),
+                                nullptr);
+    for (size_t w = 0; w < where.size(); ++w)
+        where[w].first->parts[where[w].second][k] =
+            alias_table(outs[rep[w]].get(), where[w].first->pr.scans[where[w].second]);
+    for (auto &q : s->active) ++q->seen;
+    s->next_chunk = (k + 1) % s->C;
+    // queries with a full revolution
+    std::vector<std::unique_ptr<ServeQuery>> complete, still;
+    for (auto &q : s->active) (q->seen == s->C ? complete : still).push_back(std::move(q));
+    s->active = std::move(still);
+    if (complete.empty()) return finished;
+    std::vector<tid_table *> counted;
+    for (auto &q : complete)
+        for (auto &per : q->parts)
+            for (auto &t : per) counted.push_back(t.get());
+    resolve_counts(ctx, counted.data(), (int)counted.size());
+    // each scan's chunk tables end to end, in chunk (= triple position) order
+    std::vector<std::vector<std::unique_ptr<tid_table>>> pre(complete.size());
+    std::vector<CopyJob> copies;
+    for (size_t i = 0; i < complete.size(); ++i) {
+        ServeQuery &q = *complete[i];
+        for (auto &per : q.parts) {
+            uint64_t rows = 0;
+            for (auto &t : per) rows += t->nrows;
+            const tid_table *t0 = per[0].get();
+            auto cat = make_table(ctx, t0->ncols, t0->vars, rows);
+            cat->maxv_known = t0->maxv_known;
+            copy_bounds(cat.get(), t0, nullptr, t0->ncols);
+            uint64_t at = 0;
+            for (auto &t : per) {
+                for (int c = 0; c < t->ncols; ++c)
+                    copies.push_back(CopyJob{t->col[c], cat->col[c] + at, t->nrows});
+                at += t->nrows;
+            }
+            set_count(ctx, cat.get(), rows);
+            pre[i].push_back(std::move(cat));
+        }
+    }
+    BatchState bs;
+    batch_copy(ctx, copies, bs);
+    for (auto &q : complete) q->parts.clear();  // the chunk tables go back in stream order
+    std::vector<const tid_plan *> plans;
+    for (auto &q : complete) plans.push_back(&q->plan);
+    try {
+        auto res = run_plans(ctx, s->g, plans.data(), (int)plans.size(), &pre);
+        for (size_t i = 0; i < complete.size(); ++i) {
+            s->done[complete[i]->ticket] = std::move(res[i]);
+            finished.push_back(complete[i]->ticket);
+        }
+    } catch (const Error &e) {
+        // a group that fails (memory, ...) is not retried here: each query of
+        // it reports the error
+        for (auto &q : complete) {
+            s->failed[q->ticket] = {e.code, e.what()};
+            finished.push_back(q->ticket);
+        }
+    }
+    ctx->sync();  // the copy job tables in `bs` are read by now
+    return finished;
 }
 
 }  // namespace tid

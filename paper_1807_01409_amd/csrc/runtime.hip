@@ -380,10 +380,37 @@ uint32_t tid_ctx::next_epoch(size_t bytes, uint64_t **state) {
 
 void tid_ctx::sync() { TID_HIP(hipStreamSynchronize(stream)); }
 
+namespace tid {
+
+// The predicate histogram of a chunk view (its other positions take their
+// bounds from the whole graph's histograms).
+void chunk_stats(tid_ctx *ctx, tid_graph *v) {
+    if (v->n == 0 || v->max_id[1] >= kMaxHistIds) return;
+    HistArgs a{};
+    a.nbins[1] = v->max_id[1] + 1;
+    DevBuf hist(ctx, (size_t)a.nbins[1] * sizeof(uint32_t));
+    TID_HIP(hipMemsetAsync(hist.get(), 0, (size_t)a.nbins[1] * sizeof(uint32_t), ctx->stream));
+    a.hist[1] = hist.get<uint32_t>();
+    const int hb = (int)std::min<uint64_t>((v->n + kHistBlock - 1) / kHistBlock,
+                                           2ull * (uint64_t)device_cus(ctx));
+    hipLaunchKernelGGL(hist3_kernel, dim3(hb), dim3(kHistBlock), 0, ctx->stream, v->triples(),
+                       v->n, a);
+    TID_HIP(hipGetLastError());
+    std::vector<uint32_t> hh(a.nbins[1]);
+    TID_HIP(hipMemcpyAsync(hh.data(), hist.get(), hh.size() * sizeof(uint32_t),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    TID_HIP(hipStreamSynchronize(ctx->stream));
+    auto &c = v->cdf[1];
+    c.assign((size_t)a.nbins[1] + 1, 0);
+    for (uint32_t i = 0; i < a.nbins[1]; ++i) c[i + 1] = c[i] + hh[i];
+}
+
+}  // namespace tid
+
 uint64_t tid_graph::count_in(int pos, uint64_t lo, uint64_t hi) const {
     if (hi <= lo) return 0;
     const auto &c = cdf[pos];
-    if (c.empty()) return n;
+    if (c.empty()) return bounds_from ? std::min(n, bounds_from->count_in(pos, lo, hi)) : n;
     const uint64_t last = c.size() - 1;  // c[last] = n
     const uint64_t a = std::min<uint64_t>(lo, last), b = std::min<uint64_t>(hi, last);
     return c[b] - c[a];

@@ -365,7 +365,7 @@ static void launch_multi(tid_ctx *ctx, const tid_graph *g, MultiArgs &a, int k, 
     uint64_t *sync = state + 1;
     uint32_t *counters = reinterpret_cast<uint32_t *>(state);
     hipLaunchKernelGGL(kern, dim3((uint32_t)P), dim3(BLOCK), lds, ctx->stream,
-                       g->data.get<const uint32_t>(), n, a, sync, counters, ctx->d_flags);
+                       g->triples(), n, a, sync, counters, ctx->d_flags);
     TID_HIP(hipGetLastError());
 }
 

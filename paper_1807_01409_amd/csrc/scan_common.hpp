@@ -172,7 +172,7 @@ template <class SRC, int MAXK>
 void fill_scan_args(const tid_graph *g, const tid_pattern *pats, int k,
                            tid_table *const *outs, const PatternSet *sets,
                            const ScanFilter *filters, SRC &src, CompactArgs<MAXK, 3> &a) {
-    src.g = g->data.get<const uint32_t>();
+    src.g = g->triples();
     src.n = g->n;
     for (int j = 0; j < k; ++j) {
         src.pat[j] = compile_pattern(pats[j], sets ? &sets[j] : nullptr,

@@ -82,7 +82,7 @@ void scan_noalloc(tid_ctx *ctx, const tid_graph *g, const tid_pattern &p,
     }
     ScanSrc<1, false> sc{};
     CompactArgs<1, 3> a{};
-    sc.g = g->data.get<const uint32_t>();
+    sc.g = g->triples();
     sc.n = g->n;
     sc.pat[0] = compile_pattern(p);
     for (int c = 0; c < nc; ++c) a.out[0].col[c] = cols[c];

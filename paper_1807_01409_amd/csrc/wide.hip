@@ -427,7 +427,7 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
 void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
               tid_table *const *outs, const ScanFilter *filters) {
     WideSource whole;
-    whole.g = g->data.get<const uint32_t>();
+    whole.g = g->triples();
     whole.n = g->n;
     std::vector<std::vector<int>> by_pred(kWidePreds);
     for (int j = 0; j < k; ++j)

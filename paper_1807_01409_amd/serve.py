@@ -191,3 +191,127 @@ class Server:
                           max_inflight_bytes=int(max_inflight), max_queue=int(max_queue),
                           latencies_ms=lat.tolist(), failed=sum(1 for r in reqs if r.error))
 
+
+
+class CircularServer:
+    """Serving with the library's circular chunked shared scan (tid_serve_*).
+
+    The resident graph is cut into `chunks` contiguous chunks scanned one per
+    step, round and round, for every admitted query; a query is admitted at a
+    chunk boundary into one of `slots` slots (while the estimated bytes of the
+    queries in flight stay under the budget) and finishes one revolution
+    later, its joins and other ops run with those of the queries finishing at
+    the same step.  Results equal tid_query's."""
+
+    def __init__(self, triples, chunks: int = 16, slots: int = 512,
+                 budget_bytes: int = 64 << 30, device: int = 0):
+        import ctypes
+
+        from . import _lib as L
+        from .tid import _check
+        self._ct = ctypes
+        self._L = L
+        self._check = _check
+        self.ctx = Context(device)
+        self.graph: Graph = self.ctx.load(triples)
+        self.budget = int(budget_bytes)
+        self.slots = int(slots)
+        out = ctypes.c_void_p()
+        _check(self.ctx.ptr, self.ctx._lib.tid_serve_open(self.ctx.ptr, self.graph._p, int(chunks),
+                                                          self.slots, ctypes.byref(out)))
+        self._s = out
+        self.chunks = int(chunks)
+
+    def close(self):
+        if self._s:
+            self.ctx._lib.tid_serve_close(self._s)
+            self._s = None
+        self.graph.free()
+        self.ctx.close()
+
+    def _submit(self, plan) -> int:
+        from .tid import _plan
+        keep: list = []
+        cp = _plan(plan, keep)
+        t = self._ct.c_uint64()
+        self._check(self.ctx.ptr, self.ctx._lib.tid_serve_submit(self._s, self._ct.byref(cp),
+                                                                 self._ct.byref(t)))
+        return int(t.value)
+
+    def _step(self) -> List[int]:
+        buf = (self._ct.c_uint64 * self.slots)()
+        n = self._ct.c_int32()
+        self._check(self.ctx.ptr, self.ctx._lib.tid_serve_step(self._s, buf, self.slots,
+                                                               self._ct.byref(n)))
+        return [int(buf[i]) for i in range(n.value)]
+
+    def _result(self, ticket: int):
+        from .tid import Table, TidError
+        out = self._ct.c_void_p()
+        st = self.ctx._lib.tid_serve_result(self._s, ticket, self._ct.byref(out))
+        if st != 0:
+            raise TidError(st, self.ctx._lib.tid_last_error(self.ctx.ptr).decode())
+        return Table(self.ctx, out)
+
+    def run(self, requests: Sequence[Request], keep_results=False,
+            warmup_s: float = 0.0) -> ServeStats:
+        from .tid import TidError
+        for r in requests:
+            r.est_bytes = self.ctx.plan_estimate(self.graph, r.plan)
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        waiting: "collections.deque[Request]" = collections.deque()
+        inflight: dict = {}
+        inflight_bytes = 0
+        nxt = finished = 0
+        steps = max_queue = max_inflight = 0
+        t0 = time.perf_counter()
+        while finished < len(reqs):
+            now = time.perf_counter() - t0
+            while nxt < len(reqs) and reqs[nxt].arrival <= now:
+                waiting.append(reqs[nxt])
+                nxt += 1
+            max_queue = max(max_queue, len(waiting))
+            # admit in arrival order while slots and budget allow; a request
+            # larger than the budget runs alone when nothing else does
+            while waiting and len(inflight) < self.slots:
+                r = waiting[0]
+                if inflight_bytes + r.est_bytes > self.budget and inflight:
+                    break
+                waiting.popleft()
+                r.admitted = time.perf_counter() - t0
+                inflight[self._submit(r.plan)] = r
+                inflight_bytes += r.est_bytes
+            max_inflight = max(max_inflight, inflight_bytes)
+            if not inflight:
+                if nxt < len(reqs):
+                    time.sleep(max(0.0, min(0.001, reqs[nxt].arrival - now)))
+                continue
+            done = self._step()
+            steps += 1
+            tnow = time.perf_counter() - t0
+            for tk in done:
+                r = inflight.pop(tk)
+                inflight_bytes -= r.est_bytes
+                try:
+                    t = self._result(tk)
+                    if keep_results is True or (keep_results and r.rid in keep_results):
+                        r.result = t.to_numpy()
+                        r.rows = r.result.shape[0]
+                    else:
+                        r.rows = t.nrows
+                    t.free()
+                except TidError as e:
+                    r.error = str(e)
+                r.done = tnow
+                finished += 1
+        wall = time.perf_counter() - t0
+        meas = [r for r in reqs if r.arrival >= warmup_s]
+        lat = np.array([(r.done - r.arrival) * 1e3 for r in meas]) if meas else np.zeros(1)
+        span = (max(r.done for r in meas) - warmup_s) if meas else wall
+        return ServeStats(completed=len(meas), wall_s=wall,
+                          qps=len(meas) / span if span > 0 else 0.0,
+                          p50_ms=float(np.percentile(lat, 50)),
+                          p99_ms=float(np.percentile(lat, 99)),
+                          mean_batch=float(len(reqs)) / max(steps, 1) * self.chunks,
+                          max_inflight_bytes=int(max_inflight), max_queue=int(max_queue),
+                          latencies_ms=lat.tolist(), failed=sum(1 for r in reqs if r.error))

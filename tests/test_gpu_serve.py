@@ -3,6 +3,7 @@ equals the same query run alone (byte for byte), and the oracle's."""
 import numpy as np
 import pytest
 
+import oracle
 from oracle_threads import oracle_queries
 from synth.batch import PredIndex, batch_queries, poisson_arrivals
 
@@ -81,3 +82,55 @@ def test_served_group_failure_is_contained(ctx, mix):
     for r in reqs:
         if not r.error:
             assert r.result.shape[0] <= 1
+
+
+@pytest.mark.parametrize("chunks,slots", [(1, 8), (3, 16), (7, 40)])
+def test_circular_served_mix_equals_oracle(ctx, mix, mix_oracle, chunks, slots):
+    """The circular chunked shared scan (tid_serve_*): queries admitted at
+    different chunks of the revolution, results equal the oracle's and
+    tid_query's, whatever the chunk and slot counts."""
+    from paper_1807_01409_amd.serve import CircularServer, Request
+    g, plans, infos = mix
+    arrivals = poisson_arrivals(150, qps=3000.0, seed=13)
+    reqs = [Request(i, plans[(7 * i) % len(plans)], float(arrivals[i])) for i in range(150)]
+    srv = CircularServer(g, chunks=chunks, slots=slots)
+    try:
+        stats = srv.run(reqs, keep_results=True)
+    finally:
+        srv.close()
+    assert stats.completed == len(reqs) and stats.failed == 0
+    for r in reqs:
+        assert np.array_equal(r.result, mix_oracle[(7 * r.rid) % len(plans)]), r.rid
+
+
+def test_circular_tickets_and_errors(ctx, graphs):
+    """A ticket's result is taken once; a bad plan is refused at submit; the
+    info call tracks waiting and admitted queries."""
+    import ctypes
+    from paper_1807_01409_amd.serve import CircularServer
+    from paper_1807_01409_amd import TidError
+    from synth import Plan, pat
+    g = graphs("small")
+    srv = CircularServer(g, chunks=4, slots=4)
+    try:
+        n = {}
+        plan = Plan().scan(pat("?s 3 ?a", n)).scan(pat("?s 11 ?b", n)).join(n["?s"])
+        tickets = [srv._submit(plan) for _ in range(6)]
+        w, a, k = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        srv.ctx._lib.tid_serve_info(srv._s, ctypes.byref(w), ctypes.byref(a), ctypes.byref(k))
+        assert (w.value, a.value) == (6, 0)
+        done = []
+        while len(done) < 6:
+            done += srv._step()
+        assert sorted(done) == sorted(tickets)
+        want = oracle.query(g, plan).rows
+        for tk in tickets:
+            assert np.array_equal(srv._result(tk).to_numpy(), want)
+        with pytest.raises(TidError):
+            srv._result(tickets[0])
+        bad = Plan()
+        bad.ops = [99]
+        with pytest.raises(TidError):
+            srv._submit(bad)
+    finally:
+        srv.close()
