@@ -285,6 +285,10 @@ void flush_join_jobs(tid_ctx *ctx, BatchState &bs, bool expand) {
 }
 
 void flush_sort_jobs(tid_ctx *ctx, BatchState &bs) {
+    if (!bs.row_sorts.empty()) {
+        sort_rows_batched(ctx, bs.row_sorts, bs.keep, bs.host_keep);
+        bs.row_sorts.clear();
+    }
     if (bs.sort_jobs.empty()) return;
     const SortJob *d = upload(ctx, bs, bs.sort_jobs);
     for (size_t j0 = 0; j0 < bs.sort_jobs.size(); j0 += 65535) {

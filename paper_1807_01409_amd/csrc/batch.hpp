@@ -27,6 +27,16 @@ struct JoinJob {
     uint64_t *total;
 };
 
+// A table to put in lexicographic row order with the round's other larger
+// sorts (sort_rows_batched, sort.hip): input, output (n rows allocated).
+struct RowSortJob {
+    const tid_table *in;
+    tid_table *out;
+    uint64_t n;
+};
+void sort_rows_batched(tid_ctx *ctx, const std::vector<RowSortJob> &jobs,
+                       std::vector<DevBuf> &keep, std::vector<std::vector<char>> &host_keep);
+
 struct SortJob {
     const uint32_t *in[kSortCols];
     uint32_t *out[kSortCols];
@@ -40,6 +50,7 @@ struct SortJob {
 struct BatchState {
     std::vector<JoinJob> count_jobs, expand_jobs;
     std::vector<SortJob> sort_jobs;
+    std::vector<RowSortJob> row_sorts;
     std::vector<DevBuf> keep;
     std::vector<std::vector<char>> host_keep;
     std::vector<std::unique_ptr<tid_table>> keep_tables;  // inputs of queued sorts
@@ -49,7 +60,7 @@ struct BatchState {
 };
 // launch and clear the queued jobs of one kind
 void flush_join_jobs(tid_ctx *ctx, BatchState &bs, bool expand);
-void flush_sort_jobs(tid_ctx *ctx, BatchState &bs);
+void flush_sort_jobs(tid_ctx *ctx, BatchState &bs);  // small sorts, then the larger ones
 
 }  // namespace tid
 

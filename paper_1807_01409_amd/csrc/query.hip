@@ -472,6 +472,20 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
                 r.done = true;
                 return;
             }
+            if (bs && ctx->opt.batch_small && T->ncols > 0 && T->maxv_known &&
+                T->nrows > 1 && T->nrows < (1ull << 32)) {
+                // one job of the round's batched larger sorts; the input stays
+                // alive in the batch state until the round's wait
+                auto out = make_table(ctx, T->ncols, T->vars, T->nrows);
+                out->maxv_known = T->maxv_known;
+                copy_bounds(out.get(), T, nullptr, T->ncols);
+                set_count(ctx, out.get(), T->nrows);
+                bs->row_sorts.push_back(RowSortJob{T, out.get(), T->nrows});
+                bs->keep_tables.push_back(std::move(top.t));
+                r.result = std::move(out);
+                r.done = true;
+                return;
+            }
             r.result = sort_rows(ctx, top.t.get(), top.t->nrows, 0);
             r.done = true;
             return;

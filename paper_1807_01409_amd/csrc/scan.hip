@@ -446,18 +446,88 @@ static void run_scan_any(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pa
 bool wide_eligible(const tid_pattern &p);
 void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
               tid_table *const *outs, const ScanFilter *filters);
+void run_wide_parts(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+                    tid_table *const *outs, const ScanFilter *filters);
+
+// A pattern whose rows are exactly its predicate's slice of the partitioned
+// layout: a constant predicate, subject and object free (and not one
+// variable), no range, no filter and no value set.
+static bool whole_slice(const tid_pattern &p, const PatternSet *set, const ScanFilter *f) {
+    return p.p != 0 && p.s == 0 && p.o == 0 && p.range_pos < 0 && !(p.vs >= 0 && p.vs == p.vo) &&
+           (!set || set->pos < 0) && (!f || f->pos < 0);
+}
+
+// The rows of a whole-slice pattern without a pass: the table's columns point
+// into the partitioned layout (read only, valid while the graph's layout is).
+static std::unique_ptr<tid_table> slice_table(tid_ctx *ctx, const tid_graph *g,
+                                              const tid_pattern &p) {
+    int32_t vars[3], src[3];
+    const int nc = pattern_schema(p, vars, src);
+    const auto &cdf = g->cdf[1];
+    const uint64_t last = cdf.size() - 1;
+    const uint64_t a = cdf[std::min<uint64_t>(p.p, last)];
+    const uint64_t b = cdf[std::min<uint64_t>((uint64_t)p.p + 1, last)];
+    auto t = make_table(ctx, nc, vars, 0);  // the count word only
+    for (int c = 0; c < nc; ++c) {
+        t->col[c] = const_cast<uint32_t *>(
+            (src[c] == 0 ? g->part_s : g->part_o).get<const uint32_t>() + a);
+        t->maxv[c] = g->max_id[src[c]];
+    }
+    t->maxv_known = true;
+    t->cap = b - a;
+    set_count(ctx, t.get(), b - a);
+    return t;
+}
 
 // Any number of patterns: those with a constant (bucketable) predicate go
 // through wide passes of up to 1024 patterns when there are at least
-// `wide_min` of them; the rest through passes of up to 16.
+// `wide_min` of them; the rest through passes of up to 16.  With the graph's
+// partitioned layout built, a constant predicate's patterns read only its
+// slice: a whole-slice pattern reads nothing (its table is the slice), the
+// others go through segment passes over the slices they need.  Tables that
+// point into the layout are for plan evaluation only: every plan result is a
+// table of its own.
 void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                std::unique_ptr<tid_table> *outs, const PatternSet *sets,
                const ScanFilter *filters) {
     const int64_t wide_min = ctx->opt.wide_min > 0 ? ctx->opt.wide_min : 8;
+    const bool parts = g->partitioned && ctx->opt.layout != 0 && g->n > 0 &&
+                       ctx->opt.capacity_override <= 0 && !g->cdf[1].empty();
     std::vector<int> wide, rest;
     for (int j = 0; j < k; ++j) {
-        const bool has_set = sets && sets[j].pos >= 0;
-        (!has_set && wide_eligible(pats[j]) ? wide : rest).push_back(j);
+        const PatternSet *set = sets ? &sets[j] : nullptr;
+        const ScanFilter *f = filters ? &filters[j] : nullptr;
+        if (parts && whole_slice(pats[j], set, f)) {
+            outs[j] = slice_table(ctx, g, pats[j]);
+            continue;
+        }
+        const bool ok = (!set || set->pos < 0) && !(f && f->pos >= 0 && f->exact) &&
+                        wide_eligible(pats[j]);
+        (ok ? wide : rest).push_back(j);
+    }
+    if (parts && wide.size() >= 2) {
+        // segment passes, however few the patterns: one read of their slices
+        // to count and one to write, against a graph read per 4 patterns
+        for (size_t w0 = 0; w0 < wide.size(); w0 += 1024) {
+            const int m = (int)std::min<size_t>(1024, wide.size() - w0);
+            std::vector<tid_pattern> wp(m);
+            std::vector<ScanFilter> wf(m);
+            std::vector<tid_table *> wt(m);
+            for (int j = 0; j < m; ++j) {
+                const tid_pattern &p = pats[wide[w0 + j]];
+                int32_t vars[3], src[3];
+                const int nc = pattern_schema(p, vars, src);
+                auto t = make_table(ctx, nc, vars, pattern_bound(g, p));
+                for (int c = 0; c < nc; ++c) t->maxv[c] = g->max_id[src[c]];
+                t->maxv_known = true;
+                wp[j] = p;
+                if (filters) wf[j] = filters[wide[w0 + j]];
+                wt[j] = t.get();
+                outs[wide[w0 + j]] = std::move(t);
+            }
+            run_wide_parts(ctx, g, wp.data(), m, wt.data(), wf.data());
+        }
+        wide.clear();
     }
     if ((int64_t)wide.size() < wide_min || ctx->opt.capacity_override > 0 || g->n == 0) {
         rest.insert(rest.end(), wide.begin(), wide.end());

@@ -19,6 +19,7 @@
 // A row of k columns is sorted as one or more packed 64-bit keys (as many
 // leading columns as fit their bit widths), least significant group first,
 // carrying the row permutation as the value.
+#include "batch.hpp"
 #include "compact.hpp"
 
 #include <algorithm>
@@ -358,6 +359,218 @@ struct UniqueSrc {
 };
 
 // ---------------------------------------------------------------------------
+// Batched row sorts: the final sorts of many plans of one round share their
+// launches.  Each job is one table's (key, value) pairs; a pass cuts every
+// active job into ranges of whole tiles (the ranges of all jobs concatenated,
+// rbase = a job's first range) and runs the three steps of the single sort
+// above over all of them: per-range digit counts, one workgroup per job that
+// turns its counts into output offsets (four quarters of its ranges in
+// parallel), and the stable scatter of every range.
+// ---------------------------------------------------------------------------
+
+struct SegPass {
+    const uint64_t *kin;
+    const uint32_t *vin;
+    uint64_t *kout;
+    uint32_t *vout;
+    uint64_t n;         // pairs
+    uint64_t range;     // pairs per range, a multiple of the tile
+    uint64_t rbase;     // the job's first range in this pass
+    uint32_t nranges;
+    int32_t shift;
+};
+
+// job j with jobs[j].rbase <= r < jobs[j + 1].rbase
+__device__ __forceinline__ int seg_job_of(const SegPass *jobs, int J, uint64_t r) {
+    int lo = 0, hi = J;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].rbase <= r) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kSortBlock) void seg_hist(const SegPass *jobs, int J,
+                                                        uint32_t *counts) {
+    __shared__ uint32_t s_h[kSortNW][kRadix];
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    for (uint32_t d = tid; d < kSortNW * kRadix; d += kSortBlock) (&s_h[0][0])[d] = 0;
+    __syncthreads();
+    const uint64_t gr = blockIdx.x;
+    const SegPass &p = jobs[seg_job_of(jobs, J, gr)];
+    const uint64_t r0 = (gr - p.rbase) * p.range, r1 = min(p.n, r0 + p.range);
+    for (uint64_t t0 = r0; t0 < r1; t0 += kSortTile) {
+        uint32_t d[kSortIPT];
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            const uint64_t i = sort_item(t0, wave, it, lane);
+            d[it] = i < r1 ? (uint32_t)(p.kin[i] >> p.shift) & (kRadix - 1) : 0u;
+        }
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            const bool valid = sort_item(t0, wave, it, lane) < r1;
+            const uint64_t peers = match_digit(d[it], valid);
+            if (valid && lane == __builtin_ctzll(peers)) s_h[wave][d[it]] += (uint32_t)__popcll(peers);
+        }
+    }
+    __syncthreads();
+    for (uint32_t dd = tid; dd < kRadix; dd += kSortBlock) {
+        uint32_t sum = 0;
+        for (int ww = 0; ww < kSortNW; ++ww) sum += s_h[ww][dd];
+        counts[gr * kRadix + dd] = sum;
+    }
+}
+
+// In place: counts[range][d] -> the job-relative output position of the
+// range's first pair of digit d (pairs of smaller digits, then those of
+// digit d in earlier ranges).
+constexpr int kSegParts = 4;
+__global__ __launch_bounds__(kRadix * kSegParts) void seg_offsets(const SegPass *jobs,
+                                                                   uint32_t *counts) {
+    constexpr int kPer = kRadix / dev::kWave;
+    __shared__ uint32_t s_part[kSegParts][kRadix];
+    __shared__ uint32_t s_base[kRadix];
+    const SegPass &p = jobs[blockIdx.x];
+    const int d = threadIdx.x % kRadix, part = threadIdx.x / kRadix;
+    const uint32_t R = p.nranges;
+    const uint32_t per = (R + kSegParts - 1) / kSegParts;
+    const uint32_t a = min(R, (uint32_t)part * per), b = min(R, a + per);
+    uint32_t *c = counts + p.rbase * kRadix;
+    uint32_t sum = 0;
+    for (uint32_t r = a; r < b; ++r) sum += c[(size_t)r * kRadix + d];
+    s_part[part][d] = sum;
+    __syncthreads();
+    if (part == 0) {
+        uint32_t tot = 0;
+#pragma unroll
+        for (int x = 0; x < kSegParts; ++x) tot += s_part[x][d];
+        s_base[d] = tot;
+    }
+    __syncthreads();
+    if (threadIdx.x < dev::kWave) {  // digit totals -> digit bases
+        const int lane = threadIdx.x;
+        uint32_t v[kPer], loc = 0;
+#pragma unroll
+        for (int x = 0; x < kPer; ++x) {
+            v[x] = s_base[lane * kPer + x];
+            loc += v[x];
+        }
+        uint32_t run = dev::wave_inclusive_sum(loc) - loc;
+#pragma unroll
+        for (int x = 0; x < kPer; ++x) {
+            s_base[lane * kPer + x] = run;
+            run += v[x];
+        }
+    }
+    __syncthreads();
+    uint32_t run = s_base[d];
+    for (int x = 0; x < part; ++x) run += s_part[x][d];
+    for (uint32_t r = a; r < b; ++r) {
+        const uint32_t v = c[(size_t)r * kRadix + d];
+        c[(size_t)r * kRadix + d] = run;
+        run += v;
+    }
+}
+
+__global__ __launch_bounds__(kSortBlock) void seg_scatter(const SegPass *jobs, int J,
+                                                           const uint32_t *offs) {
+    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_wh[kSortNW][kRadix];
+    const int tid = threadIdx.x, wave = tid / dev::kWave, lane = tid % dev::kWave;
+    const uint64_t gr = blockIdx.x;
+    const SegPass &p = jobs[seg_job_of(jobs, J, gr)];
+    for (uint32_t d = tid; d < kRadix; d += kSortBlock) s_run[d] = offs[gr * kRadix + d];
+    const uint64_t r0 = (gr - p.rbase) * p.range, r1 = min(p.n, r0 + p.range);
+    const uint64_t lt = (1ull << lane) - 1ull;
+    __syncthreads();
+    for (uint64_t t0 = r0; t0 < r1; t0 += kSortTile) {
+        uint64_t key[kSortIPT];
+        uint32_t val[kSortIPT], rank[kSortIPT];
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            const uint64_t i = sort_item(t0, wave, it, lane);
+            key[it] = i < r1 ? p.kin[i] : 0ull;
+            val[it] = i < r1 ? p.vin[i] : 0u;
+        }
+        for (uint32_t d = lane; d < kRadix; d += dev::kWave) s_wh[wave][d] = 0;
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            const bool valid = sort_item(t0, wave, it, lane) < r1;
+            const uint32_t d = (uint32_t)(key[it] >> p.shift) & (kRadix - 1);
+            const uint64_t peers = match_digit(d, valid);
+            const uint32_t before = valid ? s_wh[wave][d] : 0u;
+            rank[it] = before + (uint32_t)__popcll(peers & lt);
+            if (valid && lane == __builtin_ctzll(peers)) s_wh[wave][d] = before + (uint32_t)__popcll(peers);
+        }
+        __syncthreads();
+        for (uint32_t d = tid; d < kRadix; d += kSortBlock) {
+            uint32_t run = s_run[d];
+            for (int ww = 0; ww < kSortNW; ++ww) {
+                const uint32_t c = s_wh[ww][d];
+                s_wh[ww][d] = run;
+                run += c;
+            }
+            s_run[d] = run;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < kSortIPT; ++it) {
+            if (sort_item(t0, wave, it, lane) < r1) {
+                const uint32_t d = (uint32_t)(key[it] >> p.shift) & (kRadix - 1);
+                const uint32_t pos = s_wh[wave][d] + rank[it];
+                p.kout[pos] = key[it];
+                p.vout[pos] = val[it];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Keys of one column group for every job: key[i] = the group's columns of
+// row perm[i] (or of row i, when perm is null: the first group, which also
+// writes the identity permutation).  One y-row of the grid per job.
+struct SegPack {
+    const uint32_t *col[TID_MAX_COLS];
+    int32_t shift[TID_MAX_COLS];
+    int32_t ncols;
+    const uint32_t *perm;
+    uint32_t *iota;
+    uint64_t *key;
+    uint64_t n;
+};
+
+__global__ void seg_pack(const SegPack *jobs) {
+    const SegPack &p = jobs[blockIdx.y];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+        const uint64_t r = p.perm ? p.perm[i] : i;
+        if (!p.perm) p.iota[i] = (uint32_t)i;
+        uint64_t k = 0;
+        for (int c = 0; c < p.ncols; ++c) k |= (uint64_t)p.col[c][r] << p.shift[c];
+        p.key[i] = k;
+    }
+}
+
+// rows of every job's input in the order of its permutation
+struct SegGather {
+    const uint32_t *in[TID_MAX_COLS];
+    uint32_t *out[TID_MAX_COLS];
+    int32_t ncols;
+    const uint32_t *perm;
+    uint64_t n;
+};
+
+__global__ void seg_gather(const SegGather *jobs) {
+    const SegGather &p = jobs[blockIdx.y];
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p.n; i += stride) {
+        const uint32_t r = p.perm[i];
+        for (int c = 0; c < p.ncols; ++c) p.out[c][i] = p.in[c][r];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
 
@@ -546,6 +759,204 @@ std::unique_ptr<tid_table> sort_rows(tid_ctx *ctx, const tid_table *t, uint64_t 
     set_count(ctx, sorted.get(), n);
     if (!distinct) return sorted;
     return unique_sorted(ctx, sorted.get(), n);
+}
+
+// Row sorts of many tables in shared launches (see the batched kernels
+// above).  Every table needs its column bounds on the host and fewer than
+// 2^32 rows; each output table is allocated by the caller with n rows.  The
+// job tables, key arrays and permutations go into `keep` / `host_keep`,
+// which the caller holds until the stream has passed these launches.
+void sort_rows_batched(tid_ctx *ctx, const std::vector<RowSortJob> &jobs,
+                       std::vector<DevBuf> &keep, std::vector<std::vector<char>> &host_keep) {
+    if (jobs.empty()) return;
+    constexpr uint64_t kChunkRows = 1ull << 27;  // rows per arena fill
+    struct Plan {
+        std::vector<std::pair<int, int>> groups;  // [first, last) columns, most significant first
+        std::vector<int> width;
+    };
+    auto upload = [&](const void *data, size_t bytes) -> const void * {
+        host_keep.emplace_back(reinterpret_cast<const char *>(data),
+                               reinterpret_cast<const char *>(data) + bytes);
+        keep.emplace_back(ctx, bytes);
+        TID_HIP(hipMemcpyAsync(keep.back().get(), host_keep.back().data(), bytes,
+                               hipMemcpyHostToDevice, ctx->stream));
+        return keep.back().get();
+    };
+    // chunks of jobs in order, each within kChunkRows rows (a larger job alone)
+    size_t j0 = 0;
+    uint64_t most = 0;
+    std::vector<std::pair<size_t, size_t>> chunks;
+    while (j0 < jobs.size()) {
+        size_t j1 = j0;
+        uint64_t rows = 0;
+        while (j1 < jobs.size() && (j1 == j0 || rows + jobs[j1].n <= kChunkRows))
+            rows += jobs[j1++].n;
+        chunks.emplace_back(j0, j1);
+        most = std::max(most, rows);
+        j0 = j1;
+    }
+    // one arena for every chunk (stream order keeps the fills apart): per
+    // job two key and two value arrays
+    DevBuf arena(ctx, std::max<uint64_t>(most, 1) * 24 + 4 * kAlign * jobs.size());
+    char *const base = arena.get<char>();
+    for (const auto &ch : chunks) {
+        const int J = (int)(ch.second - ch.first);
+        std::vector<Plan> plans(J);
+        std::vector<uint64_t *> ka(J), kb(J);
+        std::vector<uint32_t *> va(J), vb(J);
+        size_t at = 0;
+        int max_groups = 0;
+        for (int j = 0; j < J; ++j) {
+            const RowSortJob &job = jobs[ch.first + j];
+            const tid_table *t = job.in;
+            TID_REQUIRE(t->maxv_known && job.n < (1ull << 32) && t->ncols > 0, TID_E_INTERNAL,
+                        "batched sort: bad job");
+            Plan &pl = plans[j];
+            int c = 0;
+            while (c < t->ncols) {
+                int w = 0, e = c;
+                while (e < t->ncols && w + bit_width(t->maxv[e]) <= 64) w += bit_width(t->maxv[e++]);
+                if (e == c) e = c + 1;
+                pl.groups.emplace_back(c, e);
+                pl.width.push_back(w);
+                c = e;
+            }
+            max_groups = std::max(max_groups, (int)pl.groups.size());
+            ka[j] = reinterpret_cast<uint64_t *>(base + at);
+            at += align_up(job.n * 8);
+            kb[j] = reinterpret_cast<uint64_t *>(base + at);
+            at += align_up(job.n * 8);
+            va[j] = reinterpret_cast<uint32_t *>(base + at);
+            at += align_up(job.n * 4);
+            vb[j] = reinterpret_cast<uint32_t *>(base + at);
+            at += align_up(job.n * 4);
+        }
+        // the whole schedule on the host: per step (column group, least
+        // significant first) the packs, then its digit passes
+        std::vector<SegPack> packs;
+        std::vector<std::pair<size_t, size_t>> step_packs;  // [first, last) in packs
+        std::vector<SegPass> passes;
+        struct PassLaunch { size_t first; int J; uint64_t ranges; };
+        std::vector<std::vector<PassLaunch>> step_passes;
+        std::vector<int> cur(J, 0);  // 0: (ka, va) hold the current pairs, 1: (kb, vb)
+        uint64_t most_ranges = 0;
+        for (int st = 0; st < max_groups; ++st) {
+            const size_t p0 = packs.size();
+            std::vector<int> npass(J, 0);
+            for (int j = 0; j < J; ++j) {
+                const Plan &pl = plans[j];
+                const int G = (int)pl.groups.size();
+                if (st >= G) continue;
+                const int g = G - 1 - st;
+                const int w = pl.width[g];
+                if (w == 0 && st > 0) continue;  // all-zero columns order nothing
+                const tid_table *t = jobs[ch.first + j].in;
+                SegPack pk{};
+                int shift = 0;
+                for (int x = pl.groups[g].second - 1; x >= pl.groups[g].first; --x) {
+                    pk.col[pk.ncols] = t->col[x];
+                    pk.shift[pk.ncols] = shift;
+                    ++pk.ncols;
+                    shift += bit_width(t->maxv[x]);
+                }
+                pk.perm = st == 0 ? nullptr : (cur[j] ? vb[j] : va[j]);
+                pk.iota = cur[j] ? vb[j] : va[j];
+                pk.key = cur[j] ? kb[j] : ka[j];
+                pk.n = jobs[ch.first + j].n;
+                packs.push_back(pk);
+                npass[j] = (w + kRadixBits - 1) / kRadixBits;
+            }
+            step_packs.emplace_back(p0, packs.size());
+            std::vector<PassLaunch> pl_launch;
+            for (int pass = 0;; ++pass) {
+                uint64_t active = 0;
+                for (int j = 0; j < J; ++j)
+                    if (npass[j] > pass) active += jobs[ch.first + j].n;
+                if (active == 0) break;
+                const uint64_t tile = kSortTile;
+                const uint64_t g_range =
+                    std::max<uint64_t>(tile, (active / 4096 + tile - 1) / tile * tile);
+                PassLaunch L{passes.size(), 0, 0};
+                for (int j = 0; j < J; ++j) {
+                    if (npass[j] <= pass) continue;
+                    const uint64_t n = jobs[ch.first + j].n;
+                    SegPass sp{};
+                    sp.kin = cur[j] ? kb[j] : ka[j];
+                    sp.vin = cur[j] ? vb[j] : va[j];
+                    sp.kout = cur[j] ? ka[j] : kb[j];
+                    sp.vout = cur[j] ? va[j] : vb[j];
+                    sp.n = n;
+                    sp.range = std::max<uint64_t>(g_range, ((n + 255) / 256 + tile - 1) / tile * tile);
+                    sp.nranges = (uint32_t)((n + sp.range - 1) / sp.range);
+                    sp.rbase = L.ranges;
+                    sp.shift = pass * kRadixBits;
+                    L.ranges += sp.nranges;
+                    ++L.J;
+                    passes.push_back(sp);
+                    cur[j] ^= 1;
+                }
+                most_ranges = std::max(most_ranges, L.ranges);
+                pl_launch.push_back(L);
+            }
+            step_passes.push_back(std::move(pl_launch));
+        }
+        std::vector<SegGather> gathers(J);
+        uint64_t most_n = 0;
+        for (int j = 0; j < J; ++j) {
+            const RowSortJob &job = jobs[ch.first + j];
+            SegGather &g = gathers[j];
+            g.ncols = job.in->ncols;
+            for (int c = 0; c < g.ncols; ++c) {
+                g.in[c] = job.in->col[c];
+                g.out[c] = job.out->col[c];
+            }
+            g.perm = cur[j] ? vb[j] : va[j];
+            g.n = job.n;
+            most_n = std::max(most_n, job.n);
+        }
+        TID_REQUIRE(!packs.empty(), TID_E_INTERNAL, "batched sort: nothing to pack");
+        const SegPack *d_pack = reinterpret_cast<const SegPack *>(
+            upload(packs.data(), packs.size() * sizeof(SegPack)));
+        const SegPass *d_pass = passes.empty() ? nullptr
+                                               : reinterpret_cast<const SegPass *>(upload(
+                                                     passes.data(), passes.size() * sizeof(SegPass)));
+        const SegGather *d_gather = reinterpret_cast<const SegGather *>(
+            upload(gathers.data(), gathers.size() * sizeof(SegGather)));
+        keep.emplace_back(ctx, std::max<uint64_t>(most_ranges, 1) * kRadix * sizeof(uint32_t));
+        uint32_t *counts = keep.back().get<uint32_t>();
+        auto grid_x = [](uint64_t n) {
+            return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 1024));
+        };
+        for (int st = 0; st < max_groups; ++st) {
+            const size_t a = step_packs[st].first, b = step_packs[st].second;
+            uint64_t mn = 0;
+            for (size_t x = a; x < b; ++x) mn = std::max(mn, packs[x].n);
+            for (size_t y0 = a; y0 < b; y0 += 65535) {
+                const unsigned gy = (unsigned)std::min<size_t>(65535, b - y0);
+                hipLaunchKernelGGL(seg_pack, dim3(grid_x(mn), gy), dim3(256), 0, ctx->stream,
+                                   d_pack + y0);
+                TID_HIP(hipGetLastError());
+            }
+            for (const PassLaunch &L : step_passes[st]) {
+                hipLaunchKernelGGL(seg_hist, dim3((unsigned)L.ranges), dim3(kSortBlock), 0,
+                                   ctx->stream, d_pass + L.first, L.J, counts);
+                TID_HIP(hipGetLastError());
+                hipLaunchKernelGGL(seg_offsets, dim3((unsigned)L.J), dim3(kRadix * kSegParts), 0,
+                                   ctx->stream, d_pass + L.first, counts);
+                TID_HIP(hipGetLastError());
+                hipLaunchKernelGGL(seg_scatter, dim3((unsigned)L.ranges), dim3(kSortBlock), 0,
+                                   ctx->stream, d_pass + L.first, L.J, (const uint32_t *)counts);
+                TID_HIP(hipGetLastError());
+            }
+        }
+        for (int y0 = 0; y0 < J; y0 += 65535) {
+            const unsigned gy = (unsigned)std::min(65535, J - y0);
+            hipLaunchKernelGGL(seg_gather, dim3(grid_x(most_n), gy), dim3(256), 0, ctx->stream,
+                               d_gather + y0);
+            TID_HIP(hipGetLastError());
+        }
+    }
+    keep.push_back(std::move(arena));
 }
 
 std::unique_ptr<tid_table> sort_table(tid_ctx *ctx, const tid_table *t, int distinct) {

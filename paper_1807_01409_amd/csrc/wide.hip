@@ -11,7 +11,10 @@
 //   - count pass -> column-wise exclusive scan of the (sub-range x pattern)
 //     count matrix -> write pass, which places every match at its pattern's
 //     offset for the sub-range plus its rank: ascending triple position per
-//     pattern, as a single-pattern scan gives.
+//     pattern, as a single-pattern scan gives;
+//   - a pass reads the TripleID array, or segments of (subject, object)
+//     columns, each segment the rows of one predicate in triple order (a
+//     slice of the predicate-partitioned layout, or of a temporary slice).
 // The graph is read twice per pass; the work per triple is the size of its
 // predicate's bucket, and a wave steps through the longest bucket among its
 // lanes.  A predicate that many patterns of one pass share is therefore
@@ -49,11 +52,20 @@ struct WideOut {
     uint64_t cap;
 };
 
+// One predicate's rows in a segment pass: `len` rows of the subject and object
+// columns from `pbase` on, all with predicate p, at virtual position vbase
+// (each segment starts on a walk unit, so a unit never spans two segments).
+struct WideSeg {
+    uint64_t vbase, pbase;
+    uint32_t len, p;
+};
+
 struct WideArgs {
     const uint32_t *g;          // AoS triples (graph pass)
-    const uint32_t *ss, *so;    // slice pass: subject and object columns ...
-    uint32_t sp;                // ... of the rows whose predicate is sp
-    uint64_t n;
+    const uint32_t *ss, *so;    // segment pass: subject and object columns
+    const WideSeg *segs;        // segment pass: nseg segments by ascending vbase
+    uint32_t nseg;
+    uint64_t n;                 // triples (graph pass) or virtual positions (segment pass)
     const WidePat *pats;      // k
     const uint32_t *bucket;   // kWidePreds words: start << 12 | len
     const uint16_t *ids;      // k pattern ids grouped by predicate
@@ -111,21 +123,17 @@ __device__ __forceinline__ void wide_setup(const WideArgs &a, WidePat *s_pat, ui
 // wave's running count of that pattern (s_run) advances by the number of
 // lanes matching it in the same step; the write pass (WRITE) also stores the
 // binding at that running count plus the lane's rank among them.
-// triple i of the pass's source
-template <bool SLICE>
-__device__ __forceinline__ WTri wide_load(const WideArgs &a, uint64_t i) {
-    if (SLICE) {
-        WTri t;
-        t.v[0] = a.ss[i];
-        t.v[1] = a.sp;
-        t.v[2] = a.so[i];
-        return t;
+constexpr uint64_t kWideUnit = (uint64_t)dev::kWave * kWideIPT;  // triples a wave loads per step
+
+// the last segment whose virtual base is at most v
+__device__ __forceinline__ uint32_t wide_seg_of(const WideArgs &a, uint64_t v) {
+    uint32_t lo = 0, hi = a.nseg;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (a.segs[mid].vbase <= v) lo = mid;
+        else hi = mid;
     }
-    WTri t;  // the graph is streamed once per pass: non-temporal loads
-    t.v[0] = __builtin_nontemporal_load(a.g + 3 * i);
-    t.v[1] = __builtin_nontemporal_load(a.g + 3 * i + 1);
-    t.v[2] = __builtin_nontemporal_load(a.g + 3 * i + 2);
-    return t;
+    return lo;
 }
 
 template <bool WRITE, bool SLICE>
@@ -135,13 +143,38 @@ __device__ __forceinline__ void wide_walk(const WideArgs &a, const WidePat *s_pa
                                           uint32_t *flags) {
     const int lane = dev::lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
-    for (uint64_t t0 = r0; t0 < r1; t0 += (uint64_t)dev::kWave * kWideIPT) {
+    // segment pass: the segment holding the current step (steps only move forward)
+    uint32_t sg = SLICE && r0 < r1 ? wide_seg_of(a, r0) : 0u;
+    for (uint64_t t0 = r0; t0 < r1; t0 += kWideUnit) {
         WTri t[kWideIPT];
+        if (SLICE) {
+            while (sg + 1 < a.nseg && a.segs[sg + 1].vbase <= t0) ++sg;
+            const WideSeg sgm = a.segs[sg];
+            const uint64_t off = t0 - sgm.vbase;
 #pragma unroll
-        for (int it = 0; it < kWideIPT; ++it) {
-            const uint64_t i = t0 + (uint64_t)it * dev::kWave + lane;
-            if (i < r1) t[it] = wide_load<SLICE>(a, i);
-            else t[it].v[0] = t[it].v[1] = t[it].v[2] = 0;
+            for (int it = 0; it < kWideIPT; ++it) {
+                const uint64_t l = off + (uint64_t)it * dev::kWave + lane;
+                if (l < sgm.len) {
+                    t[it].v[0] = __builtin_nontemporal_load(a.ss + sgm.pbase + l);
+                    t[it].v[1] = sgm.p;
+                    t[it].v[2] = __builtin_nontemporal_load(a.so + sgm.pbase + l);
+                } else {
+                    t[it].v[0] = t[it].v[1] = t[it].v[2] = 0;
+                }
+            }
+        } else {
+            // the graph is streamed once per pass: non-temporal loads
+#pragma unroll
+            for (int it = 0; it < kWideIPT; ++it) {
+                const uint64_t i = t0 + (uint64_t)it * dev::kWave + lane;
+                if (i < r1) {
+                    t[it].v[0] = __builtin_nontemporal_load(a.g + 3 * i);
+                    t[it].v[1] = __builtin_nontemporal_load(a.g + 3 * i + 1);
+                    t[it].v[2] = __builtin_nontemporal_load(a.g + 3 * i + 2);
+                } else {
+                    t[it].v[0] = t[it].v[1] = t[it].v[2] = 0;
+                }
+            }
         }
 #pragma unroll
         for (int it = 0; it < kWideIPT; ++it) {
@@ -308,12 +341,13 @@ static size_t wide_lds_bytes(int k) {
            4 * (size_t)kWideNW * (size_t)k;
 }
 
-// What one pass reads: the graph, or the (s, o) slice of one predicate.
+// What one pass reads: the graph, or segments of (s, o) columns, each the
+// rows of one predicate in triple order (segs: vbase is filled in here).
 struct WideSource {
     const uint32_t *g = nullptr;
     const uint32_t *s = nullptr, *o = nullptr;
-    uint32_t p = 0;
-    uint64_t n = 0;
+    std::vector<WideSeg> segs;
+    uint64_t n = 0;  // graph pass: triples
 };
 
 // Allow up to 160 KB of dynamic LDS per workgroup: once per process, also
@@ -330,18 +364,37 @@ static void set_wide_lds_limit() {
 }
 
 // One pass for k <= kWideMax eligible patterns into preallocated tables.  In
-// a slice pass every pattern has the slice's predicate.
-static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pats, int k,
+// a segment pass every pattern's predicate is one of the segments'.
+static void wide_pass(tid_ctx *ctx, WideSource src, const tid_pattern *pats, int k,
                       tid_table *const *outs, const ScanFilter *filters) {
     TID_REQUIRE(k >= 1 && k <= kWideMax, TID_E_INTERNAL, "wide pass: bad pattern count");
     const bool slice = src.g == nullptr;
+    if (slice) {
+        // virtual positions: every segment starts on a walk unit
+        std::vector<char> seg_pred(kWidePreds, 0);
+        uint64_t v = 0;
+        for (WideSeg &sg : src.segs) {
+            TID_REQUIRE(sg.p > 0 && sg.p < kWidePreds && sg.len > 0, TID_E_INTERNAL,
+                        "wide pass: bad segment");
+            seg_pred[sg.p] = 1;
+            sg.vbase = v;
+            v += (sg.len + kWideUnit - 1) / kWideUnit * kWideUnit;
+        }
+        src.n = v;
+        for (int j = 0; j < k; ++j)
+            TID_REQUIRE(wide_eligible(pats[j]) && seg_pred[pats[j].p], TID_E_INTERNAL,
+                        "wide pass: pattern without segment");
+        if (v == 0) {
+            for (int j = 0; j < k; ++j) set_count(ctx, outs[j], 0);
+            return;
+        }
+    }
     std::vector<WidePat> wp(k);
     std::vector<WideOut> wo(k);
     std::vector<uint64_t *> wc(k);
     std::vector<std::vector<uint16_t>> by_pred(kWidePreds);
     for (int j = 0; j < k; ++j) {
-        TID_REQUIRE(wide_eligible(pats[j]) && (!slice || pats[j].p == src.p), TID_E_INTERNAL,
-                    "wide pass: pattern not eligible");
+        TID_REQUIRE(wide_eligible(pats[j]), TID_E_INTERNAL, "wide pass: pattern not eligible");
         wp[j] = compile_wide(pats[j]);
         if (filters && filters[j].pos >= 0) {
             wp[j].flags |= kWideFiltered | ((uint32_t)filters[j].pos << 15);
@@ -362,10 +415,12 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
         ids.insert(ids.end(), by_pred[p].begin(), by_pred[p].end());
     }
     // tables of constants, in one device block
+    const size_t nseg = src.segs.size();
     const size_t b_pats = align_up(sizeof(WidePat) * k), b_bucket = align_up(4 * kWidePreds),
                  b_ids = align_up(2 * (size_t)k), b_outs = align_up(sizeof(WideOut) * k),
-                 b_cnts = align_up(8 * (size_t)k), b_tot = align_up(8 * (size_t)k);
-    const size_t consts = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot;
+                 b_cnts = align_up(8 * (size_t)k), b_tot = align_up(8 * (size_t)k),
+                 b_segs = align_up(sizeof(WideSeg) * std::max<size_t>(nseg, 1));
+    const size_t consts = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot + b_segs;
     std::vector<char> host(consts, 0);
     char *h = host.data();
     std::memcpy(h, wp.data(), sizeof(WidePat) * k);
@@ -373,6 +428,8 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
     std::memcpy(h + b_pats + b_bucket, ids.data(), 2 * (size_t)k);
     std::memcpy(h + b_pats + b_bucket + b_ids, wo.data(), sizeof(WideOut) * k);
     std::memcpy(h + b_pats + b_bucket + b_ids + b_outs, wc.data(), 8 * (size_t)k);
+    const size_t at_segs = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot;
+    if (nseg) std::memcpy(h + at_segs, src.segs.data(), sizeof(WideSeg) * nseg);
     DevBuf dconst(ctx, consts);
     TID_HIP(hipMemcpyAsync(dconst.get(), host.data(), consts, hipMemcpyHostToDevice, ctx->stream));
     char *d = dconst.get<char>();
@@ -384,7 +441,7 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
     else set_wide_lds_limit<false>();
     const int per_cu = resident_blocks(write_fn, kWideBlock, lds);
     const uint64_t waves = (uint64_t)per_cu * device_cus(ctx) * kWideNW;
-    const uint64_t unit = (uint64_t)dev::kWave * kWideIPT;
+    const uint64_t unit = kWideUnit;
     const uint64_t units = (src.n + unit - 1) / unit;
     uint64_t W = std::max<uint64_t>(1, std::min(units, waves));
     const uint64_t sub = (units + W - 1) / W * unit;
@@ -395,7 +452,8 @@ static void wide_pass(tid_ctx *ctx, const WideSource &src, const tid_pattern *pa
     a.g = src.g;
     a.ss = src.s;
     a.so = src.o;
-    a.sp = src.p;
+    a.segs = reinterpret_cast<const WideSeg *>(d + at_segs);
+    a.nseg = (uint32_t)nseg;
     a.n = src.n;
     a.pats = reinterpret_cast<const WidePat *>(d);
     a.bucket = reinterpret_cast<const uint32_t *>(d + b_pats);
@@ -474,8 +532,7 @@ void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
         WideSource part;
         part.s = slices[i]->col[0];
         part.o = slices[i]->col[1];
-        part.p = p;
-        part.n = slices[i]->cap;  // the histogram count is exact
+        part.segs.push_back(WideSeg{0, 0, (uint32_t)slices[i]->cap, p});  // the count is exact
         std::vector<tid_pattern> sp;
         std::vector<tid_table *> st;
         std::vector<ScanFilter> sf;
@@ -486,6 +543,51 @@ void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
         }
         wide_pass(ctx, part, sp.data(), (int)sp.size(), st.data(), sf.data());
     }
+}
+
+// One segment pass over the predicate-partitioned layout for k <= kWideMax
+// eligible patterns: only the slices of the patterns' predicates are read (8 B
+// per row, once to count and once to write) instead of the whole TripleID
+// array.  A slice keeps triple order, so every table comes out as the graph
+// pass would write it.
+void run_wide_parts(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
+                    tid_table *const *outs, const ScanFilter *filters) {
+    TID_REQUIRE(g->partitioned && !g->cdf[1].empty(), TID_E_INTERNAL,
+                "segment pass: the graph has no partitioned layout");
+    const auto &cdf = g->cdf[1];
+    const uint64_t last = cdf.size() - 1;
+    auto slice_of = [&](uint32_t p, uint64_t &a, uint64_t &b) {
+        a = cdf[std::min<uint64_t>(p, last)];
+        b = cdf[std::min<uint64_t>((uint64_t)p + 1, last)];
+    };
+    std::vector<char> used(kWidePreds, 0);
+    std::vector<tid_pattern> sp;
+    std::vector<tid_table *> st;
+    std::vector<ScanFilter> sf;
+    for (int j = 0; j < k; ++j) {
+        TID_REQUIRE(wide_eligible(pats[j]), TID_E_INTERNAL, "segment pass: pattern not eligible");
+        uint64_t a, b;
+        slice_of(pats[j].p, a, b);
+        if (b == a) {  // no triple has the predicate
+            set_count(ctx, outs[j], 0);
+            continue;
+        }
+        used[pats[j].p] = 1;
+        sp.push_back(pats[j]);
+        st.push_back(outs[j]);
+        sf.push_back(filters ? filters[j] : ScanFilter{});
+    }
+    if (sp.empty()) return;
+    WideSource src;
+    src.s = g->part_s.get<const uint32_t>();
+    src.o = g->part_o.get<const uint32_t>();
+    for (uint32_t p = 1; p < kWidePreds; ++p) {
+        if (!used[p]) continue;
+        uint64_t a, b;
+        slice_of(p, a, b);
+        src.segs.push_back(WideSeg{0, a, (uint32_t)(b - a), p});
+    }
+    wide_pass(ctx, std::move(src), sp.data(), (int)sp.size(), st.data(), sf.data());
 }
 
 }  // namespace tid

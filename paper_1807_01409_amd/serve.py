@@ -51,12 +51,17 @@ class ServeStats:
 
 
 class Server:
-    """Workers share one resident graph (read only) loaded by the first context."""
+    """Workers share one resident graph (read only) loaded by the first context.
+    layout: also build the graph's predicate-partitioned columns, so that the
+    patterns with a constant predicate read only their predicates' slices."""
 
     def __init__(self, triples, workers: int = 2, budget_bytes: int = 64 << 30,
-                 max_batch: int = 256, allocator: str = "pool", device: int = 0):
+                 max_batch: int = 256, allocator: str = "pool", device: int = 0,
+                 layout: bool = True):
         self.ctxs = [Context(device, allocator=allocator) for _ in range(workers)]
         self.graph: Graph = self.ctxs[0].load(triples)
+        if layout:
+            self.graph.partition(True)
         self.budget = int(budget_bytes)
         self.max_batch = int(max_batch)
         self._jobs: "queue.Queue" = queue.Queue()

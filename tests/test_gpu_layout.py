@@ -52,3 +52,51 @@ def test_partitioned_scans(ctx, graphs, name, n):
         ctx.set_option("layout", 1)
     G.partition(False)
     G.free()
+
+
+def _slice_patterns(g):
+    """Constant-predicate patterns of every kind over the small graph's
+    predicates, plus predicates without triples (one of them the largest
+    bucketable id) and one id past the bucket table."""
+    hot_o = int(np.bincount(g[:, 2]).argmax())
+    s0 = int(g[0, 0])
+    out = []
+    for p in list(range(1, 51)) + [60, 4095, 4096]:
+        out += [Pattern(0, p, 0, 0, -1, 1),                 # whole slice (s, o)
+                Pattern(0, p, 0, -1, -1, 0),                # whole slice, o only
+                Pattern(0, p, 0, -1, -1, -1),               # whole slice, count only
+                Pattern(0, p, 0, 0, -1, 0),                 # s == o
+                Pattern(0, p, hot_o, 0, -1, -1),            # constant object
+                Pattern(s0, p, 0, -1, -1, 0),               # constant subject
+                Pattern(0, p, 0, 0, -1, 1, range_pos=2, lo=5, hi=400)]
+    return out
+
+
+@pytest.mark.parametrize("semijoin", [1, 0])
+def test_segment_passes_and_whole_slices(ctx, graphs, semijoin):
+    """A batch of single-scan plans on a partitioned graph: whole-slice
+    patterns become tables over the slices (no pass), the other constant-
+    predicate patterns go through one segment pass over their predicates'
+    slices, an id past the bucket table through a graph pass.  Every result
+    equals the oracle's and the same batch on the TripleID array alone."""
+    g = graphs("small", 100_000)
+    pats = _slice_patterns(g)
+    plans = [Plan().scan(p) for p in pats]
+    want = [oracle.query(g, pl).rows for pl in plans]
+    G = ctx.load(g)
+    ctx.set_option("semijoin", semijoin)
+    try:
+        aos = [t.to_numpy() for t in ctx.query_batch(G, plans)]
+        G.partition(True)
+        got = [t.to_numpy() for t in ctx.query_batch(G, plans)]
+        for p, a, b, w in zip(pats, aos, got, want):
+            assert np.array_equal(a, w), p
+            assert np.array_equal(b, w), p
+        # joins over whole-slice tables and segment-pass tables
+        n_ = {}
+        plan = (Plan().scan(pat("?s 3 ?a", n_)).scan(pat("?s 11 ?b", n_)).join(n_["?s"])
+                .scan(pat(f"?b 7 {int(g[5, 2])}", n_)).join(n_["?b"]))
+        assert np.array_equal(ctx.query(G, plan).to_numpy(), oracle.query(g, plan).rows)
+    finally:
+        ctx.set_option("semijoin", 1)
+        G.free()

@@ -37,13 +37,33 @@ def test_batch_mix_equals_alone_and_oracle(ctx, mix, mix_oracle):
         assert np.array_equal(t.to_numpy(), o)
 
 
+@pytest.mark.parametrize("semijoin", [1, 0])
+def test_batch_mix_partitioned_equals_oracle(ctx, mix, mix_oracle, semijoin):
+    """With the predicate-partitioned layout built, the mix's patterns read
+    only their slices (whole-slice patterns read nothing, the others go
+    through segment passes); every batched and alone result equals the
+    oracle's."""
+    g, plans, _ = mix
+    G = ctx.load(g)
+    G.partition(True)
+    ctx.set_option("semijoin", semijoin)
+    try:
+        for t, o in zip(ctx.query_batch(G, plans), mix_oracle):
+            assert np.array_equal(t.to_numpy(), o)
+        for p, o in zip(plans[:24], mix_oracle[:24]):
+            assert np.array_equal(ctx.query(G, p).to_numpy(), o)
+    finally:
+        ctx.set_option("semijoin", 1)
+        G.free()
+
+
 @pytest.mark.parametrize("budget", [64 << 30, 8 << 20])
 def test_served_mix_equals_alone_and_oracle(ctx, mix, mix_oracle, budget):
     from paper_1807_01409_amd.serve import Request, Server
     g, plans, infos = mix
     arrivals = poisson_arrivals(240, qps=4000.0, seed=11)
     reqs = [Request(i, plans[i % len(plans)], float(arrivals[i])) for i in range(240)]
-    srv = Server(g, workers=3, budget_bytes=budget, max_batch=48)
+    srv = Server(g, workers=3, budget_bytes=budget, max_batch=48, layout=budget > (1 << 30))
     try:
         stats = srv.run(reqs, keep_results=True)
     finally:
