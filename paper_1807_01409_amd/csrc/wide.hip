@@ -24,6 +24,7 @@
 #include "compact.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 
 namespace tid {
@@ -72,7 +73,8 @@ struct WideArgs {
     const WideOut *outs;      // k
     uint64_t **counts_out;    // k device row-count words
     int k;
-    uint64_t sub;             // triples per wave sub-range
+    uint64_t sub;             // triples per wave sub-range (graph pass)
+    const uint64_t *wbound;   // segment pass: W + 1 sub-range bounds (virtual positions)
     uint32_t W;               // sub-ranges
     uint32_t *cnt;            // W x k counts, then offsets in place
     uint64_t *tot;            // k totals
@@ -247,7 +249,8 @@ __global__ __launch_bounds__(kWideBlock) void wide_count(WideArgs a, uint32_t *f
     __syncthreads();
     const uint32_t gw = blockIdx.x * kWideNW + wave;
     if (gw < a.W) {
-        const uint64_t r0 = (uint64_t)gw * a.sub, r1 = min(a.n, r0 + a.sub);
+        const uint64_t r0 = a.wbound ? a.wbound[gw] : (uint64_t)gw * a.sub;
+        const uint64_t r1 = a.wbound ? a.wbound[gw + 1] : min(a.n, r0 + a.sub);
         wide_walk<false, SLICE>(a, s_pat, s_bucket, s_ids, run, r0, r1, flags);
         for (int j = lane; j < a.k; j += dev::kWave) a.cnt[(size_t)gw * a.k + j] = run[j];
     }
@@ -300,7 +303,8 @@ __global__ __launch_bounds__(kWideBlock) void wide_write(WideArgs a, uint32_t *f
         for (int j = lane; j < a.k; j += dev::kWave) run[j] = a.cnt[(size_t)gw * a.k + j];
     __syncthreads();
     if (gw < a.W) {
-        const uint64_t r0 = (uint64_t)gw * a.sub, r1 = min(a.n, r0 + a.sub);
+        const uint64_t r0 = a.wbound ? a.wbound[gw] : (uint64_t)gw * a.sub;
+        const uint64_t r1 = a.wbound ? a.wbound[gw + 1] : min(a.n, r0 + a.sub);
         wide_walk<true, SLICE>(a, s_pat, s_bucket, s_ids, run, r0, r1, flags);
     }
 }
@@ -414,26 +418,7 @@ static void wide_pass(tid_ctx *ctx, WideSource src, const tid_pattern *pats, int
         bucket[p] = ((uint32_t)ids.size() << 12) | (uint32_t)by_pred[p].size();
         ids.insert(ids.end(), by_pred[p].begin(), by_pred[p].end());
     }
-    // tables of constants, in one device block
-    const size_t nseg = src.segs.size();
-    const size_t b_pats = align_up(sizeof(WidePat) * k), b_bucket = align_up(4 * kWidePreds),
-                 b_ids = align_up(2 * (size_t)k), b_outs = align_up(sizeof(WideOut) * k),
-                 b_cnts = align_up(8 * (size_t)k), b_tot = align_up(8 * (size_t)k),
-                 b_segs = align_up(sizeof(WideSeg) * std::max<size_t>(nseg, 1));
-    const size_t consts = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot + b_segs;
-    std::vector<char> host(consts, 0);
-    char *h = host.data();
-    std::memcpy(h, wp.data(), sizeof(WidePat) * k);
-    std::memcpy(h + b_pats, bucket.data(), 4 * kWidePreds);
-    std::memcpy(h + b_pats + b_bucket, ids.data(), 2 * (size_t)k);
-    std::memcpy(h + b_pats + b_bucket + b_ids, wo.data(), sizeof(WideOut) * k);
-    std::memcpy(h + b_pats + b_bucket + b_ids + b_outs, wc.data(), 8 * (size_t)k);
-    const size_t at_segs = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot;
-    if (nseg) std::memcpy(h + at_segs, src.segs.data(), sizeof(WideSeg) * nseg);
-    DevBuf dconst(ctx, consts);
-    TID_HIP(hipMemcpyAsync(dconst.get(), host.data(), consts, hipMemcpyHostToDevice, ctx->stream));
-    char *d = dconst.get<char>();
-
+    // the grid: one sub-range per resident wave
     const size_t lds = wide_lds_bytes(k);
     const void *count_fn = slice ? (const void *)wide_count<true> : (const void *)wide_count<false>;
     const void *write_fn = slice ? (const void *)wide_write<true> : (const void *)wide_write<false>;
@@ -445,8 +430,60 @@ static void wide_pass(tid_ctx *ctx, WideSource src, const tid_pattern *pats, int
     const uint64_t units = (src.n + unit - 1) / unit;
     uint64_t W = std::max<uint64_t>(1, std::min(units, waves));
     const uint64_t sub = (units + W - 1) / W * unit;
-    W = std::max<uint64_t>(1, (src.n + sub - 1) / sub);
+    std::vector<uint64_t> wb;  // segment pass: W + 1 sub-range bounds
+    if (slice) {
+        // A row costs its load plus one test per pattern of its predicate, so
+        // equal rows per wave would leave the waves on a predicate with many
+        // patterns far behind: bounds are placed (on walk units) at equal
+        // shares of the summed cost instead.
+        double total = 0;
+        std::vector<double> unit_cost(src.segs.size());
+        for (size_t x = 0; x < src.segs.size(); ++x) {
+            unit_cost[x] = (double)unit * (1.0 + (double)by_pred[src.segs[x].p].size());
+            total += unit_cost[x] * (double)((src.segs[x].len + unit - 1) / unit);
+        }
+        wb.assign(W + 1, src.n);
+        wb[0] = 0;
+        uint64_t w = 1;
+        double acc = 0;
+        for (size_t x = 0; x < src.segs.size() && w < W; ++x) {
+            const uint64_t su = (src.segs[x].len + unit - 1) / unit;
+            const double seg_cost = unit_cost[x] * (double)su;
+            while (w < W && acc + seg_cost >= total * (double)w / (double)W) {
+                const double need = total * (double)w / (double)W - acc;
+                const uint64_t u = std::min<uint64_t>(su, (uint64_t)std::ceil(need / unit_cost[x]));
+                wb[w] = std::max(wb[w - 1], src.segs[x].vbase + u * unit);
+                ++w;
+            }
+            acc += seg_cost;
+        }
+    } else {
+        W = std::max<uint64_t>(1, (src.n + sub - 1) / sub);
+    }
     DevBuf cnt(ctx, (size_t)W * k * 4);
+
+    // tables of constants, in one device block
+    const size_t nseg = src.segs.size();
+    const size_t b_pats = align_up(sizeof(WidePat) * k), b_bucket = align_up(4 * kWidePreds),
+                 b_ids = align_up(2 * (size_t)k), b_outs = align_up(sizeof(WideOut) * k),
+                 b_cnts = align_up(8 * (size_t)k), b_tot = align_up(8 * (size_t)k),
+                 b_segs = align_up(sizeof(WideSeg) * std::max<size_t>(nseg, 1)),
+                 b_wb = align_up(8 * std::max<size_t>(wb.size(), 1));
+    const size_t consts = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot + b_segs + b_wb;
+    std::vector<char> host(consts, 0);
+    char *h = host.data();
+    std::memcpy(h, wp.data(), sizeof(WidePat) * k);
+    std::memcpy(h + b_pats, bucket.data(), 4 * kWidePreds);
+    std::memcpy(h + b_pats + b_bucket, ids.data(), 2 * (size_t)k);
+    std::memcpy(h + b_pats + b_bucket + b_ids, wo.data(), sizeof(WideOut) * k);
+    std::memcpy(h + b_pats + b_bucket + b_ids + b_outs, wc.data(), 8 * (size_t)k);
+    const size_t at_segs = b_pats + b_bucket + b_ids + b_outs + b_cnts + b_tot;
+    if (nseg) std::memcpy(h + at_segs, src.segs.data(), sizeof(WideSeg) * nseg);
+    const size_t at_wb = at_segs + b_segs;
+    if (!wb.empty()) std::memcpy(h + at_wb, wb.data(), 8 * wb.size());
+    DevBuf dconst(ctx, consts);
+    TID_HIP(hipMemcpyAsync(dconst.get(), host.data(), consts, hipMemcpyHostToDevice, ctx->stream));
+    char *d = dconst.get<char>();
 
     WideArgs a{};
     a.g = src.g;
@@ -454,6 +491,7 @@ static void wide_pass(tid_ctx *ctx, WideSource src, const tid_pattern *pats, int
     a.so = src.o;
     a.segs = reinterpret_cast<const WideSeg *>(d + at_segs);
     a.nseg = (uint32_t)nseg;
+    a.wbound = wb.empty() ? nullptr : reinterpret_cast<const uint64_t *>(d + at_wb);
     a.n = src.n;
     a.pats = reinterpret_cast<const WidePat *>(d);
     a.bucket = reinterpret_cast<const uint32_t *>(d + b_pats);
