@@ -81,7 +81,8 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
      "scan_prefetch"      1: the scan loads tile t+1 before testing tile t;
                           0: it does not; -1: built-in default (autotuner)
      "stage_words"        LDS words per workgroup for staging compacted rows
-                          (0 = default, at most 16384)
+                          (0 = default, at most 40448; above 20352 one
+                          512-thread workgroup fits a compute unit)
      "multi_kernel"       multi-pattern scans: 0 passes of at most 4
                           patterns (unrolled), 1 one pass of up to 16
                           patterns (LDS pattern loop)      (autotuner)

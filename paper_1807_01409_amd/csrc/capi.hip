@@ -182,8 +182,8 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
             TID_REQUIRE(value >= 0, TID_E_INVALID_ARG, "wide_min must be >= 0");
             ctx->opt.wide_min = value;
         } else if (k == "stage_words") {
-            TID_REQUIRE(value >= 0 && value <= 16384, TID_E_INVALID_ARG,
-                        "stage_words must be in 0..16384");
+            TID_REQUIRE(value >= 0 && value <= 40448, TID_E_INVALID_ARG,
+                        "stage_words must be in 0..40448");
             ctx->opt.stage_words = value;
         } else {
             throw Error(TID_E_INVALID_ARG, "unknown option " + k);

@@ -68,6 +68,11 @@ template <class Src, int BLOCK, int IPT>
 __device__ __forceinline__ void tile_load(const Src &src, uint64_t t0, uint64_t r1,
                                           typename Src::Item *item) {
     const int tid = threadIdx.x;
+    if (t0 + (uint64_t)BLOCK * IPT <= r1) {  // a whole tile: no bounds tests
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) item[it] = src.load(t0 + (uint64_t)it * BLOCK + tid);
+        return;
+    }
 #pragma unroll
     for (int it = 0; it < IPT; ++it) {
         const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
@@ -84,12 +89,21 @@ __device__ __forceinline__ void tile_test(const Src &src, int k, uint64_t t0, ui
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
 #pragma unroll
     for (int j = 0; j < MAXK; ++j) mb[j] = 0;
+    if (t0 + (uint64_t)BLOCK * IPT <= r1) {  // a whole tile: every item is valid
 #pragma unroll
-    for (int it = 0; it < IPT; ++it) {
-        const bool valid = t0 + (uint64_t)it * BLOCK + tid < r1;
+        for (int it = 0; it < IPT; ++it) {
 #pragma unroll
-        for (int j = 0; j < MAXK; ++j)
-            if (j < k && valid && src.match(j, item[it])) mb[j] |= 1u << it;
+            for (int j = 0; j < MAXK; ++j)
+                if (j < k && src.match(j, item[it])) mb[j] |= 1u << it;
+        }
+    } else {
+#pragma unroll
+        for (int it = 0; it < IPT; ++it) {
+            const bool valid = t0 + (uint64_t)it * BLOCK + tid < r1;
+#pragma unroll
+            for (int j = 0; j < MAXK; ++j)
+                if (j < k && valid && src.match(j, item[it])) mb[j] |= 1u << it;
+        }
     }
 #pragma unroll
     for (int j = 0; j < MAXK; ++j) {

@@ -422,7 +422,14 @@ namespace tid {
 int resident_blocks(const void *kernel, int block, size_t lds) {
     static std::mutex mu;
     static std::map<std::pair<const void *, size_t>, int> cache;
+    static std::map<const void *, size_t> allowed;
     std::lock_guard<std::mutex> lock(mu);
+    // above 64 KB of dynamic LDS a kernel must be allowed that much first
+    // (its static LDS counts against the same 160 KB)
+    if (lds > 65536 && lds > allowed[kernel]) {
+        TID_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        allowed[kernel] = lds;
+    }
     auto key = std::make_pair(kernel, lds);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;

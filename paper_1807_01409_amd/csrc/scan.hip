@@ -294,9 +294,14 @@ DevPattern compile_pattern(const tid_pattern &p, const PatternSet *set,
     if (v[0] >= 0 && v[0] == v[1]) d.eq |= 1u;
     if (v[0] >= 0 && v[0] == v[2]) d.eq |= 2u;
     if (v[1] >= 0 && v[1] == v[2]) d.eq |= 4u;
-    d.rpos = p.range_pos;
-    d.lo = p.lo;
-    d.span = p.hi > p.lo ? p.hi - p.lo : 0u;
+    for (int x = 0; x < 3; ++x) {
+        d.rlo[x] = 0;
+        d.rmax[x] = 0xFFFFFFFFu;
+    }
+    if (p.range_pos >= 0 && p.hi > p.lo) {
+        d.rlo[p.range_pos] = p.lo;
+        d.rmax[p.range_pos] = p.hi - p.lo - 1;
+    }
     for (int j = 0; j < d.ncols; ++j) d.src[j] = src[j];
     if (set && set->pos >= 0) {
         TID_REQUIRE(set->pos <= 2 && set->n >= 1 && set->n <= kMaxSet, TID_E_INTERNAL,
@@ -306,6 +311,13 @@ DevPattern compile_pattern(const tid_pattern &p, const PatternSet *set,
         d.set_pos = set->pos;
         d.nset = set->n;
         for (int i = 0; i < set->n; ++i) d.set[i] = set->v[i];
+    }
+    if (p.range_pos >= 0 && p.hi <= p.lo) {
+        // an empty range: require ID 0 at a position without a value set,
+        // which no stored triple has (tid_load refuses ID 0)
+        const int x = d.set_pos == 0 ? 1 : 0;
+        d.key[x] = 0;
+        d.msk[x] = 0xFFFFFFFFu;
     }
     return d;
 }

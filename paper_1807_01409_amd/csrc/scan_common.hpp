@@ -25,14 +25,15 @@ struct __attribute__((packed, aligned(4))) Tri {
 };
 
 // A pattern compiled for the device: constant test by xor+mask, equalities
-// between free positions named by one variable, optional range on one
-// position as (x - lo) < span (unsigned), output column sources.
+// between free positions named by one variable, a range test on every
+// position as (x - rlo) <= rmax (unsigned; 0 and 2^32 - 1 where the pattern
+// has no range), output column sources.  A pattern with an empty range
+// requires subject 0, which no stored triple has (ID 0 is refused at load).
 struct DevPattern {
     uint32_t key[3];
     uint32_t msk[3];
     uint32_t eq;      // bit0: s==p, bit1: s==o, bit2: p==o
-    int32_t rpos;     // -1: no range
-    uint32_t lo, span;
+    uint32_t rlo[3], rmax[3];
     int32_t ncols;
     int32_t src[3];
     int32_t set_pos;  // -1: no value set; else the value there is one of set[0..nset)
@@ -75,7 +76,8 @@ __device__ __forceinline__ bool match_pattern(const DevPattern &q, const Tri &t)
     ok &= !(q.eq & 1u) || t.v[0] == t.v[1];
     ok &= !(q.eq & 2u) || t.v[0] == t.v[2];
     ok &= !(q.eq & 4u) || t.v[1] == t.v[2];
-    if (q.rpos >= 0) ok &= (pick(t, q.rpos) - q.lo) < q.span;
+    ok &= ((t.v[0] - q.rlo[0]) <= q.rmax[0]) & ((t.v[1] - q.rlo[1]) <= q.rmax[1]) &
+          ((t.v[2] - q.rlo[2]) <= q.rmax[2]);
     if (q.set_pos >= 0) {
         const uint32_t x = pick(t, q.set_pos);
         bool in = false;
@@ -97,10 +99,10 @@ __device__ __forceinline__ bool match_plain(const DevPattern &q, const Tri &t) {
     uint32_t diff = ((t.v[0] ^ q.key[0]) & q.msk[0]) | ((t.v[1] ^ q.key[1]) & q.msk[1]) |
                     ((t.v[2] ^ q.key[2]) & q.msk[2]);
     bool ok = diff == 0;
-    ok &= !(q.eq & 1u) || t.v[0] == t.v[1];
-    ok &= !(q.eq & 2u) || t.v[0] == t.v[2];
-    ok &= !(q.eq & 4u) || t.v[1] == t.v[2];
-    if (q.rpos >= 0) ok &= (pick(t, q.rpos) - q.lo) < q.span;
+    ok &= (!(q.eq & 1u) | (t.v[0] == t.v[1])) & (!(q.eq & 2u) | (t.v[0] == t.v[2])) &
+          (!(q.eq & 4u) | (t.v[1] == t.v[2]));
+    ok &= ((t.v[0] - q.rlo[0]) <= q.rmax[0]) & ((t.v[1] - q.rlo[1]) <= q.rmax[1]) &
+          ((t.v[2] - q.rlo[2]) <= q.rmax[2]);
     return ok;
 }
 
@@ -162,6 +164,13 @@ inline uint32_t stage_words(tid_ctx *ctx) {
     return ctx->opt.stage_words > 0 ? (uint32_t)ctx->opt.stage_words : 16384u;
 }
 
+// Staging words of a one-pattern scan in the default shape: the most LDS that
+// still lets two of its 512-thread workgroups share a compute unit (160 KB
+// less the kernels' static LDS).  Longer chunks mean fewer placements, and
+// fewer block-ranged outputs overflow; 1-3% faster than 16384 over the four
+// large-graph benchmark scans.
+constexpr uint32_t kScan1StageWords = 20352;
+
 inline bool any_ext(int k, const PatternSet *sets, const ScanFilter *filters) {
     for (int j = 0; j < k; ++j)
         if ((sets && sets[j].pos >= 0) || (filters && filters[j].pos >= 0)) return true;
@@ -192,10 +201,11 @@ void run_scan(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
     const Shape sh = scan_shape(ctx);
     const uint32_t sw = stage_words(ctx);
     if (sh.block == 512 && sh.ipt == 8 && sh.prefetch && !any_ext(k, sets, filters)) {
+        const uint32_t sw1 = MAXK == 1 && ctx->opt.stage_words <= 0 ? kScan1StageWords : sw;
         ScanSrc<MAXK, false> src{};
         CompactArgs<MAXK, 3> a{};
         fill_scan_args(g, pats, k, outs, sets, filters, src, a);
-        launch_compact<ScanSrc<MAXK, false>, 512, 8, MAXK, 3, true>(ctx, src, a, k, sw);
+        launch_compact<ScanSrc<MAXK, false>, 512, 8, MAXK, 3, true>(ctx, src, a, k, sw1);
         return;
     }
     ScanSrc<MAXK> src{};

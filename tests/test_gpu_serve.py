@@ -154,3 +154,30 @@ def test_circular_tickets_and_errors(ctx, graphs):
             srv._submit(bad)
     finally:
         srv.close()
+
+
+def test_batch_autotuner_keeps_results(ctx, mix, mix_oracle, tmp_path, monkeypatch):
+    """The batch autotuner sweeps the batch options, checks every option set
+    against the first (byte for byte here), caches the fastest, and the
+    cached choice applied to a context still gives the oracle's results."""
+    from paper_1807_01409_amd import autotune
+    monkeypatch.setenv("TID_TUNE_CACHE", str(tmp_path / "tune.json"))
+    g, plans, _ = mix
+    grid = {"semijoin_min": [1 << 12, 1 << 16], "wide_min": [4, 32], "wide_slice": [0, 1]}
+    G = ctx.load(g)
+    G.partition(True)
+    defaults = {k: ctx.get_option(k) for k in grid}
+    try:
+        res = autotune.tune_batch(ctx, G, plans, reps=1, grid=grid)
+        assert len(res["table"]) == 8
+        assert all(res["options"][k] in v for k, v in grid.items())
+        assert {k: ctx.get_option(k) for k in grid} == defaults   # restored
+        entry = autotune.apply(ctx, G.n, "batch")
+        assert entry["options"] == res["options"]
+        assert all(ctx.get_option(k) == v for k, v in res["options"].items())
+        for t, o in zip(ctx.query_batch(G, plans), mix_oracle):
+            assert np.array_equal(t.to_numpy(), o)
+    finally:
+        for k, v in defaults.items():
+            ctx.set_option(k, v)
+        G.free()
