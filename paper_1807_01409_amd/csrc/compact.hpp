@@ -62,8 +62,7 @@ constexpr uint64_t kRowsMask = (1ull << kEpochShift) - 1;
 namespace dev {
 
 // Load one tile of items (striped: item `it` of thread `tid` is
-// t0 + it*BLOCK + tid), test them, and leave per-(item, wave) match counts of
-// every pattern in s_off.  Returns the match bits in mb.
+// t0 + it*BLOCK + tid); items past r1 are left empty.
 template <class Src, int BLOCK, int IPT>
 __device__ __forceinline__ void tile_load(const Src &src, uint64_t t0, uint64_t r1,
                                           typename Src::Item *item) {
@@ -80,21 +79,21 @@ __device__ __forceinline__ void tile_load(const Src &src, uint64_t t0, uint64_t 
     }
 }
 
-// Test a loaded tile and leave the per-(item, wave) match counts in s_off.
+// Test a loaded tile: bal[j][it] is the wave's match mask of pattern j for
+// item `it` (a ballot, so lane l matched iff bit l is set), and the
+// per-(item, wave) match counts go to s_off.
 template <class Src, int BLOCK, int IPT, int MAXK>
 __device__ __forceinline__ void tile_test(const Src &src, int k, uint64_t t0, uint64_t r1,
-                                          const typename Src::Item *item, uint32_t *mb,
+                                          const typename Src::Item *item, uint64_t (*bal)[IPT],
                                           uint32_t (*s_off)[IPT * (BLOCK / kWave)]) {
     constexpr int NW = BLOCK / kWave;
     const int tid = threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-#pragma unroll
-    for (int j = 0; j < MAXK; ++j) mb[j] = 0;
     if (t0 + (uint64_t)BLOCK * IPT <= r1) {  // a whole tile: every item is valid
 #pragma unroll
         for (int it = 0; it < IPT; ++it) {
 #pragma unroll
             for (int j = 0; j < MAXK; ++j)
-                if (j < k && src.match(j, item[it])) mb[j] |= 1u << it;
+                bal[j][it] = j < k ? ballot(src.match(j, item[it])) : 0ull;
         }
     } else {
 #pragma unroll
@@ -102,26 +101,24 @@ __device__ __forceinline__ void tile_test(const Src &src, int k, uint64_t t0, ui
             const bool valid = t0 + (uint64_t)it * BLOCK + tid < r1;
 #pragma unroll
             for (int j = 0; j < MAXK; ++j)
-                if (j < k && valid && src.match(j, item[it])) mb[j] |= 1u << it;
+                bal[j][it] = j < k ? ballot(valid && src.match(j, item[it])) : 0ull;
         }
     }
 #pragma unroll
     for (int j = 0; j < MAXK; ++j) {
         if (j >= k) break;
 #pragma unroll
-        for (int it = 0; it < IPT; ++it) {
-            const uint64_t b = ballot((mb[j] >> it) & 1u);
-            if (lane == 0) s_off[j][it * NW + wave] = (uint32_t)__popcll(b);
-        }
+        for (int it = 0; it < IPT; ++it)
+            if (lane == 0) s_off[j][it * NW + wave] = (uint32_t)__popcll(bal[j][it]);
     }
 }
 
 template <class Src, int BLOCK, int IPT, int MAXK>
 __device__ __forceinline__ void tile_matches(const Src &src, int k, uint64_t t0, uint64_t r1,
-                                             typename Src::Item *item, uint32_t *mb,
+                                             typename Src::Item *item, uint64_t (*bal)[IPT],
                                              uint32_t (*s_off)[IPT * (BLOCK / kWave)]) {
     tile_load<Src, BLOCK, IPT>(src, t0, r1, item);
-    tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, mb, s_off);
+    tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, bal, s_off);
 }
 
 // exclusive offsets (in item order) of NV counts, in place; returns the total
@@ -157,7 +154,6 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
     constexpr int NW = BLOCK / dev::kWave;
     constexpr int NV = IPT * NW;
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
-    static_assert(IPT <= 32, "match bits live in one 32-bit word per pattern");
     extern __shared__ uint32_t stage[];
     __shared__ uint32_t s_off[MAXK][NV];
     __shared__ uint32_t s_tot[MAXK];
@@ -182,7 +178,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
 
     typename Src::Item item[IPT];
     typename Src::Item next[PREFETCH ? IPT : 1];
-    uint32_t mb[MAXK];
+    uint64_t bal[MAXK][IPT];  // match masks of the tile being placed
 
     // ---- phase 1: test the range, stage compacted outputs in LDS ----------
     // With PREFETCH the loads of tile t+1 are issued before tile t is tested,
@@ -193,9 +189,9 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
 #pragma unroll
             for (int it = 0; it < IPT; ++it) item[it] = next[PREFETCH ? it : 0];
             if (t0 + TILE < r1) dev::tile_load<Src, BLOCK, IPT>(src, t0 + TILE, r1, next);
-            dev::tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, mb, s_off);
+            dev::tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, bal, s_off);
         } else {
-            dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, mb, s_off);
+            dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, bal, s_off);
         }
         __syncthreads();
         for (int j = wave; j < k; j += NW) {
@@ -211,8 +207,8 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
             if (s_ovf[j] != kNoTile || cnt + s_tot[j] > o.stage_cap) continue;
 #pragma unroll
             for (int it = 0; it < IPT; ++it) {
-                const bool bit = (mb[j] >> it) & 1u;
-                const uint64_t b = dev::ballot(bit);
+                const uint64_t b = bal[j][it];
+                const bool bit = (b >> lane) & 1u;
                 if (bit) {
                     const uint32_t r =
                         (uint32_t)cnt + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
@@ -294,7 +290,7 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
     uint64_t first = kNoTile;
     for (int j = 0; j < k; ++j) first = min(first, s_ovf[j]);
     for (uint64_t t0 = first; t0 < r1; t0 += TILE) {
-        dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, mb, s_off);
+        dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, r1, item, bal, s_off);
         __syncthreads();
         for (int j = wave; j < k; j += NW) {
             const uint32_t tot = dev::offsets_in_place<NV>(s_off[j]);
@@ -309,8 +305,8 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
             const uint64_t base = s_pre[j] + s_run[j];
 #pragma unroll
             for (int it = 0; it < IPT; ++it) {
-                const bool bit = (mb[j] >> it) & 1u;
-                const uint64_t b = dev::ballot(bit);
+                const uint64_t b = bal[j][it];
+                const bool bit = (b >> lane) & 1u;
                 if (bit) {
                     const uint64_t dst = base + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
                     const uint64_t i = t0 + (uint64_t)it * BLOCK + tid;
@@ -380,7 +376,6 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
     constexpr int NW = BLOCK / dev::kWave;
     constexpr int NV = IPT * NW;
     constexpr uint64_t TILE = (uint64_t)BLOCK * IPT;
-    static_assert(IPT <= 32, "match bits live in one 32-bit word per pattern");
     extern __shared__ uint32_t stage[];
     __shared__ uint32_t s_off[MAXK][NV];
     __shared__ uint32_t s_tot[MAXK];
@@ -406,7 +401,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
     __syncthreads();
 
     typename Src::Item item[IPT], next[IPT];
-    uint32_t mb[MAXK];
+    uint64_t bal[MAXK][IPT];  // match masks of the tile being placed
 
     // Count slots are chunk-major (the k counts of chunk i at slots[i*k ..]),
     // so one round trip fetches every output's counts of a window of
@@ -494,7 +489,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
         uint64_t first = kNoTile;
         for (int j = 0; j < k; ++j) first = min(first, s_povf[j]);
         for (uint64_t t0 = first; t0 < c1; t0 += TILE) {
-            dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, c1, item, mb, s_off);
+            dev::tile_matches<Src, BLOCK, IPT, MAXK>(src, k, t0, c1, item, bal, s_off);
             __syncthreads();
             for (int j = wave; j < k; j += NW) {
                 const uint32_t tot = dev::offsets_in_place<NV>(s_off[j]);
@@ -509,8 +504,8 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
                 const uint64_t base = s_pre[j] + s_run[j];
 #pragma unroll
                 for (int it = 0; it < IPT; ++it) {
-                    const bool bit = (mb[j] >> it) & 1u;
-                    const uint64_t b = dev::ballot(bit);
+                    const uint64_t b = bal[j][it];
+                    const bool bit = (b >> lane) & 1u;
                     if (bit) {
                         const uint64_t dst =
                             base + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
@@ -565,7 +560,7 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
                 dev::tile_load<Src, BLOCK, IPT>(src, t0 + TILE, c1, next);
             else if (tid == 0)
                 ticket = atomicAdd(&counters[0], 1u);  // result first used after the loop
-            dev::tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, c1, item, mb, s_off);
+            dev::tile_test<Src, BLOCK, IPT, MAXK>(src, k, t0, c1, item, bal, s_off);
             __syncthreads();
             for (int j = wave; j < k; j += NW) {
                 const uint32_t tot = dev::offsets_in_place<NV>(s_off[j]);
@@ -580,8 +575,8 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
                 if (s_ovf[j] != kNoTile || cnt + s_tot[j] > o.stage_cap) continue;
 #pragma unroll
                 for (int it = 0; it < IPT; ++it) {
-                    const bool bit = (mb[j] >> it) & 1u;
-                    const uint64_t b = dev::ballot(bit);
+                    const uint64_t b = bal[j][it];
+                    const bool bit = (b >> lane) & 1u;
                     if (bit) {
                         const uint32_t r =
                             (uint32_t)cnt + s_off[j][it * NW + wave] + dev::rank_in_mask(b);
