@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <memory>
 #include <stdexcept>
@@ -102,6 +103,9 @@ struct tid_ctx {
     // stamp for the next chunked launch; *state gets the slot area of `bytes`
     uint32_t next_epoch(size_t bytes, uint64_t **state);
     void sync();
+    // device row-count words whose values the host already knows, written
+    // together by tid::flush_counts (one launch per 128)
+    std::vector<std::pair<uint64_t *, uint64_t>> pending_counts;
 };
 
 namespace tid {
@@ -220,6 +224,21 @@ std::unique_ptr<tid_table> make_table(tid_ctx *ctx, int32_t ncols, const int32_t
 void resolve_counts(tid_ctx *ctx, tid_table *const *ts, int k);
 // Write a known row count to the table's device word and host copy.
 void set_count(tid_ctx *ctx, tid_table *t, uint64_t n);
+// The same, with the device word written by the next flush_counts (the host
+// copy at once); for the many tables of a batch round, whose device words no
+// kernel reads before the round's end.
+void set_count_later(tid_ctx *ctx, tid_table *t, uint64_t n);
+void flush_counts(tid_ctx *ctx);
+// Drops the counts still pending when a call fails (their tables may be
+// freed with the error); on success the call has flushed them itself.
+struct PendingCountsGuard {
+    tid_ctx *ctx;
+    int exc;
+    explicit PendingCountsGuard(tid_ctx *c) : ctx(c), exc(std::uncaught_exceptions()) {}
+    ~PendingCountsGuard() {
+        if (std::uncaught_exceptions() > exc) ctx->pending_counts.clear();
+    }
+};
 // Column value bounds: dst column c takes the bound of src column map[c].
 void copy_bounds(tid_table *dst, const tid_table *src, const int *map, int n, int dst_off = 0);
 

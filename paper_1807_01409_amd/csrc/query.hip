@@ -479,7 +479,7 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
                 auto out = make_table(ctx, T->ncols, T->vars, T->nrows);
                 out->maxv_known = T->maxv_known;
                 copy_bounds(out.get(), T, nullptr, T->ncols);
-                set_count(ctx, out.get(), T->nrows);
+                set_count_later(ctx, out.get(), T->nrows);  // a result: not freed this round
                 bs->row_sorts.push_back(RowSortJob{T, out.get(), T->nrows});
                 bs->keep_tables.push_back(std::move(top.t));
                 r.result = std::move(out);
@@ -693,6 +693,7 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
 std::vector<std::unique_ptr<tid_table>> run_plans(
     tid_ctx *ctx, const tid_graph *g, const tid_plan *const *plans, int nq,
     std::vector<std::vector<std::unique_ptr<tid_table>>> *pre = nullptr) {
+    PendingCountsGuard counts_guard(ctx);
     std::vector<PlanRun> runs(nq);
     int nrounds = pre ? 0 : 1;
     for (int i = 0; i < nq; ++i) {
@@ -809,7 +810,7 @@ std::vector<std::unique_ptr<tid_table>> run_plans(
                 for (int c = 0; c < t->ncols; ++c) j.out[c] = t->col[c];
                 bs.expand_jobs.push_back(j);
             }
-            set_count(ctx, t.get(), r.pj->total);
+            set_count_later(ctx, t.get(), r.pj->total);
             r.pj->small_result = std::move(t);
         }
         flush_join_jobs(ctx, bs, true);
@@ -837,10 +838,11 @@ std::vector<std::unique_ptr<tid_table>> run_plans(
                 bs.big_out_total += r.pj->total;
                 bs.big_expand_jobs.push_back(x);
             }
-            set_count(ctx, t.get(), r.pj->total);
+            set_count_later(ctx, t.get(), r.pj->total);
             r.pj->small_result = std::move(t);
         }
         if (arena) flush_big_expand(ctx, *arena, bs.big_expand_jobs, bs);
+        flush_counts(ctx);  // before any plan can consume (and free) these tables
         Needs needs;
         bool all_done = true;
         for (auto &r : runs) {
@@ -849,6 +851,7 @@ std::vector<std::unique_ptr<tid_table>> run_plans(
         }
         flush_join_jobs(ctx, bs, false);
         flush_sort_jobs(ctx, bs);
+        flush_counts(ctx);
         std::shared_ptr<BigArena> fresh;
         flush_big_count(ctx, bs.big_reqs, &fresh);
         if (all_done) break;

@@ -103,6 +103,38 @@ void set_count(tid_ctx *ctx, tid_table *t, uint64_t n) {
     t->count_known = true;
 }
 
+constexpr int kCountSets = 128;
+struct CountSets {
+    uint64_t *p[kCountSets];
+    uint64_t v[kCountSets];
+    int n;
+};
+
+__global__ void set_u64_many(CountSets s) {
+    if ((int)threadIdx.x < s.n) *s.p[threadIdx.x] = s.v[threadIdx.x];
+}
+
+void set_count_later(tid_ctx *ctx, tid_table *t, uint64_t n) {
+    ctx->pending_counts.emplace_back(t->d_count, n);
+    t->nrows = n;
+    t->count_known = true;
+}
+
+void flush_counts(tid_ctx *ctx) {
+    auto &pc = ctx->pending_counts;
+    for (size_t i = 0; i < pc.size(); i += kCountSets) {
+        CountSets s{};
+        s.n = (int)std::min<size_t>(kCountSets, pc.size() - i);
+        for (int j = 0; j < s.n; ++j) {
+            s.p[j] = pc[i + j].first;
+            s.v[j] = pc[i + j].second;
+        }
+        hipLaunchKernelGGL(set_u64_many, dim3(1), dim3(kCountSets), 0, ctx->stream, s);
+        TID_HIP(hipGetLastError());
+    }
+    pc.clear();
+}
+
 __global__ void gather_words(const uint64_t *const *src, uint64_t *dst, int n,
                              const uint32_t *flags) {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x)

@@ -487,7 +487,7 @@ static std::unique_ptr<tid_table> slice_table(tid_ctx *ctx, const tid_graph *g,
     }
     t->maxv_known = true;
     t->cap = b - a;
-    set_count(ctx, t.get(), b - a);
+    set_count_later(ctx, t.get(), b - a);  // written when scan_many returns
     return t;
 }
 
@@ -502,6 +502,7 @@ static std::unique_ptr<tid_table> slice_table(tid_ctx *ctx, const tid_graph *g,
 void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                std::unique_ptr<tid_table> *outs, const PatternSet *sets,
                const ScanFilter *filters) {
+    PendingCountsGuard counts_guard(ctx);
     const int64_t wide_min = ctx->opt.wide_min > 0 ? ctx->opt.wide_min : 8;
     const bool parts = g->partitioned && ctx->opt.layout != 0 && g->n > 0 &&
                        ctx->opt.capacity_override <= 0 && !g->cdf[1].empty();
@@ -579,6 +580,7 @@ void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
         scan_multi(ctx, g, rp.data(), m, rt, rs.data(), rf.data());
         for (int j = 0; j < m; ++j) outs[rest[r0 + j]] = std::move(rt[j]);
     }
+    flush_counts(ctx);  // the whole-slice tables' count words
 }
 
 void scan_multi(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
