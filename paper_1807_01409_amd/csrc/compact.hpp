@@ -277,7 +277,12 @@ __global__ __launch_bounds__(BLOCK) void compact_kernel(Src src, CompactArgs<MAX
         if (o.ncols == 0) continue;
         const uint64_t pre = s_pre[j];
         const uint32_t st = (uint32_t)s_staged[j];
-        for (uint32_t r = tid; r < st; r += BLOCK) {
+        // thread slots start at the 32-row (128-byte) boundary below pre, so
+        // each wave's stores cover whole cache lines
+        const uint32_t lead = (uint32_t)(pre & 31u);
+        for (uint32_t x = tid; x < st + lead; x += BLOCK) {
+            if (x < lead) continue;
+            const uint32_t r = x - lead;
             const uint64_t dst = pre + r;
             if (dst < o.cap) {
                 TID_FOR_COLS(MAXC, c, o.ncols)
@@ -476,7 +481,11 @@ __global__ __launch_bounds__(BLOCK) void chunk_compact_kernel(Src src, CompactAr
             if (o.ncols == 0) continue;
             const uint64_t pre = s_pre[j];
             const uint32_t stg = (uint32_t)s_pstg[j];
-            for (uint32_t r = tid; r < stg; r += BLOCK) {
+            // from the 32-row boundary below pre: whole cache lines per wave
+            const uint32_t lead = (uint32_t)(pre & 31u);
+            for (uint32_t x = tid; x < stg + lead; x += BLOCK) {
+                if (x < lead) continue;
+                const uint32_t r = x - lead;
                 const uint64_t dst = pre + r;
                 if (dst < o.cap) {
                     TID_FOR_COLS(MAXC, c, o.ncols)
