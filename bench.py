@@ -140,10 +140,10 @@ def mix_summary(infos):
                 [int(x) for x in np.quantile(rows, [0.1, 0.5, 0.9, 0.99, 1.0])]}
 
 
-def scan_workload(g, chain=True):
+def scan_workload(g, chain=True, star=False):
     from synth import Pattern
     from synth.queries import (chain_query, predicate_for_selectivity, range_pattern,
-                               union_query)
+                               star_query, union_query)
     preds = [predicate_for_selectivity(g, s) for s in (1e-3, 1e-2, 1e-1)]
     w = {"preds": preds, "scans": [Pattern(0, p, 0, 0, -1, 1) for p, _ in preds]}
     w["range"], w["range_info"] = range_pattern(g)
@@ -152,6 +152,8 @@ def scan_workload(g, chain=True):
         t0 = time.time()
         w["chain"], w["chain_info"] = chain_query(g)
         log(f"chain {w['chain_info']} chosen in {time.time() - t0:.1f}s")
+    if star:
+        w["star"], w["star_info"] = star_query(g)
     return w
 
 
@@ -290,11 +292,22 @@ def medium_part(torch, args, spec, g, w):
     per, probe = scan_measurements(torch, ctx, G, spec.n, w, args.reps)
     dur = sum(x["us"] for x in per) * 1e-6
     achieved = sum(x["bytes"] for x in per) / dur / 1e9
+    tm = Timer(torch, ctx)
+    queries = {}
+    for name in ("star", "union"):
+        if name not in w:
+            continue
+        d = tm.launches(lambda: ctx.query(G, w[name]), 5)
+        queries[f"{name}_query_ms"] = round(float(np.median(d)) * 1e3, 3)
+        queries[f"{name}_rows"] = ctx.query(G, w[name]).nrows
+    del tm
     G.free()
     ctx.close()
-    log(f"medium scans {per}")
+    log(f"medium scans {per}; queries {queries}")
     return {"workload": f"medium graph {spec.n} triples (s Zipf 1.0/5M, p Zipf 1.2/1000, "
-                        "o Zipf 1.1/10M): the same four scans",
+                        "o Zipf 1.1/10M): the same four scans; a 3-pattern star on ?s and "
+                        "the 8-way union with DISTINCT as whole queries (median of 5, flushed)",
+            "queries": queries,
             "value": len(per) * spec.n / dur, "unit": "triples/s",
             "frac": achieved / HBM_PEAK_GBS, "read_probe_GBps": probe,
             "frac_of_read_probe": achieved / probe["dwordx3"],
@@ -519,7 +532,7 @@ def main():
         spec, g = draw_graph(name, args.n)
         item = {"spec": spec, "g": g}
         if name in ("large", "medium"):
-            item["w"] = scan_workload(g, chain=name == "large")
+            item["w"] = scan_workload(g, chain=name == "large", star=name == "medium")
         else:
             item["plans"], item["infos"] = draw_mix(name, spec, g, args.queries, spec.seed)
         inputs[name] = item
