@@ -123,7 +123,12 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           the larger of 65536 and 1/4096 of the graph)
      "layout"             1 (default): scans use a graph's predicate-partitioned
                           layout when it is built (tid_graph_partition) and
-                          pays; 0: scans always read the TripleID array */
+                          pays; 0: scans always read the TripleID array
+     "index_semijoin"     1 (default): in plans on a partitioned graph, a
+                          scan filtered by a small semi-join source looks the
+                          source's values up in the layout's (predicate,
+                          subject) or (predicate, object) order instead of
+                          testing every row of the predicate; 0: never */
 tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value);
 tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value);
 
@@ -150,12 +155,16 @@ tid_status tid_graph_count(const tid_graph *g, int32_t pos, uint32_t lo, uint32_
                            uint64_t *count);
 /* Layout variant (the paper's ID assignment for pruning a search, Sec. 4.3):
    enable = 1 builds, beside the TripleID array, the triples stably sorted by
-   predicate as two device columns (subject, object), 8 B per triple more;
-   enable = 0 drops it.  While it exists (and the context option "layout" is
-   1), scans whose patterns all have a constant predicate and whose slices
-   add up to less than one read of the array read only those predicates'
-   slices; results are identical (ascending triple position).  Needs the
-   predicate histogram (TID_E_UNSUPPORTED otherwise).  Synchronises. */
+   predicate as two device columns (subject, object), and the same rows
+   ordered by (predicate, subject) and by (predicate, object) for semi-join
+   lookups: 24 B per triple more; enable = 0 drops them.  While they exist
+   (and the context option "layout" is 1), scans whose patterns all have a
+   constant predicate and whose slices add up to less than one read of the
+   array read only those predicates' slices; results are identical
+   (ascending triple position).  Plans and batches use the layout as well
+   (see the options "layout" and "index_semijoin").  Needs the predicate
+   histogram and fewer than 2^32 triples (TID_E_UNSUPPORTED otherwise).
+   Synchronises. */
 tid_status tid_graph_partition(tid_ctx *ctx, tid_graph *g, int32_t enable);
 void tid_graph_free(tid_graph *g);
 

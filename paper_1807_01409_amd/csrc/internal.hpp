@@ -70,6 +70,8 @@ struct Options {
     int64_t slice_rows = 0;      // rows a predicate needs to be sliced (0 = default)
     int64_t layout = 1;          // 1: scans use a graph's partitioned layout if built; 0: never
     int64_t batch_small = 1;     // 1: small joins and final sorts of plans batched per round
+    int64_t index_semijoin = 1;  // 1: small semi-join sources look their keys up in the
+                                 // partitioned layout's sorted copies; 0: Bloom filters
 };
 
 }  // namespace tid
@@ -171,6 +173,11 @@ struct tid_graph {
     // [cdf[1][p], cdf[1][p + 1]) in ascending triple position.  Scans with a
     // constant predicate then read only that slice (8 B per triple of p).
     tid::DevBuf part_s, part_o;
+    // The same rows ordered by (predicate, subject) and by (predicate,
+    // object), ties in triple order, as (subject, object) columns: predicate
+    // p's rows are the same [cdf[1][p], cdf[1][p + 1]) in both.  A semi-join
+    // on a pattern's subject or object looks its keys up in these.
+    tid::DevBuf ps_s, ps_o, po_s, po_o;
     bool partitioned = false;
     // A chunk of another graph (circular serving scan): `view` is its first
     // triple (not owned); positions without a histogram here take their
@@ -268,6 +275,14 @@ struct ScanFilter {
     uint32_t mask = 0;
     int32_t pos = -1;  // -1: none
     int32_t exact = 0;
+    // index = 1: no bits; the rows are those of the pattern's predicate whose
+    // value at `pos` is one of the `nkeys` values at `keys` (device, any
+    // order, repeats allowed), found in the sorted copies of the partitioned
+    // layout (index_semijoin); rows then come grouped by key
+    const uint32_t *keys = nullptr;
+    uint64_t nkeys = 0;
+    uint32_t key_max = 0;  // bound of the key values
+    int32_t index = 0;
 };
 
 // Scan: fill `outs[j]` for k patterns in one pass.  Tables are allocated here.

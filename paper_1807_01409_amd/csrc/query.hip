@@ -380,6 +380,9 @@ static std::string scan_key(const tid_pattern &p, const PatternSet &set, const S
     k.append(reinterpret_cast<const char *>(&f.bits), sizeof f.bits);
     k.append(reinterpret_cast<const char *>(&f.mask), sizeof f.mask);
     k.append(reinterpret_cast<const char *>(&f.pos), sizeof f.pos);
+    k.append(reinterpret_cast<const char *>(&f.index), sizeof f.index);
+    k.append(reinterpret_cast<const char *>(&f.keys), sizeof f.keys);
+    k.append(reinterpret_cast<const char *>(&f.nkeys), sizeof f.nkeys);
     return k;
 }
 
@@ -392,6 +395,22 @@ static std::unique_ptr<tid_table> alias_table(const tid_table *t, const tid_patt
     TID_REQUIRE(nc == t->ncols, TID_E_INTERNAL, "scan alias: schema mismatch");
     for (int c = 0; c < nc; ++c) out->vars[c] = vars[c];
     return out;
+}
+
+// Whether a scan filtered on position `pos` by a source of `rows` rows is a
+// semi-join by index (index_semijoin): the partitioned layout is built and
+// used, the pattern has a constant predicate and a free subject and object
+// (no other test), and the source is small against the predicate's rows (a
+// lookup per source value then costs less than testing every row).
+static bool index_semijoin_ok(tid_ctx *ctx, const tid_graph *g, const tid_pattern &p,
+                              const PatternSet &set, int pos, uint64_t rows) {
+    if (!g->partitioned || !ctx->opt.layout || !ctx->opt.index_semijoin ||
+        ctx->opt.capacity_override > 0 || g->cdf[1].empty())
+        return false;
+    if (p.p == 0 || p.s != 0 || p.o != 0 || p.range_pos >= 0 || (p.vs >= 0 && p.vs == p.vo) ||
+        set.pos >= 0 || (pos != 0 && pos != 2) || rows >= (1ull << 32))
+        return false;
+    return 4 * rows <= g->count_in(1, p.p, (uint64_t)p.p + 1);
 }
 
 // One Bloom filter per job: the values of a table column.
@@ -739,6 +758,17 @@ std::vector<std::unique_ptr<tid_table>> run_plans(
             const tid_table *S = runs[where[j].first].scanned[sr.src].get();
             const int c = col_of(S, sr.var);
             TID_REQUIRE(c >= 0, TID_E_INTERNAL, "semi-join: source lacks the variable");
+            const int fpos = position_of(all[j], sr.var);
+            if (index_semijoin_ok(ctx, g, all[j], all_sets[j], fpos, S->nrows)) {
+                ScanFilter &f = all_filters[j];
+                f.pos = fpos;
+                f.index = 1;
+                f.keys = S->col[c];
+                f.nkeys = S->nrows;
+                f.key_max = S->maxv_known ? S->maxv[c]
+                                          : std::max({g->max_id[0], g->max_id[1], g->max_id[2]});
+                continue;  // no Bloom filter
+            }
             uint64_t bits = 4096;
             while (bits < 16 * S->nrows && bits < (1ull << 28)) bits <<= 1;
             jobs.push_back(BloomJob{S->col[c], S->nrows, nullptr, (uint32_t)(bits - 1)});

@@ -460,6 +460,8 @@ void run_wide(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
               tid_table *const *outs, const ScanFilter *filters);
 void run_wide_parts(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
                     tid_table *const *outs, const ScanFilter *filters);
+void index_semijoin(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats,
+                    const ScanFilter *filters, int J, std::unique_ptr<tid_table> *outs);
 
 // A pattern whose rows are exactly its predicate's slice of the partitioned
 // layout: a constant predicate, subject and object free (and not one
@@ -506,10 +508,26 @@ void scan_many(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats, int k,
     const int64_t wide_min = ctx->opt.wide_min > 0 ? ctx->opt.wide_min : 8;
     const bool parts = g->partitioned && ctx->opt.layout != 0 && g->n > 0 &&
                        ctx->opt.capacity_override <= 0 && !g->cdf[1].empty();
+    // semi-joins by index: every such pattern of the call in one batch
+    std::vector<int> idx;
+    for (int j = 0; j < k && filters; ++j)
+        if (filters[j].index) idx.push_back(j);
+    if (!idx.empty()) {
+        std::vector<tid_pattern> ip;
+        std::vector<ScanFilter> ifl;
+        for (int j : idx) {
+            ip.push_back(pats[j]);
+            ifl.push_back(filters[j]);
+        }
+        std::vector<std::unique_ptr<tid_table>> io(idx.size());
+        index_semijoin(ctx, g, ip.data(), ifl.data(), (int)idx.size(), io.data());
+        for (size_t x = 0; x < idx.size(); ++x) outs[idx[x]] = std::move(io[x]);
+    }
     std::vector<int> wide, rest;
     for (int j = 0; j < k; ++j) {
         const PatternSet *set = sets ? &sets[j] : nullptr;
         const ScanFilter *f = filters ? &filters[j] : nullptr;
+        if (f && f->index) continue;
         if (parts && whole_slice(pats[j], set, f)) {
             outs[j] = slice_table(ctx, g, pats[j]);
             continue;

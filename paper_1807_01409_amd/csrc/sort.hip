@@ -769,6 +769,16 @@ std::unique_ptr<tid_table> sort_rows(tid_ctx *ctx, const tid_table *t, uint64_t 
 void sort_rows_batched(tid_ctx *ctx, const std::vector<RowSortJob> &jobs,
                        std::vector<DevBuf> &keep, std::vector<std::vector<char>> &host_keep) {
     if (jobs.empty()) return;
+    if (jobs.size() == 1) {
+        // one table (a single plan): the sort of one table, whose passes
+        // spread over up to two ranges per compute unit
+        const RowSortJob &job = jobs[0];
+        TID_REQUIRE(job.in->maxv_known && job.n < (1ull << 32) && job.in->ncols > 0,
+                    TID_E_INTERNAL, "batched sort: bad job");
+        keep.push_back(sort_permutation(ctx, job.in, job.n));
+        gather_table(ctx, job.in, keep.back().get<const uint32_t>(), job.n, job.out);
+        return;
+    }
     constexpr uint64_t kChunkRows = 1ull << 27;  // rows per arena fill
     struct Plan {
         std::vector<std::pair<int, int>> groups;  // [first, last) columns, most significant first
