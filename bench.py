@@ -433,6 +433,21 @@ def serving_part(args, spec, g, plans, infos):
             if not np.array_equal(t.to_numpy(), r.result):
                 mism += 1
             t.free()
+    sat = None
+    if args.saturation > 0:
+        # the same server under `saturation` times the offered load for 2 s:
+        # what it sustains when arrivals outpace it
+        q2 = args.qps * args.saturation
+        n2 = int(q2 * 2.0)
+        arr2 = poisson_arrivals(n2, q2, spec.seed + 1)
+        pick2 = rng.integers(0, len(plans), size=n2)
+        st2 = srv.run([Request(i, plans[int(pick2[i])], float(arr2[i])) for i in range(n2)],
+                      warmup_s=0.2)
+        sat = {"offered_qps": q2, "requests": n2, "value": st2.qps, "p50_ms": st2.p50_ms,
+               "p99_ms": st2.p99_ms, "mean_batch": st2.mean_batch, "max_queue": st2.max_queue,
+               "failed": st2.failed}
+        log(f"saturation: {n2} requests at {q2:.0f} q/s offered: {st2.qps:.0f} q/s, "
+            f"p50 {st2.p50_ms:.2f} ms p99 {st2.p99_ms:.2f} ms")
     srv.close()
     mode = ({"mode": "circular chunked shared scan", "chunks": args.chunks, "slots": args.slots}
             if args.serve_mode == "circular" else
@@ -448,6 +463,7 @@ def serving_part(args, spec, g, plans, infos):
             "max_inflight_bytes": st.max_inflight_bytes,
             "budget_gib": args.budget_gb,
             "mix_equals_alone_checked": len(check), "mix_equals_alone_mismatches": mism,
+            "saturation": sat,
             "workload": f"serving graph {spec.n} triples resident in HBM (s Zipf 1.0/1e8, "
                         "p Zipf 1.2/1000, o Zipf 1.1/2e8); Poisson arrivals from a pool of "
                         f"{len(plans)} batched-mix queries",
@@ -508,6 +524,8 @@ def main():
     ap.add_argument("--warmup-s", type=float, default=1.0, help="serving: arrivals not measured")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: result budget")
     ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--saturation", type=float, default=8.0,
+                    help="serving: also offer this many times the load for 2 s (0: skip)")
     ap.add_argument("--serve-mode", choices=["circular", "groups"], default="groups")
     ap.add_argument("--chunks", type=int, default=16, help="serving: chunks of the revolution")
     ap.add_argument("--slots", type=int, default=512, help="serving: query slots")
