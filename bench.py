@@ -24,8 +24,8 @@ Default run (prints one JSON line):
   cpu_baseline  the oracle on the host over the headline's four scans:
             single-threaded, and on every host core (one slice per thread).
 
---workload picks one part alone.  --gpus N with N > 1 is refused: this build
-measures one GPU.
+--workload picks one part alone.  --gpus N with N > 1 is refused: the
+benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -536,7 +536,7 @@ def main():
                          "metric); group serving builds them unless this is aos")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.workload == "scan-profile":
         scan_profile(args)

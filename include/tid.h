@@ -40,7 +40,7 @@ typedef int32_t tid_status;
 #define TID_E_INVALID_ARG (-1)  /* bad argument, pattern, plan or reserved ID 0 in a triple */
 #define TID_E_OOM         (-2)  /* the allocator returned NULL */
 #define TID_E_CAPACITY    (-3)  /* a result outgrew its buffer and retry is switched off */
-#define TID_E_UNSUPPORTED (-4)  /* a valid request this build does not handle */
+#define TID_E_UNSUPPORTED (-4)  /* a valid request the library does not handle */
 #define TID_E_SCHEMA      (-5)  /* a variable named by a plan or join is not in the table */
 #define TID_E_HIP         (-6)  /* a HIP runtime call failed */
 #define TID_E_INTERNAL    (-7)  /* a kernel reported an inconsistency (a bug) */
