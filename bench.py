@@ -523,7 +523,7 @@ def main():
     ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrivals")
     ap.add_argument("--warmup-s", type=float, default=1.0, help="serving: arrivals not measured")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="serving: result budget")
-    ap.add_argument("--serve-workers", type=int, default=2)
+    ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--saturation", type=float, default=8.0,
                     help="serving: also offer this many times the load for 2 s (0: skip)")
     ap.add_argument("--serve-mode", choices=["circular", "groups"], default="groups")

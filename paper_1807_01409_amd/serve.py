@@ -55,7 +55,7 @@ class Server:
     layout: also build the graph's predicate-partitioned columns, so that the
     patterns with a constant predicate read only their predicates' slices."""
 
-    def __init__(self, triples, workers: int = 2, budget_bytes: int = 64 << 30,
+    def __init__(self, triples, workers: int = 4, budget_bytes: int = 64 << 30,
                  max_batch: int = 256, allocator: str = "pool", device: int = 0,
                  layout: bool = True):
         self.ctxs = [Context(device, allocator=allocator) for _ in range(workers)]
