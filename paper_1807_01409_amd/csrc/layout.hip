@@ -5,7 +5,9 @@
 // predicate p reads only p's slice, 8 B per triple of p instead of 12 B per
 // triple of the graph, and finds the same rows in the same order (ascending
 // triple position, since the sort is stable).  Patterns with a free
-// predicate still read the TripleID array.
+// predicate still read the TripleID array.  The same rows are also kept in
+// (predicate, subject) and (predicate, object) order, where a semi-join looks
+// its source's values up (index_semijoin, at the end of this file).
 #include "batch.hpp"
 #include "scan_common.hpp"
 
