@@ -128,7 +128,9 @@ tid_status tid_ctx_synchronize(tid_ctx *ctx);
                           scan filtered by a small semi-join source looks the
                           source's values up in the layout's (predicate,
                           subject) or (predicate, object) order instead of
-                          testing every row of the predicate; 0: never */
+                          testing every row of the predicate; 0: never
+     "index_ratio"        a source is small when index_ratio times its rows
+                          are at most the predicate's rows (default 4) */
 tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value);
 tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value);
 

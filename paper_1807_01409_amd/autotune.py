@@ -6,7 +6,8 @@ HIP events on the context's stream, checks that every shape returns the same
 bytes as the first (a race or ordering bug would show up as a difference),
 and keeps the fastest.  tune_batch does the same for a batch of plans over
 the batch options (when a scan is semi-join filtered, how many patterns make
-a wide pass, whether wide passes slice shared predicates).  Results are
+a wide pass, whether wide passes slice shared predicates, when a semi-join is
+an index lookup).  Results are
 cached in a JSON file keyed by device name, operation and graph-size bucket;
 TID_TUNE_CACHE names the file.
 """
@@ -24,7 +25,7 @@ SHAPES: List[Tuple[int, int]] = [(256, 16), (256, 8), (256, 32), (512, 8), (512,
 STAGE_WORDS = [4096, 8192, 12288, 16384]
 KEYS = ("scan_block", "scan_items", "scan_prefetch", "stage_words")
 BATCH_GRID = {"semijoin_min": [1 << 12, 1 << 16, 1 << 20], "wide_min": [4, 8, 32],
-              "wide_slice": [0, 1]}
+              "wide_slice": [0, 1], "index_ratio": [1, 4, 16]}
 BATCH_KEYS = tuple(BATCH_GRID)
 
 

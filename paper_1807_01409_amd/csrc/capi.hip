@@ -173,6 +173,10 @@ tid_status tid_ctx_set_option(tid_ctx *ctx, const char *key, int64_t value) {
             TID_REQUIRE(value == 0 || value == 1, TID_E_INVALID_ARG,
                         "index_semijoin must be 0 or 1");
             ctx->opt.index_semijoin = value;
+        } else if (k == "index_ratio") {
+            TID_REQUIRE(value >= 0 && value <= (1 << 20), TID_E_INVALID_ARG,
+                        "index_ratio must be in 0..2^20");
+            ctx->opt.index_ratio = value;
         } else if (k == "chunk_epoch") {
             TID_REQUIRE(value >= 0 && value <= (int64_t)tid::kEpochMax, TID_E_INVALID_ARG,
                         "chunk_epoch is 0..2^23-1");
@@ -218,6 +222,7 @@ tid_status tid_ctx_get_option(tid_ctx *ctx, const char *key, int64_t *value) {
         else if (k == "slice_rows") *value = ctx->opt.slice_rows;
         else if (k == "layout") *value = ctx->opt.layout;
         else if (k == "index_semijoin") *value = ctx->opt.index_semijoin;
+        else if (k == "index_ratio") *value = ctx->opt.index_ratio;
         else throw Error(TID_E_INVALID_ARG, "unknown option " + k);
     });
 }

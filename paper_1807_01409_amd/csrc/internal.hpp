@@ -72,6 +72,7 @@ struct Options {
     int64_t batch_small = 1;     // 1: small joins and final sorts of plans batched per round
     int64_t index_semijoin = 1;  // 1: small semi-join sources look their keys up in the
                                  // partitioned layout's sorted copies; 0: Bloom filters
+    int64_t index_ratio = 4;     // "small": index_ratio x source rows <= the predicate's rows
 };
 
 }  // namespace tid

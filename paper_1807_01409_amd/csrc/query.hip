@@ -400,8 +400,9 @@ static std::unique_ptr<tid_table> alias_table(const tid_table *t, const tid_patt
 // Whether a scan filtered on position `pos` by a source of `rows` rows is a
 // semi-join by index (index_semijoin): the partitioned layout is built and
 // used, the pattern has a constant predicate and a free subject and object
-// (no other test), and the source is small against the predicate's rows (a
-// lookup per source value then costs less than testing every row).
+// (no other test), and the source is small against the predicate's rows
+// (option index_ratio: a lookup per source value then costs less than
+// testing every row).
 static bool index_semijoin_ok(tid_ctx *ctx, const tid_graph *g, const tid_pattern &p,
                               const PatternSet &set, int pos, uint64_t rows) {
     if (!g->partitioned || !ctx->opt.layout || !ctx->opt.index_semijoin ||
@@ -410,7 +411,7 @@ static bool index_semijoin_ok(tid_ctx *ctx, const tid_graph *g, const tid_patter
     if (p.p == 0 || p.s != 0 || p.o != 0 || p.range_pos >= 0 || (p.vs >= 0 && p.vs == p.vo) ||
         set.pos >= 0 || (pos != 0 && pos != 2) || rows >= (1ull << 32))
         return false;
-    return 4 * rows <= g->count_in(1, p.p, (uint64_t)p.p + 1);
+    return (uint64_t)ctx->opt.index_ratio * rows <= g->count_in(1, p.p, (uint64_t)p.p + 1);
 }
 
 // One Bloom filter per job: the values of a table column.
