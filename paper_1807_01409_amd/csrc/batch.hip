@@ -6,7 +6,8 @@
 // one count launch, then of the next round's one expansion launch.  A plan's
 // final lexicographic sort of at most kSortRows rows is likewise a job of one
 // sort launch.  Everything a job touches besides its inputs and outputs lives
-// in the workgroup's LDS.
+// in the workgroup's LDS, except for a join with a large output, whose
+// expansion is spread over many workgroups (below).
 //
 // Join job (Sec. 4.2: an equi-join on the shared variable, done here with a
 // hash table in LDS): the R side's keys go into an open-addressing table
@@ -159,10 +160,85 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_count(const JoinJob *j
     }
 }
 
+// Expansion.  With no other shared variable, L row i owns the output rows
+// [off[i], off[i+1]), paired in turn with the R rows of its key, so each
+// output row is one thread's: its L row by a binary search of the offsets,
+// its R row the matching entry of the key's group; consecutive threads write
+// consecutive rows.  (Giving each L row to a thread instead makes the thread
+// of a hub key walk hundreds of pairs, a global load after the other.)  With
+// other shared variables, a row's pairs are those that also agree on them,
+// and each L row's thread writes its pairs.
+namespace {
+__shared__ uint32_t s_off[kSmallRows], s_lb[kSmallRows];
+
+// the last row i in [lo, hi] with off[i] <= o (off non-decreasing, off[lo] <= o)
+__device__ __forceinline__ uint32_t owner_row(const uint32_t *off, uint32_t lo, uint32_t hi,
+                                              uint32_t o) {
+    uint32_t n = hi - lo + 1, a = lo;
+    while (n > 1) {
+        const uint32_t half = n / 2;
+        if (off[a + half] <= o) a += half;
+        n -= half;
+    }
+    return a;
+}
+
+constexpr int kUnroll = 4;
+
+// Output rows [o0, o1) of a job without other shared variables, thread-
+// parallel: the L rows i0 + k own [loff[k], loff[k+1]) (loff in LDS, i0..i1),
+// each paired in turn with the entries of its key's group of R rows, which
+// start at lb[k] in grp.  The loads of kUnroll rows are issued before their
+// stores.
+__device__ __forceinline__ void expand_rows(const JoinJob &j, const uint32_t *loff,
+                                            const uint32_t *lb, const uint32_t *grp,
+                                            uint32_t i0, uint32_t i1, uint32_t o0,
+                                            uint32_t o1) {
+    for (uint32_t base = o0; base < o1; base += kBatchBlock * kUnroll) {
+        uint32_t li[kUnroll], ri[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const uint32_t o = base + u * kBatchBlock + threadIdx.x;
+            li[u] = ri[u] = 0;
+            if (o < o1) {
+                const uint32_t k = owner_row(loff, 0, i1 - i0, o);
+                li[u] = i0 + k;
+                ri[u] = grp[lb[k] + (o - loff[k])];
+            }
+        }
+        for (int c = 0; c < j.nlc + j.nrc; ++c) {
+            const bool left = c < j.nlc;
+            const uint32_t *src = left ? j.lcol[c] : j.rcol[c - j.nlc];
+            uint32_t v[kUnroll];
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u)
+                v[u] = base + u * kBatchBlock + threadIdx.x < o1 ? src[left ? li[u] : ri[u]] : 0u;
+#pragma unroll
+            for (int u = 0; u < kUnroll; ++u) {
+                const uint32_t o = base + u * kBatchBlock + threadIdx.x;
+                if (o < o1) j.out[c][o] = v[u];
+            }
+        }
+    }
+}
+}  // namespace
+
 __global__ __launch_bounds__(kBatchBlock) void batch_join_expand(const JoinJob *jobs) {
     const JoinJob &j = jobs[blockIdx.x];
     Table t{s_key, s_cnt, s_start, s_rows, 0};
     build_table(j, t, s_w);
+    if (j.neq == 0) {
+        // each output row a thread's: L row i owns [off[i], off[i+1]), paired
+        // with its key's R rows in slot order
+        for (uint32_t i = threadIdx.x; i < j.nl; i += kBatchBlock) {
+            const uint32_t h = find_slot(t, j.lkey[i]);
+            s_off[i] = j.off[i];
+            s_lb[i] = h == kEmptyKey ? 0u : t.start[h];  // a row without a match owns no output
+        }
+        __syncthreads();
+        expand_rows(j, s_off, s_lb, t.rows, 0, j.nl - 1, 0, j.nout);
+        return;
+    }
     for (uint32_t i = threadIdx.x; i < j.nl; i += kBatchBlock) {
         const uint32_t h = find_slot(t, j.lkey[i]);
         if (h == kEmptyKey) continue;
@@ -170,12 +246,56 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_expand(const JoinJob *
         const uint32_t a = t.start[h], b = a + t.cnt[h];
         for (uint32_t m = a; m < b; ++m) {
             const uint32_t r = t.rows[m];
-            if (j.neq && !agree(j, i, r)) continue;
+            if (!agree(j, i, r)) continue;
             for (int c = 0; c < j.nlc; ++c) j.out[c][o] = j.lcol[c][i];
             for (int c = 0; c < j.nrc; ++c) j.out[j.nlc + c][o] = j.rcol[c][r];
             ++o;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// A job with a large output (a hub key: few rows on each side, up to
+// millions of pairs) and no other shared variable is spread over many
+// workgroups.  One workgroup per job rebuilds the table and writes the R
+// rows grouped by key (grp) and, for each L row, where its key's group
+// starts (lbase); then each workgroup of the second launch expands a tile
+// of kSplitTile output rows, staging the offsets of the L rows that own it.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBatchBlock) void batch_join_group(const SplitJob *jobs) {
+    const SplitJob &x = jobs[blockIdx.x];
+    const JoinJob &j = x.j;
+    Table t{s_key, s_cnt, s_start, s_rows, 0};
+    build_table(j, t, s_w);
+    for (uint32_t m = threadIdx.x; m < j.nr; m += kBatchBlock) x.grp[m] = t.rows[m];
+    for (uint32_t i = threadIdx.x; i < j.nl; i += kBatchBlock) {
+        const uint32_t h = find_slot(t, j.lkey[i]);
+        x.lbase[i] = h == kEmptyKey ? 0u : t.start[h];  // a row without a match owns no output
+    }
+}
+
+__global__ __launch_bounds__(kBatchBlock) void batch_join_split(const SplitJob *jobs, int nj,
+                                                                uint32_t tile_base) {
+    const uint32_t tile = tile_base + blockIdx.x;
+    int lo = 0, hi = nj - 1;  // the job: the last one whose first tile is <= tile
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (jobs[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+    }
+    const SplitJob &x = jobs[lo];
+    const JoinJob &j = x.j;
+    const uint32_t o0 = (tile - x.tile0) * kSplitTile;
+    const uint32_t o1 = min(o0 + kSplitTile, j.nout);
+    // the L rows owning [o0, o1): i0..i1 (at most nl of them)
+    const uint32_t i0 = owner_row(j.off, 0, j.nl - 1, o0);
+    const uint32_t i1 = owner_row(j.off, i0, j.nl - 1, o1 - 1);
+    for (uint32_t k = threadIdx.x; k <= i1 - i0; k += kBatchBlock) {
+        s_off[k] = j.off[i0 + k];
+        s_lb[k] = x.lbase[i0 + k];
+    }
+    __syncthreads();
+    expand_rows(j, s_off, s_lb, x.grp, i0, i1, o0, o1);
 }
 
 // ---------------------------------------------------------------------------
@@ -267,9 +387,59 @@ static const Job *upload(tid_ctx *ctx, BatchState &bs, const std::vector<Job> &j
     return bs.keep.back().get<const Job>();
 }
 
+// the expansions with a large output and no other shared variable: grouped
+// lists, then one output-row-parallel launch; returns the other jobs
+static std::vector<JoinJob> expand_split_jobs(tid_ctx *ctx, BatchState &bs,
+                                              const std::vector<JoinJob> &jobs) {
+    std::vector<JoinJob> rest;
+    std::vector<SplitJob> split;
+    uint64_t words = 0, tiles = 0;
+    for (const JoinJob &j : jobs) {
+        if (j.neq != 0 || j.nout <= kSplitOut) {
+            rest.push_back(j);
+            continue;
+        }
+        SplitJob x{};
+        x.j = j;
+        x.tile0 = (uint32_t)tiles;
+        tiles += (j.nout + kSplitTile - 1) / kSplitTile;
+        words += (uint64_t)j.nl + j.nr;
+        split.push_back(x);
+    }
+    if (split.empty()) return rest;
+    TID_REQUIRE(tiles < (1ull << 32), TID_E_UNSUPPORTED, "batched joins: output too large");
+    bs.keep.emplace_back(ctx, words * 4);
+    uint32_t *lists = bs.keep.back().get<uint32_t>();
+    for (SplitJob &x : split) {
+        x.grp = lists;
+        x.lbase = lists + x.j.nr;
+        lists += (uint64_t)x.j.nr + x.j.nl;
+    }
+    const SplitJob *d = upload(ctx, bs, split);
+    for (size_t j0 = 0; j0 < split.size(); j0 += 65535) {
+        const unsigned g = (unsigned)std::min<size_t>(65535, split.size() - j0);
+        hipLaunchKernelGGL(batch_join_group, dim3(g), dim3(kBatchBlock), 0, ctx->stream, d + j0);
+        TID_HIP(hipGetLastError());
+    }
+    for (uint64_t t0 = 0; t0 < tiles; t0 += 1u << 20) {
+        const unsigned g = (unsigned)std::min<uint64_t>(1u << 20, tiles - t0);
+        hipLaunchKernelGGL(batch_join_split, dim3(g), dim3(kBatchBlock), 0, ctx->stream, d,
+                           (int)split.size(), (uint32_t)t0);
+        TID_HIP(hipGetLastError());
+    }
+    return rest;
+}
+
 void flush_join_jobs(tid_ctx *ctx, BatchState &bs, bool expand) {
-    std::vector<JoinJob> &jobs = expand ? bs.expand_jobs : bs.count_jobs;
-    if (jobs.empty()) return;
+    std::vector<JoinJob> &all = expand ? bs.expand_jobs : bs.count_jobs;
+    if (all.empty()) return;
+    std::vector<JoinJob> rest;
+    if (expand) rest = expand_split_jobs(ctx, bs, all);
+    std::vector<JoinJob> &jobs = expand ? rest : all;
+    if (jobs.empty()) {
+        all.clear();
+        return;
+    }
     const JoinJob *d = upload(ctx, bs, jobs);
     for (size_t j0 = 0; j0 < jobs.size(); j0 += 65535) {
         const unsigned g = (unsigned)std::min<size_t>(65535, jobs.size() - j0);
@@ -281,7 +451,7 @@ void flush_join_jobs(tid_ctx *ctx, BatchState &bs, bool expand) {
                                d + j0);
         TID_HIP(hipGetLastError());
     }
-    jobs.clear();
+    all.clear();
 }
 
 void flush_sort_jobs(tid_ctx *ctx, BatchState &bs) {

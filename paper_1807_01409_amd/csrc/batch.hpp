@@ -15,6 +15,10 @@ constexpr uint32_t kSortRows = 8192;        // rows of a batched sort
 constexpr uint32_t kSortWords = 24576;      // rows x columns of a batched sort
 constexpr int kSortCols = 16;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+// A join job with more output rows than kSplitOut and no other shared
+// variable is expanded by many workgroups, kSplitTile rows each.
+constexpr uint32_t kSplitOut = 8192;
+constexpr uint32_t kSplitTile = 2048;
 
 struct JoinJob {
     const uint32_t *lkey, *rkey;
@@ -25,6 +29,17 @@ struct JoinJob {
     uint32_t *out[2 * kSmallCols];
     uint32_t *off;     // nl + 1 entries
     uint64_t *total;
+    uint32_t nout;     // output rows (set on the host for the expansion)
+};
+
+// A join job expanded output-row-parallel (nout > kSplitOut, neq == 0):
+// device lists written by its grouping launch, and its first tile in the
+// expansion launch.
+struct SplitJob {
+    JoinJob j;
+    uint32_t *grp;     // nr entries: R row indices grouped by key
+    uint32_t *lbase;   // nl entries: where each L row's key group starts in grp
+    uint32_t tile0;
 };
 
 // A table to put in lexicographic row order with the round's other larger

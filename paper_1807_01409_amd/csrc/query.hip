@@ -839,6 +839,7 @@ std::vector<std::unique_ptr<tid_table>> run_plans(
             if (r.pj->total) {
                 JoinJob j = r.sj;
                 for (int c = 0; c < t->ncols; ++c) j.out[c] = t->col[c];
+                j.nout = (uint32_t)r.pj->total;  // at most kSmallRows^2
                 bs.expand_jobs.push_back(j);
             }
             set_count_later(ctx, t.get(), r.pj->total);

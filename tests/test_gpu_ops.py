@@ -143,6 +143,51 @@ def test_natural_join_two_shared_vars(ctx):
     same(ctx.query(G, p), oracle.query(g, p))
 
 
+def _hub_graph(seed):
+    """Predicates 1, 2, 4 on a few hub subjects of very different degrees
+    (every side of a join on ?s stays within a batched small join, while the
+    hub pairs give hundreds of thousands of output rows), predicate 5 and 6
+    on many subjects of degree 1-3, and subjects present under one predicate
+    only (rows without a match)."""
+    rng = np.random.default_rng(seed)
+    rows = []
+    deg = {1: {101: 700, 102: 37, 103: 5, 104: 1},
+           2: {101: 600, 102: 29, 105: 9, 104: 1},
+           4: {101: 333, 103: 64, 102: 1},
+           7: {101: 2, 102: 3}}
+    for p, subj in deg.items():
+        for s, d in subj.items():
+            for o in rng.choice(100000, size=d, replace=False) + 1:
+                rows.append((s, p, o))
+    for s in range(1000, 2500):
+        for p in (5, 6):
+            for o in rng.choice(50, size=int(rng.integers(1, 4)), replace=False) + 1:
+                rows.append((s, p, o))
+    g = np.array(rows, dtype=np.uint32)
+    return g[rng.permutation(len(g))]
+
+
+def test_small_join_large_output(ctx):
+    """Joins whose sides are small but whose output is large (hub keys) are
+    expanded output-row-parallel; alone and in one batch with small-output
+    joins, every result equals the oracle's."""
+    g = _hub_graph(5)
+    G = ctx.load(g)
+    plans = []
+    for a, b in ((1, 2), (1, 4), (2, 4), (5, 6), (4, 1)):
+        n = {}
+        plans.append(Plan().scan(pat(f"?s {a} ?x", n)).scan(pat(f"?s {b} ?y", n)).join(n["?s"]))
+    n = {}  # a 3-way star: the second join's left side is the first's output
+    plans.append(Plan().scan(pat("?s 1 ?x", n)).scan(pat("?s 7 ?y", n)).join(n["?s"])
+                 .scan(pat("?s 2 ?z", n)).join(n["?s"]))
+    want = [oracle.query(g, p) for p in plans]
+    assert want[0].rows.shape[0] == 700 * 600 + 37 * 29 + 1
+    for p, w in zip(plans, want):
+        same(ctx.query(G, p), w)
+    for t, w in zip(ctx.query_batch(G, plans), want):
+        same(t, w)
+
+
 def test_random_plans(ctx):
     rng = np.random.default_rng(2024)
     for i in range(150):
