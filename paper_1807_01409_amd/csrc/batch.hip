@@ -5,19 +5,19 @@
 // its own hash build, scans, probe and expansion; it is a job of the round's
 // one count launch, then of the next round's one expansion launch.  A plan's
 // final lexicographic sort of at most kSortRows rows is likewise a job of one
-// sort launch.  Everything a job touches besides its inputs and outputs lives
-// in the workgroup's LDS, except for a join with a large output, whose
-// expansion is spread over many workgroups (below).
+// sort launch.  A job's hash table lives in the workgroup's LDS.
 //
 // Join job (Sec. 4.2: an equi-join on the shared variable, done here with a
 // hash table in LDS): the R side's keys go into an open-addressing table
 // (slot = key, count, first position of its rows in a per-slot row list);
 // each L row finds its key's slot and pairs with the slot's R rows that also
 // agree on every other shared variable (natural join).  The count launch
-// writes each L row's exclusive output offset and the job's total; the
-// expansion launch rebuilds the table and writes the rows.  The order of
-// rows within a join's output is not defined (a plan's result is always
-// sorted at its end).
+// writes each L row's exclusive output offset and the job's total.  Without
+// other shared variables it also leaves its grouping of R's rows by key in
+// device memory, and the expansion is one launch of output tiles over it;
+// otherwise the expansion launch rebuilds the table and each L row's thread
+// writes its pairs.  The order of rows within a join's output is not
+// defined (a plan's result is always sorted at its end).
 #include "batch.hpp"
 #include "device_common.hpp"
 
@@ -56,24 +56,46 @@ struct Table {
     uint32_t mask;
 };
 
-// R's keys into the LDS table: slot counts, slot starts, rows grouped by slot
+constexpr uint32_t kRowsPerThread = kSmallRows / kBatchBlock;  // 16
+
+// R's keys into the LDS table: slot counts, slot starts, rows grouped by slot.
+// Each thread loads its (up to kRowsPerThread) keys at once, then inserts
+// them.  The lanes of a wave that share the key of its first row (a hub key
+// fills whole waves) insert, count and reserve places through that row's
+// lane: one LDS atomic for the group instead of one per lane on one word.
 __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
     const uint32_t ts = pow2_at_least(2 * j.nr);
     t.mask = ts - 1;
+    uint32_t rk[kRowsPerThread];
+#pragma unroll
+    for (uint32_t u = 0; u < kRowsPerThread; ++u) {
+        const uint32_t r = u * kBatchBlock + threadIdx.x;
+        rk[u] = r < j.nr ? j.rkey[r] : kEmptyKey;
+    }
     for (uint32_t s = threadIdx.x; s < ts; s += kBatchBlock) {
         t.key[s] = kEmptyKey;
         t.cnt[s] = 0;
     }
     __syncthreads();
-    for (uint32_t r = threadIdx.x; r < j.nr; r += kBatchBlock) {
-        const uint32_t k = j.rkey[r];
-        uint32_t h = dev::hash32(k) & t.mask;
-        for (;;) {  // ends: the table has more slots than keys
-            const uint32_t prev = atomicCAS(&t.key[h], kEmptyKey, k);
-            if (prev == kEmptyKey || prev == k) break;
-            h = (h + 1) & t.mask;
+    const int lane = dev::lane_id();
+#pragma unroll
+    for (uint32_t u = 0; u < kRowsPerThread; ++u) {  // u is uniform: every lane takes the ballots
+        const bool live = u * kBatchBlock + threadIdx.x < j.nr;
+        const uint32_t k = rk[u];
+        const uint64_t lv = dev::ballot(live);
+        if (lv == 0) continue;  // the whole wave is past the end
+        const int lead = __builtin_ctzll(lv);
+        const uint32_t lk = __shfl(k, lead);
+        const uint64_t same = dev::ballot(live && k == lk);
+        if (live && (k != lk || lane == lead)) {
+            uint32_t h = dev::hash32(k) & t.mask;
+            for (;;) {  // ends: the table has more slots than keys
+                const uint32_t prev = atomicCAS(&t.key[h], kEmptyKey, k);
+                if (prev == kEmptyKey || prev == k) break;
+                h = (h + 1) & t.mask;
+            }
+            atomicAdd(&t.cnt[h], k == lk ? (uint32_t)__popcll(same) : 1u);
         }
-        atomicAdd(&t.cnt[h], 1u);
     }
     __syncthreads();
     // slot starts: each thread scans a contiguous run of ts / block slots
@@ -89,11 +111,24 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
         t.cnt[s] = 0;  // counts again while the rows are placed
     }
     __syncthreads();
-    for (uint32_t r = threadIdx.x; r < j.nr; r += kBatchBlock) {
-        const uint32_t k = j.rkey[r];
-        uint32_t h = dev::hash32(k) & t.mask;
-        while (t.key[h] != k) h = (h + 1) & t.mask;
-        t.rows[t.start[h] + atomicAdd(&t.cnt[h], 1u)] = r;
+#pragma unroll
+    for (uint32_t u = 0; u < kRowsPerThread; ++u) {
+        const uint32_t r = u * kBatchBlock + threadIdx.x;
+        const bool live = r < j.nr;
+        const uint32_t k = rk[u];
+        const uint64_t lv = dev::ballot(live);
+        if (lv == 0) continue;
+        const int lead = __builtin_ctzll(lv);
+        const uint32_t lk = __shfl(k, lead);
+        const uint64_t same = dev::ballot(live && k == lk);
+        uint32_t at = 0;
+        if (live && (k != lk || lane == lead)) {
+            uint32_t h = dev::hash32(k) & t.mask;
+            while (t.key[h] != k) h = (h + 1) & t.mask;
+            at = t.start[h] + atomicAdd(&t.cnt[h], k == lk ? (uint32_t)__popcll(same) : 1u);
+        }
+        const uint32_t group_at = __shfl(at, lead);
+        if (live) t.rows[k == lk ? group_at + dev::rank_in_mask(same) : at] = r;
     }
     __syncthreads();
 }
@@ -115,8 +150,6 @@ __device__ __forceinline__ bool agree(const JoinJob &j, uint32_t l, uint32_t r) 
     return ok;
 }
 
-constexpr uint32_t kRowsPerThread = kSmallRows / kBatchBlock;  // 16
-
 __shared__ uint32_t s_key[kSmallSlots], s_cnt[kSmallSlots], s_start[kSmallSlots];
 __shared__ uint32_t s_rows[kSmallRows];
 __shared__ uint32_t s_w[kBatchBlock / dev::kWave];
@@ -127,22 +160,25 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_count(const JoinJob *j
     const JoinJob &j = jobs[blockIdx.x];
     Table t{s_key, s_cnt, s_start, s_rows, 0};
     build_table(j, t, s_w);
-    // each thread a contiguous run of L rows, so offsets follow row order
-    uint32_t c[kRowsPerThread];
-    uint32_t local = 0;
+    // each thread a contiguous run of L rows, so offsets follow row order;
+    // the keys are loaded at once, the offsets (and group starts) stored after
+    uint32_t c[kRowsPerThread], lb[kRowsPerThread], lk[kRowsPerThread];
     const uint32_t i0 = threadIdx.x * kRowsPerThread;
 #pragma unroll
+    for (uint32_t u = 0; u < kRowsPerThread; ++u) lk[u] = i0 + u < j.nl ? j.lkey[i0 + u] : 0u;
+    uint32_t local = 0;
+#pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
-        const uint32_t i = i0 + u;
-        c[u] = 0;
-        if (i >= j.nl) continue;
-        const uint32_t h = find_slot(t, j.lkey[i]);
+        c[u] = lb[u] = 0;  // a row without a match owns no output
+        if (i0 + u >= j.nl) continue;
+        const uint32_t h = find_slot(t, lk[u]);
         if (h == kEmptyKey) continue;
         const uint32_t a = t.start[h], b = a + t.cnt[h];
+        lb[u] = a;
         if (j.neq == 0) {
             c[u] = b - a;
         } else {
-            for (uint32_t m = a; m < b; ++m) c[u] += agree(j, i, t.rows[m]);
+            for (uint32_t m = a; m < b; ++m) c[u] += agree(j, i0 + u, t.rows[m]);
         }
         local += c[u];
     }
@@ -151,13 +187,18 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_count(const JoinJob *j
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
         const uint32_t i = i0 + u;
-        if (i < j.nl) j.off[i] = run;
+        if (i < j.nl) {
+            j.off[i] = run;
+            if (j.neq == 0) j.lbase[i] = lb[u];
+        }
         run += c[u];
     }
     if (threadIdx.x == 0) {
         j.off[j.nl] = all;
         *j.total = all;
     }
+    if (j.neq == 0)  // the expansion pairs through this table's grouping
+        for (uint32_t m = threadIdx.x; m < j.nr; m += kBatchBlock) j.grp[m] = t.rows[m];
 }
 
 // Expansion.  With no other shared variable, L row i owns the output rows
@@ -223,22 +264,11 @@ __device__ __forceinline__ void expand_rows(const JoinJob &j, const uint32_t *lo
 }
 }  // namespace
 
+// a job with other shared variables: each L row's thread writes its pairs
 __global__ __launch_bounds__(kBatchBlock) void batch_join_expand(const JoinJob *jobs) {
     const JoinJob &j = jobs[blockIdx.x];
     Table t{s_key, s_cnt, s_start, s_rows, 0};
     build_table(j, t, s_w);
-    if (j.neq == 0) {
-        // each output row a thread's: L row i owns [off[i], off[i+1]), paired
-        // with its key's R rows in slot order
-        for (uint32_t i = threadIdx.x; i < j.nl; i += kBatchBlock) {
-            const uint32_t h = find_slot(t, j.lkey[i]);
-            s_off[i] = j.off[i];
-            s_lb[i] = h == kEmptyKey ? 0u : t.start[h];  // a row without a match owns no output
-        }
-        __syncthreads();
-        expand_rows(j, s_off, s_lb, t.rows, 0, j.nl - 1, 0, j.nout);
-        return;
-    }
     for (uint32_t i = threadIdx.x; i < j.nl; i += kBatchBlock) {
         const uint32_t h = find_slot(t, j.lkey[i]);
         if (h == kEmptyKey) continue;
@@ -254,27 +284,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_expand(const JoinJob *
     }
 }
 
-// ---------------------------------------------------------------------------
-// A job with a large output (a hub key: few rows on each side, up to
-// millions of pairs) and no other shared variable is spread over many
-// workgroups.  One workgroup per job rebuilds the table and writes the R
-// rows grouped by key (grp) and, for each L row, where its key's group
-// starts (lbase); then each workgroup of the second launch expands a tile
-// of kSplitTile output rows, staging the offsets of the L rows that own it.
-// ---------------------------------------------------------------------------
-
-__global__ __launch_bounds__(kBatchBlock) void batch_join_group(const SplitJob *jobs) {
-    const SplitJob &x = jobs[blockIdx.x];
-    const JoinJob &j = x.j;
-    Table t{s_key, s_cnt, s_start, s_rows, 0};
-    build_table(j, t, s_w);
-    for (uint32_t m = threadIdx.x; m < j.nr; m += kBatchBlock) x.grp[m] = t.rows[m];
-    for (uint32_t i = threadIdx.x; i < j.nl; i += kBatchBlock) {
-        const uint32_t h = find_slot(t, j.lkey[i]);
-        x.lbase[i] = h == kEmptyKey ? 0u : t.start[h];  // a row without a match owns no output
-    }
-}
-
+// a job without other shared variables: tiles of kSplitTile output rows, a
+// workgroup each, over the grouping the count launch left (lbase, grp); a
+// tile stages the offsets and group starts of the L rows that own it
 __global__ __launch_bounds__(kBatchBlock) void batch_join_split(const SplitJob *jobs, int nj,
                                                                 uint32_t tile_base) {
     const uint32_t tile = tile_base + blockIdx.x;
@@ -292,10 +304,10 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_split(const SplitJob *
     const uint32_t i1 = owner_row(j.off, i0, j.nl - 1, o1 - 1);
     for (uint32_t k = threadIdx.x; k <= i1 - i0; k += kBatchBlock) {
         s_off[k] = j.off[i0 + k];
-        s_lb[k] = x.lbase[i0 + k];
+        s_lb[k] = j.lbase[i0 + k];
     }
     __syncthreads();
-    expand_rows(j, s_off, s_lb, x.grp, i0, i1, o0, o1);
+    expand_rows(j, s_off, s_lb, j.grp, i0, i1, o0, o1);
 }
 
 // ---------------------------------------------------------------------------
@@ -387,15 +399,15 @@ static const Job *upload(tid_ctx *ctx, BatchState &bs, const std::vector<Job> &j
     return bs.keep.back().get<const Job>();
 }
 
-// the expansions with a large output and no other shared variable: grouped
-// lists, then one output-row-parallel launch; returns the other jobs
+// the expansions of jobs without other shared variables: one launch of
+// output tiles; returns the other jobs
 static std::vector<JoinJob> expand_split_jobs(tid_ctx *ctx, BatchState &bs,
                                               const std::vector<JoinJob> &jobs) {
     std::vector<JoinJob> rest;
     std::vector<SplitJob> split;
-    uint64_t words = 0, tiles = 0;
+    uint64_t tiles = 0;
     for (const JoinJob &j : jobs) {
-        if (j.neq != 0 || j.nout <= kSplitOut) {
+        if (j.neq != 0) {
             rest.push_back(j);
             continue;
         }
@@ -403,24 +415,11 @@ static std::vector<JoinJob> expand_split_jobs(tid_ctx *ctx, BatchState &bs,
         x.j = j;
         x.tile0 = (uint32_t)tiles;
         tiles += (j.nout + kSplitTile - 1) / kSplitTile;
-        words += (uint64_t)j.nl + j.nr;
         split.push_back(x);
     }
     if (split.empty()) return rest;
     TID_REQUIRE(tiles < (1ull << 32), TID_E_UNSUPPORTED, "batched joins: output too large");
-    bs.keep.emplace_back(ctx, words * 4);
-    uint32_t *lists = bs.keep.back().get<uint32_t>();
-    for (SplitJob &x : split) {
-        x.grp = lists;
-        x.lbase = lists + x.j.nr;
-        lists += (uint64_t)x.j.nr + x.j.nl;
-    }
     const SplitJob *d = upload(ctx, bs, split);
-    for (size_t j0 = 0; j0 < split.size(); j0 += 65535) {
-        const unsigned g = (unsigned)std::min<size_t>(65535, split.size() - j0);
-        hipLaunchKernelGGL(batch_join_group, dim3(g), dim3(kBatchBlock), 0, ctx->stream, d + j0);
-        TID_HIP(hipGetLastError());
-    }
     for (uint64_t t0 = 0; t0 < tiles; t0 += 1u << 20) {
         const unsigned g = (unsigned)std::min<uint64_t>(1u << 20, tiles - t0);
         hipLaunchKernelGGL(batch_join_split, dim3(g), dim3(kBatchBlock), 0, ctx->stream, d,

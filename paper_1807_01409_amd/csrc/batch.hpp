@@ -15,9 +15,8 @@ constexpr uint32_t kSortRows = 8192;        // rows of a batched sort
 constexpr uint32_t kSortWords = 24576;      // rows x columns of a batched sort
 constexpr int kSortCols = 16;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
-// A join job with more output rows than kSplitOut and no other shared
-// variable is expanded by many workgroups, kSplitTile rows each.
-constexpr uint32_t kSplitOut = 8192;
+// A join job without other shared variables is expanded in tiles of
+// kSplitTile output rows, a workgroup each.
 constexpr uint32_t kSplitTile = 2048;
 
 struct JoinJob {
@@ -28,17 +27,16 @@ struct JoinJob {
     const uint32_t *lcol[kSmallCols], *rcol[kSmallCols];
     uint32_t *out[2 * kSmallCols];
     uint32_t *off;     // nl + 1 entries
+    uint32_t *lbase;   // neq == 0: nl entries, where each L row's key group starts in grp
+    uint32_t *grp;     // neq == 0: nr entries, R row indices grouped by key
     uint64_t *total;
     uint32_t nout;     // output rows (set on the host for the expansion)
 };
 
-// A join job expanded output-row-parallel (nout > kSplitOut, neq == 0):
-// device lists written by its grouping launch, and its first tile in the
+// A join job expanded in tiles (neq == 0), with its first tile in the
 // expansion launch.
 struct SplitJob {
     JoinJob j;
-    uint32_t *grp;     // nr entries: R row indices grouped by key
-    uint32_t *lbase;   // nl entries: where each L row's key group starts in grp
     uint32_t tile0;
 };
 

@@ -327,8 +327,9 @@ struct PendingJoin {
     uint64_t total = 0;
     bool total_known = false;
     // a small join of a batch (batch.hip): counted and expanded as one job
-    // of a round's launch; sj_off holds its L rows' output offsets, sj_total
-    // its size, small_result its rows once expanded
+    // of a round's launch; sj_off holds its L rows' output offsets (then,
+    // without other shared variables, their key groups' starts and R's rows
+    // grouped by key), sj_total its size, small_result its rows once expanded
     bool small = false;
     DevBuf sj_off, sj_total;
     std::unique_ptr<tid_table> small_result;

@@ -549,7 +549,10 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
                 pj->small = true;
                 pj->L = L;
                 pj->R = R;
-                pj->sj_off = DevBuf(ctx, (L->nrows + 1) * 4);
+                // offsets; without other shared variables also the L rows'
+                // key group starts and R's rows grouped by key
+                const uint64_t lists = r.pj_eq.empty() ? L->nrows + R->nrows : 0;
+                pj->sj_off = DevBuf(ctx, (L->nrows + 1 + lists) * 4);
                 pj->sj_total = DevBuf(ctx, 8);
                 JoinJob &j = r.sj;
                 j = JoinJob{};
@@ -569,6 +572,10 @@ static void advance(tid_ctx *ctx, PlanRun &r, Needs &needs, BatchState *bs) {
                 for (size_t k = L->ncols; k < r.pj_keep.size(); ++k)
                     j.rcol[j.nrc++] = R->col[jp.rkeep[r.pj_keep[k] - L->ncols]];
                 j.off = pj->sj_off.get<uint32_t>();
+                if (j.neq == 0) {
+                    j.lbase = j.off + j.nl + 1;
+                    j.grp = j.lbase + j.nl;
+                }
                 j.total = pj->sj_total.get<uint64_t>();
                 for (int c = 0; c < L->ncols; ++c) pj->vars.push_back(L->vars[c]);
                 for (int c = 0; c < j.nrc; ++c)
