@@ -33,10 +33,11 @@ __device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
     return p;
 }
 
-// exclusive scan of v over the block in thread order; returns this thread's
-// prefix and leaves the total in *total
+// exclusive scan of v over a block of BLOCK threads in thread order; returns
+// this thread's prefix and leaves the total in *total
+template <int BLOCK = kBatchBlock>
 __device__ __forceinline__ uint32_t block_exclusive(uint32_t v, uint32_t *s_w, uint32_t *total) {
-    constexpr int NW = kBatchBlock / dev::kWave;
+    constexpr int NW = BLOCK / dev::kWave;
     const int lane = threadIdx.x % dev::kWave, wave = threadIdx.x / dev::kWave;
     const uint32_t incl = dev::wave_inclusive_sum(v);
     if (lane == dev::kWave - 1) s_w[wave] = incl;
@@ -318,8 +319,9 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_split(const SplitJob *
 
 namespace {
 __shared__ uint32_t s_vals[kSortWords];
-__shared__ uint16_t s_idx[kSortRows];
-__shared__ uint32_t s_sw[kBatchBlock / dev::kWave];
+__shared__ uint16_t s_idx[kSortRows], s_pos[kSortRows];
+__shared__ uint32_t s_sw[kBatchSortBlock / dev::kWave];
+constexpr uint16_t kDropped = 0xFFFF;  // s_pos of a row DISTINCT leaves out
 
 __device__ __forceinline__ bool row_less(uint32_t a, uint32_t b, uint32_t n, int ncols) {
     if (a >= n) return false;      // padding sorts last
@@ -338,49 +340,58 @@ __device__ __forceinline__ bool row_equal(uint32_t a, uint32_t b, uint32_t n, in
 }
 }  // namespace
 
-__global__ __launch_bounds__(kBatchBlock) void batch_sort(const SortJob *jobs) {
+// A workgroup of kBatchSortBlock threads per job.  Each step of the bitonic
+// network compares p/2 disjoint pairs (i, i + d), i with bit d clear; thread
+// q's pairs are numbered q, q + kBatchSortBlock, ... so that no thread idles.
+__global__ __launch_bounds__(kBatchSortBlock) void batch_sort(const SortJob *jobs) {
     const SortJob &j = jobs[blockIdx.x];
     const uint32_t n = j.n;
     for (int c = 0; c < j.ncols; ++c)
-        for (uint32_t i = threadIdx.x; i < n; i += kBatchBlock) s_vals[c * n + i] = j.in[c][i];
+        for (uint32_t i = threadIdx.x; i < n; i += kBatchSortBlock) s_vals[c * n + i] = j.in[c][i];
     uint32_t p = 1;
     while (p < n) p <<= 1;
-    for (uint32_t i = threadIdx.x; i < p; i += kBatchBlock) s_idx[i] = (uint16_t)i;
+    for (uint32_t i = threadIdx.x; i < p; i += kBatchSortBlock) s_idx[i] = (uint16_t)i;
     __syncthreads();
+    const uint32_t pairs = p >> 1;
     for (uint32_t k = 2; k <= p; k <<= 1) {
         for (uint32_t d = k >> 1; d > 0; d >>= 1) {
-            for (uint32_t i = threadIdx.x; i < p; i += kBatchBlock) {
-                const uint32_t x = i ^ d;
-                if (x > i) {
-                    const uint32_t a = s_idx[i], b = s_idx[x];
-                    const bool up = (i & k) == 0;
-                    if (row_less(b, a, n, j.ncols) == up) {
-                        s_idx[i] = (uint16_t)b;
-                        s_idx[x] = (uint16_t)a;
-                    }
+            for (uint32_t q = threadIdx.x; q < pairs; q += kBatchSortBlock) {
+                const uint32_t i = ((q & ~(d - 1)) << 1) | (q & (d - 1));
+                const uint32_t x = i | d;
+                const uint32_t a = s_idx[i], b = s_idx[x];
+                const bool up = (i & k) == 0;
+                if (row_less(b, a, n, j.ncols) == up) {
+                    s_idx[i] = (uint16_t)b;
+                    s_idx[x] = (uint16_t)a;
                 }
             }
             __syncthreads();
         }
     }
-    // output positions: all rows, or (DISTINCT) the first of each run of equal rows
-    constexpr uint32_t kPer = kSortRows / kBatchBlock;  // 32
+    // output positions: all rows, or (DISTINCT) the first of each run of equal
+    // rows; a thread counts a contiguous run of sorted rows, then the rows are
+    // written in sorted-position order across the threads
+    constexpr uint32_t kPer = kSortRows / kBatchSortBlock;  // 8
     const uint32_t i0 = threadIdx.x * kPer;
+    bool kept[kPer];
     uint32_t keep = 0;
+#pragma unroll
     for (uint32_t u = 0; u < kPer; ++u) {
         const uint32_t i = i0 + u;
-        if (i < n && (!j.distinct || i == 0 || !row_equal(s_idx[i], s_idx[i - 1], n, j.ncols)))
-            ++keep;
+        kept[u] = i < n && (!j.distinct || i == 0 || !row_equal(s_idx[i], s_idx[i - 1], n, j.ncols));
+        keep += kept[u];
     }
     uint32_t all;
-    uint32_t o = block_exclusive(keep, s_sw, &all);
+    uint32_t o = block_exclusive<kBatchSortBlock>(keep, s_sw, &all);
+#pragma unroll
     for (uint32_t u = 0; u < kPer; ++u) {
-        const uint32_t i = i0 + u;
-        if (i < n && (!j.distinct || i == 0 || !row_equal(s_idx[i], s_idx[i - 1], n, j.ncols))) {
-            for (int c = 0; c < j.ncols; ++c) j.out[c][o] = s_vals[c * n + s_idx[i]];
-            ++o;
-        }
+        if (i0 + u >= n) break;
+        s_pos[i0 + u] = kept[u] ? (uint16_t)o++ : kDropped;
     }
+    __syncthreads();
+    for (int c = 0; c < j.ncols; ++c)
+        for (uint32_t i = threadIdx.x; i < n; i += kBatchSortBlock)
+            if (s_pos[i] != kDropped) j.out[c][s_pos[i]] = s_vals[c * n + s_idx[i]];
     if (threadIdx.x == 0) *j.count = all;
 }
 
@@ -462,7 +473,7 @@ void flush_sort_jobs(tid_ctx *ctx, BatchState &bs) {
     const SortJob *d = upload(ctx, bs, bs.sort_jobs);
     for (size_t j0 = 0; j0 < bs.sort_jobs.size(); j0 += 65535) {
         const unsigned g = (unsigned)std::min<size_t>(65535, bs.sort_jobs.size() - j0);
-        hipLaunchKernelGGL(batch_sort, dim3(g), dim3(kBatchBlock), 0, ctx->stream, d + j0);
+        hipLaunchKernelGGL(batch_sort, dim3(g), dim3(kBatchSortBlock), 0, ctx->stream, d + j0);
         TID_HIP(hipGetLastError());
     }
     bs.sort_jobs.clear();

@@ -12,6 +12,7 @@ constexpr uint32_t kSmallSlots = 8192;      // LDS hash slots (>= 2 * kSmallRows
 constexpr int kSmallCols = 8;               // columns per side of a batched join
 constexpr int kSmallEq = 4;                 // other shared variables of a batched join
 constexpr uint32_t kSortRows = 8192;        // rows of a batched sort
+constexpr int kBatchSortBlock = 1024;       // threads of a batched sort's workgroup
 constexpr uint32_t kSortWords = 24576;      // rows x columns of a batched sort
 constexpr int kSortCols = 16;
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
