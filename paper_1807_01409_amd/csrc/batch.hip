@@ -60,10 +60,12 @@ struct Table {
 constexpr uint32_t kRowsPerThread = kSmallRows / kBatchBlock;  // 16
 
 // R's keys into the LDS table: slot counts, slot starts, rows grouped by slot.
-// Each thread loads its (up to kRowsPerThread) keys at once, then inserts
-// them.  The lanes of a wave that share the key of its first row (a hub key
-// fills whole waves) insert, count and reserve places through that row's
-// lane: one LDS atomic for the group instead of one per lane on one word.
+// The key equal to the empty marker (kEmptyKey, a valid ID) has a slot of its
+// own past the probed ones, slot mask + 1, placed last.  Each thread loads its
+// (up to kRowsPerThread) keys at once, then inserts them.  The lanes of a
+// wave that share the key of its first row (a hub key fills whole waves)
+// insert, count and reserve places through that row's lane: one LDS atomic
+// for the group instead of one per lane on one word.
 __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
     const uint32_t ts = pow2_at_least(2 * j.nr);
     t.mask = ts - 1;
@@ -73,7 +75,7 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
         const uint32_t r = u * kBatchBlock + threadIdx.x;
         rk[u] = r < j.nr ? j.rkey[r] : kEmptyKey;
     }
-    for (uint32_t s = threadIdx.x; s < ts; s += kBatchBlock) {
+    for (uint32_t s = threadIdx.x; s <= ts; s += kBatchBlock) {
         t.key[s] = kEmptyKey;
         t.cnt[s] = 0;
     }
@@ -89,11 +91,14 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
         const uint32_t lk = __shfl(k, lead);
         const uint64_t same = dev::ballot(live && k == lk);
         if (live && (k != lk || lane == lead)) {
-            uint32_t h = dev::hash32(k) & t.mask;
-            for (;;) {  // ends: the table has more slots than keys
-                const uint32_t prev = atomicCAS(&t.key[h], kEmptyKey, k);
-                if (prev == kEmptyKey || prev == k) break;
-                h = (h + 1) & t.mask;
+            uint32_t h = ts;
+            if (k != kEmptyKey) {
+                h = dev::hash32(k) & t.mask;
+                for (;;) {  // ends: the table has more slots than keys
+                    const uint32_t prev = atomicCAS(&t.key[h], kEmptyKey, k);
+                    if (prev == kEmptyKey || prev == k) break;
+                    h = (h + 1) & t.mask;
+                }
             }
             atomicAdd(&t.cnt[h], k == lk ? (uint32_t)__popcll(same) : 1u);
         }
@@ -111,6 +116,10 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
         run += t.cnt[s];
         t.cnt[s] = 0;  // counts again while the rows are placed
     }
+    if (threadIdx.x == 0) {  // the slot of kEmptyKey comes last
+        t.start[ts] = all;
+        t.cnt[ts] = 0;
+    }
     __syncthreads();
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
@@ -124,8 +133,11 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
         const uint64_t same = dev::ballot(live && k == lk);
         uint32_t at = 0;
         if (live && (k != lk || lane == lead)) {
-            uint32_t h = dev::hash32(k) & t.mask;
-            while (t.key[h] != k) h = (h + 1) & t.mask;
+            uint32_t h = ts;
+            if (k != kEmptyKey) {
+                h = dev::hash32(k) & t.mask;
+                while (t.key[h] != k) h = (h + 1) & t.mask;
+            }
             at = t.start[h] + atomicAdd(&t.cnt[h], k == lk ? (uint32_t)__popcll(same) : 1u);
         }
         const uint32_t group_at = __shfl(at, lead);
@@ -134,8 +146,9 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
     __syncthreads();
 }
 
-// the slot of key k, or kEmptyKey
+// the slot of key k, or kEmptyKey if R does not hold k
 __device__ __forceinline__ uint32_t find_slot(const Table &t, uint32_t k) {
+    if (k == kEmptyKey) return t.cnt[t.mask + 1] ? t.mask + 1 : kEmptyKey;
     uint32_t h = dev::hash32(k) & t.mask;
     for (;;) {
         const uint32_t x = t.key[h];
@@ -151,7 +164,7 @@ __device__ __forceinline__ bool agree(const JoinJob &j, uint32_t l, uint32_t r) 
     return ok;
 }
 
-__shared__ uint32_t s_key[kSmallSlots], s_cnt[kSmallSlots], s_start[kSmallSlots];
+__shared__ uint32_t s_key[kSmallSlots + 1], s_cnt[kSmallSlots + 1], s_start[kSmallSlots + 1];
 __shared__ uint32_t s_rows[kSmallRows];
 __shared__ uint32_t s_w[kBatchBlock / dev::kWave];
 

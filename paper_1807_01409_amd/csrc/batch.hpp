@@ -15,7 +15,7 @@ constexpr uint32_t kSortRows = 8192;        // rows of a batched sort
 constexpr int kBatchSortBlock = 1024;       // threads of a batched sort's workgroup
 constexpr uint32_t kSortWords = 24576;      // rows x columns of a batched sort
 constexpr int kSortCols = 16;
-constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;  // empty LDS hash slot (the ID itself has its own slot)
 // A join job without other shared variables is expanded in tiles of
 // kSplitTile output rows, a workgroup each.
 constexpr uint32_t kSplitTile = 2048;

@@ -188,6 +188,46 @@ def test_small_join_large_output(ctx):
         same(t, w)
 
 
+def test_small_join_key_at_id_maximum(ctx):
+    """The batched small join's LDS table marks empty slots with 2^32 - 1, also
+    a valid ID: join keys equal to it (a hub and a single row), next to keys
+    hashing anywhere, with and without a second shared variable, alone and
+    batched, equal the oracle's results."""
+    top = 2**32 - 1
+
+    def fmix32(x):  # the published MurmurHash3 finaliser, which places keys in the table
+        x ^= x >> 16
+        x = (x * 0x85EBCA6B) & 0xFFFFFFFF
+        x ^= x >> 13
+        x = (x * 0xC2B2AE35) & 0xFFFFFFFF
+        return x ^ (x >> 16)
+    # subjects whose home slot is that of 2^32 - 1 in tables of 64-256 slots
+    near = [s for s in range(20, 200000) if fmix32(s) & 255 == fmix32(top) & 255][:4]
+    assert len(near) == 4
+    rows = []
+    for p, subj in {1: {top: 40, top - 1: 3, 5: 7, 9: 1, **{s: 2 for s in near}},
+                    2: {top: 30, top - 1: 2, 9: 4, 11: 2, **{s: 1 for s in near[:3]}},
+                    3: {top: 1, 5: 2}}.items():
+        for s, d in subj.items():
+            for o in range(d):
+                rows.append((s, p, top - o if s == top else o + 1))
+    g = np.array(rows, dtype=np.uint32)
+    G = ctx.load(g)
+    plans = []
+    for a, b in ((1, 2), (2, 1), (1, 3)):
+        n = {}
+        plans.append(Plan().scan(pat(f"?s {a} ?x", n)).scan(pat(f"?s {b} ?y", n)).join(n["?s"]))
+    n = {}  # a second shared variable: the object
+    plans.append(Plan().scan(pat("?s 1 ?o", n)).scan(pat("?s 2 ?o", n)).join(n["?s"]))
+    want = [oracle.query(g, p) for p in plans]
+    assert want[0].rows.shape[0] == 40 * 30 + 3 * 2 + 1 * 4 + 3 * 2
+    assert want[3].rows.shape[0] > 0
+    for p, w in zip(plans, want):
+        same(ctx.query(G, p), w)
+    for t, w in zip(ctx.query_batch(G, plans), want):
+        same(t, w)
+
+
 def test_random_plans(ctx):
     rng = np.random.default_rng(2024)
     for i in range(150):
