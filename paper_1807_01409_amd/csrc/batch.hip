@@ -57,7 +57,7 @@ struct Table {
     uint32_t mask;
 };
 
-constexpr uint32_t kRowsPerThread = kSmallRows / kBatchBlock;  // 16
+constexpr uint32_t kRowsPerThread = kSmallRows / kJoinBlock;  // 4
 
 // R's keys into the LDS table: slot counts, slot starts, rows grouped by slot.
 // The key equal to the empty marker (kEmptyKey, a valid ID) has a slot of its
@@ -72,10 +72,10 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
     uint32_t rk[kRowsPerThread];
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
-        const uint32_t r = u * kBatchBlock + threadIdx.x;
-        rk[u] = r < j.nr ? j.rkey[r] : kEmptyKey;
+        const uint32_t r = u * kJoinBlock + threadIdx.x;
+        rk[u] = r < j.nr ? dev::gload(j.rkey + r) : kEmptyKey;
     }
-    for (uint32_t s = threadIdx.x; s <= ts; s += kBatchBlock) {
+    for (uint32_t s = threadIdx.x; s <= ts; s += kJoinBlock) {
         t.key[s] = kEmptyKey;
         t.cnt[s] = 0;
     }
@@ -83,7 +83,7 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
     const int lane = dev::lane_id();
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {  // u is uniform: every lane takes the ballots
-        const bool live = u * kBatchBlock + threadIdx.x < j.nr;
+        const bool live = u * kJoinBlock + threadIdx.x < j.nr;
         const uint32_t k = rk[u];
         const uint64_t lv = dev::ballot(live);
         if (lv == 0) continue;  // the whole wave is past the end
@@ -105,12 +105,12 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
     }
     __syncthreads();
     // slot starts: each thread scans a contiguous run of ts / block slots
-    const uint32_t per = ts / kBatchBlock > 0 ? ts / kBatchBlock : 1;
+    const uint32_t per = ts / kJoinBlock > 0 ? ts / kJoinBlock : 1;
     const uint32_t s0 = threadIdx.x * per;
     uint32_t local = 0;
     for (uint32_t s = s0; s < s0 + per && s < ts; ++s) local += t.cnt[s];
     uint32_t all;
-    uint32_t run = block_exclusive(local, s_w, &all);
+    uint32_t run = block_exclusive<kJoinBlock>(local, s_w, &all);
     for (uint32_t s = s0; s < s0 + per && s < ts; ++s) {
         t.start[s] = run;
         run += t.cnt[s];
@@ -123,7 +123,7 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
     __syncthreads();
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
-        const uint32_t r = u * kBatchBlock + threadIdx.x;
+        const uint32_t r = u * kJoinBlock + threadIdx.x;
         const bool live = r < j.nr;
         const uint32_t k = rk[u];
         const uint64_t lv = dev::ballot(live);
@@ -160,17 +160,17 @@ __device__ __forceinline__ uint32_t find_slot(const Table &t, uint32_t k) {
 
 __device__ __forceinline__ bool agree(const JoinJob &j, uint32_t l, uint32_t r) {
     bool ok = true;
-    for (int e = 0; e < j.neq; ++e) ok &= j.eq_l[e][l] == j.eq_r[e][r];
+    for (int e = 0; e < j.neq; ++e) ok &= dev::gload(j.eq_l[e] + l) == dev::gload(j.eq_r[e] + r);
     return ok;
 }
 
 __shared__ uint32_t s_key[kSmallSlots + 1], s_cnt[kSmallSlots + 1], s_start[kSmallSlots + 1];
 __shared__ uint32_t s_rows[kSmallRows];
-__shared__ uint32_t s_w[kBatchBlock / dev::kWave];
+__shared__ uint32_t s_w[kJoinBlock / dev::kWave];
 
 }  // namespace
 
-__global__ __launch_bounds__(kBatchBlock) void batch_join_count(const JoinJob *jobs) {
+__global__ __launch_bounds__(kJoinBlock) void batch_join_count(const JoinJob *jobs) {
     const JoinJob &j = jobs[blockIdx.x];
     Table t{s_key, s_cnt, s_start, s_rows, 0};
     build_table(j, t, s_w);
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_count(const JoinJob *j
     uint32_t c[kRowsPerThread], lb[kRowsPerThread], lk[kRowsPerThread];
     const uint32_t i0 = threadIdx.x * kRowsPerThread;
 #pragma unroll
-    for (uint32_t u = 0; u < kRowsPerThread; ++u) lk[u] = i0 + u < j.nl ? j.lkey[i0 + u] : 0u;
+    for (uint32_t u = 0; u < kRowsPerThread; ++u) lk[u] = i0 + u < j.nl ? dev::gload(j.lkey + i0 + u) : 0u;
     uint32_t local = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
@@ -197,22 +197,23 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_count(const JoinJob *j
         local += c[u];
     }
     uint32_t all;
-    uint32_t run = block_exclusive(local, s_w, &all);
+    uint32_t run = block_exclusive<kJoinBlock>(local, s_w, &all);
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
         const uint32_t i = i0 + u;
         if (i < j.nl) {
-            j.off[i] = run;
-            if (j.neq == 0) j.lbase[i] = lb[u];
+            dev::gstore(j.off + i, run);
+            if (j.neq == 0) dev::gstore(j.lbase + i, lb[u]);
         }
         run += c[u];
     }
     if (threadIdx.x == 0) {
-        j.off[j.nl] = all;
+        dev::gstore(j.off + j.nl, all);
         *j.total = all;
     }
     if (j.neq == 0)  // the expansion pairs through this table's grouping
-        for (uint32_t m = threadIdx.x; m < j.nr; m += kBatchBlock) j.grp[m] = t.rows[m];
+        for (uint32_t m = threadIdx.x; m < j.nr; m += kJoinBlock)
+            dev::gstore(j.grp + m, t.rows[m]);
 }
 
 // Expansion.  With no other shared variable, L row i owns the output rows
@@ -258,7 +259,7 @@ __device__ __forceinline__ void expand_rows(const JoinJob &j, const uint32_t *lo
             if (o < o1) {
                 const uint32_t k = owner_row(loff, 0, i1 - i0, o);
                 li[u] = i0 + k;
-                ri[u] = grp[lb[k] + (o - loff[k])];
+                ri[u] = dev::gload(grp + lb[k] + (o - loff[k]));
             }
         }
         for (int c = 0; c < j.nlc + j.nrc; ++c) {
@@ -267,11 +268,12 @@ __device__ __forceinline__ void expand_rows(const JoinJob &j, const uint32_t *lo
             uint32_t v[kUnroll];
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
-                v[u] = base + u * kBatchBlock + threadIdx.x < o1 ? src[left ? li[u] : ri[u]] : 0u;
+                v[u] = base + u * kBatchBlock + threadIdx.x < o1
+                           ? dev::gload(src + (left ? li[u] : ri[u])) : 0u;
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t o = base + u * kBatchBlock + threadIdx.x;
-                if (o < o1) j.out[c][o] = v[u];
+                if (o < o1) dev::gstore(j.out[c] + o, v[u]);
             }
         }
     }
@@ -279,20 +281,21 @@ __device__ __forceinline__ void expand_rows(const JoinJob &j, const uint32_t *lo
 }  // namespace
 
 // a job with other shared variables: each L row's thread writes its pairs
-__global__ __launch_bounds__(kBatchBlock) void batch_join_expand(const JoinJob *jobs) {
+__global__ __launch_bounds__(kJoinBlock) void batch_join_expand(const JoinJob *jobs) {
     const JoinJob &j = jobs[blockIdx.x];
     Table t{s_key, s_cnt, s_start, s_rows, 0};
     build_table(j, t, s_w);
-    for (uint32_t i = threadIdx.x; i < j.nl; i += kBatchBlock) {
-        const uint32_t h = find_slot(t, j.lkey[i]);
+    for (uint32_t i = threadIdx.x; i < j.nl; i += kJoinBlock) {
+        const uint32_t h = find_slot(t, dev::gload(j.lkey + i));
         if (h == kEmptyKey) continue;
-        uint32_t o = j.off[i];
+        uint32_t o = dev::gload(j.off + i);
         const uint32_t a = t.start[h], b = a + t.cnt[h];
         for (uint32_t m = a; m < b; ++m) {
             const uint32_t r = t.rows[m];
             if (!agree(j, i, r)) continue;
-            for (int c = 0; c < j.nlc; ++c) j.out[c][o] = j.lcol[c][i];
-            for (int c = 0; c < j.nrc; ++c) j.out[j.nlc + c][o] = j.rcol[c][r];
+            for (int c = 0; c < j.nlc; ++c) dev::gstore(j.out[c] + o, dev::gload(j.lcol[c] + i));
+            for (int c = 0; c < j.nrc; ++c)
+                dev::gstore(j.out[j.nlc + c] + o, dev::gload(j.rcol[c] + r));
             ++o;
         }
     }
@@ -317,8 +320,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_split(const SplitJob *
     const uint32_t i0 = owner_row(j.off, 0, j.nl - 1, o0);
     const uint32_t i1 = owner_row(j.off, i0, j.nl - 1, o1 - 1);
     for (uint32_t k = threadIdx.x; k <= i1 - i0; k += kBatchBlock) {
-        s_off[k] = j.off[i0 + k];
-        s_lb[k] = j.lbase[i0 + k];
+        s_off[k] = dev::gload(j.off + i0 + k);
+        s_lb[k] = dev::gload(j.lbase + i0 + k);
     }
     __syncthreads();
     expand_rows(j, s_off, s_lb, j.grp, i0, i1, o0, o1);
@@ -360,7 +363,8 @@ __global__ __launch_bounds__(kBatchSortBlock) void batch_sort(const SortJob *job
     const SortJob &j = jobs[blockIdx.x];
     const uint32_t n = j.n;
     for (int c = 0; c < j.ncols; ++c)
-        for (uint32_t i = threadIdx.x; i < n; i += kBatchSortBlock) s_vals[c * n + i] = j.in[c][i];
+        for (uint32_t i = threadIdx.x; i < n; i += kBatchSortBlock)
+            s_vals[c * n + i] = dev::gload(j.in[c] + i);
     uint32_t p = 1;
     while (p < n) p <<= 1;
     for (uint32_t i = threadIdx.x; i < p; i += kBatchSortBlock) s_idx[i] = (uint16_t)i;
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(kBatchSortBlock) void batch_sort(const SortJob *job
     __syncthreads();
     for (int c = 0; c < j.ncols; ++c)
         for (uint32_t i = threadIdx.x; i < n; i += kBatchSortBlock)
-            if (s_pos[i] != kDropped) j.out[c][s_pos[i]] = s_vals[c * n + s_idx[i]];
+            if (s_pos[i] != kDropped) dev::gstore(j.out[c] + s_pos[i], s_vals[c * n + s_idx[i]]);
     if (threadIdx.x == 0) *j.count = all;
 }
 
@@ -467,10 +471,10 @@ void flush_join_jobs(tid_ctx *ctx, BatchState &bs, bool expand) {
     for (size_t j0 = 0; j0 < jobs.size(); j0 += 65535) {
         const unsigned g = (unsigned)std::min<size_t>(65535, jobs.size() - j0);
         if (expand)
-            hipLaunchKernelGGL(batch_join_expand, dim3(g), dim3(kBatchBlock), 0, ctx->stream,
+            hipLaunchKernelGGL(batch_join_expand, dim3(g), dim3(kJoinBlock), 0, ctx->stream,
                                d + j0);
         else
-            hipLaunchKernelGGL(batch_join_count, dim3(g), dim3(kBatchBlock), 0, ctx->stream,
+            hipLaunchKernelGGL(batch_join_count, dim3(g), dim3(kJoinBlock), 0, ctx->stream,
                                d + j0);
         TID_HIP(hipGetLastError());
     }

@@ -7,6 +7,7 @@
 namespace tid {
 
 constexpr int kBatchBlock = 256;
+constexpr int kJoinBlock = 1024;             // threads of a small join's count or expansion (LDS table)
 constexpr uint32_t kSmallRows = 4096;       // rows per side of a batched join
 constexpr uint32_t kSmallSlots = 8192;      // LDS hash slots (>= 2 * kSmallRows)
 constexpr int kSmallCols = 8;               // columns per side of a batched join
