@@ -27,6 +27,17 @@ namespace tid {
 
 namespace {
 
+// Device-memory access through a pointer the compiler only knows as generic
+// (one read from a job table): as a global access it is counted apart from
+// LDS and scalar loads, so the waits those need do not also wait for it, as
+// they would for a flat access.  p must point to device memory.
+__device__ __forceinline__ uint32_t gload(const uint32_t *p) {
+    return *(const __attribute__((address_space(1))) uint32_t *)p;
+}
+__device__ __forceinline__ void gstore(uint32_t *p, uint32_t v) {
+    *(__attribute__((address_space(1))) uint32_t *)p = v;
+}
+
 __device__ __forceinline__ uint32_t pow2_at_least(uint32_t x) {
     uint32_t p = 64;
     while (p < x) p <<= 1;
@@ -73,7 +84,7 @@ __device__ void build_table(const JoinJob &j, Table &t, uint32_t *s_w) {
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
         const uint32_t r = u * kJoinBlock + threadIdx.x;
-        rk[u] = r < j.nr ? dev::gload(j.rkey + r) : kEmptyKey;
+        rk[u] = r < j.nr ? gload(j.rkey + r) : kEmptyKey;
     }
     for (uint32_t s = threadIdx.x; s <= ts; s += kJoinBlock) {
         t.key[s] = kEmptyKey;
@@ -160,7 +171,7 @@ __device__ __forceinline__ uint32_t find_slot(const Table &t, uint32_t k) {
 
 __device__ __forceinline__ bool agree(const JoinJob &j, uint32_t l, uint32_t r) {
     bool ok = true;
-    for (int e = 0; e < j.neq; ++e) ok &= dev::gload(j.eq_l[e] + l) == dev::gload(j.eq_r[e] + r);
+    for (int e = 0; e < j.neq; ++e) ok &= gload(j.eq_l[e] + l) == gload(j.eq_r[e] + r);
     return ok;
 }
 
@@ -179,7 +190,7 @@ __global__ __launch_bounds__(kJoinBlock) void batch_join_count(const JoinJob *jo
     uint32_t c[kRowsPerThread], lb[kRowsPerThread], lk[kRowsPerThread];
     const uint32_t i0 = threadIdx.x * kRowsPerThread;
 #pragma unroll
-    for (uint32_t u = 0; u < kRowsPerThread; ++u) lk[u] = i0 + u < j.nl ? dev::gload(j.lkey + i0 + u) : 0u;
+    for (uint32_t u = 0; u < kRowsPerThread; ++u) lk[u] = i0 + u < j.nl ? gload(j.lkey + i0 + u) : 0u;
     uint32_t local = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
@@ -202,18 +213,18 @@ __global__ __launch_bounds__(kJoinBlock) void batch_join_count(const JoinJob *jo
     for (uint32_t u = 0; u < kRowsPerThread; ++u) {
         const uint32_t i = i0 + u;
         if (i < j.nl) {
-            dev::gstore(j.off + i, run);
-            if (j.neq == 0) dev::gstore(j.lbase + i, lb[u]);
+            gstore(j.off + i, run);
+            if (j.neq == 0) gstore(j.lbase + i, lb[u]);
         }
         run += c[u];
     }
     if (threadIdx.x == 0) {
-        dev::gstore(j.off + j.nl, all);
+        gstore(j.off + j.nl, all);
         *j.total = all;
     }
     if (j.neq == 0)  // the expansion pairs through this table's grouping
         for (uint32_t m = threadIdx.x; m < j.nr; m += kJoinBlock)
-            dev::gstore(j.grp + m, t.rows[m]);
+            gstore(j.grp + m, t.rows[m]);
 }
 
 // Expansion.  With no other shared variable, L row i owns the output rows
@@ -259,7 +270,7 @@ __device__ __forceinline__ void expand_rows(const JoinJob &j, const uint32_t *lo
             if (o < o1) {
                 const uint32_t k = owner_row(loff, 0, i1 - i0, o);
                 li[u] = i0 + k;
-                ri[u] = dev::gload(grp + lb[k] + (o - loff[k]));
+                ri[u] = gload(grp + lb[k] + (o - loff[k]));
             }
         }
         for (int c = 0; c < j.nlc + j.nrc; ++c) {
@@ -269,11 +280,11 @@ __device__ __forceinline__ void expand_rows(const JoinJob &j, const uint32_t *lo
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u)
                 v[u] = base + u * kBatchBlock + threadIdx.x < o1
-                           ? dev::gload(src + (left ? li[u] : ri[u])) : 0u;
+                           ? gload(src + (left ? li[u] : ri[u])) : 0u;
 #pragma unroll
             for (int u = 0; u < kUnroll; ++u) {
                 const uint32_t o = base + u * kBatchBlock + threadIdx.x;
-                if (o < o1) dev::gstore(j.out[c] + o, v[u]);
+                if (o < o1) gstore(j.out[c] + o, v[u]);
             }
         }
     }
@@ -286,16 +297,16 @@ __global__ __launch_bounds__(kJoinBlock) void batch_join_expand(const JoinJob *j
     Table t{s_key, s_cnt, s_start, s_rows, 0};
     build_table(j, t, s_w);
     for (uint32_t i = threadIdx.x; i < j.nl; i += kJoinBlock) {
-        const uint32_t h = find_slot(t, dev::gload(j.lkey + i));
+        const uint32_t h = find_slot(t, gload(j.lkey + i));
         if (h == kEmptyKey) continue;
-        uint32_t o = dev::gload(j.off + i);
+        uint32_t o = gload(j.off + i);
         const uint32_t a = t.start[h], b = a + t.cnt[h];
         for (uint32_t m = a; m < b; ++m) {
             const uint32_t r = t.rows[m];
             if (!agree(j, i, r)) continue;
-            for (int c = 0; c < j.nlc; ++c) dev::gstore(j.out[c] + o, dev::gload(j.lcol[c] + i));
+            for (int c = 0; c < j.nlc; ++c) gstore(j.out[c] + o, gload(j.lcol[c] + i));
             for (int c = 0; c < j.nrc; ++c)
-                dev::gstore(j.out[j.nlc + c] + o, dev::gload(j.rcol[c] + r));
+                gstore(j.out[j.nlc + c] + o, gload(j.rcol[c] + r));
             ++o;
         }
     }
@@ -320,8 +331,8 @@ __global__ __launch_bounds__(kBatchBlock) void batch_join_split(const SplitJob *
     const uint32_t i0 = owner_row(j.off, 0, j.nl - 1, o0);
     const uint32_t i1 = owner_row(j.off, i0, j.nl - 1, o1 - 1);
     for (uint32_t k = threadIdx.x; k <= i1 - i0; k += kBatchBlock) {
-        s_off[k] = dev::gload(j.off + i0 + k);
-        s_lb[k] = dev::gload(j.lbase + i0 + k);
+        s_off[k] = gload(j.off + i0 + k);
+        s_lb[k] = gload(j.lbase + i0 + k);
     }
     __syncthreads();
     expand_rows(j, s_off, s_lb, j.grp, i0, i1, o0, o1);
@@ -364,7 +375,7 @@ __global__ __launch_bounds__(kBatchSortBlock) void batch_sort(const SortJob *job
     const uint32_t n = j.n;
     for (int c = 0; c < j.ncols; ++c)
         for (uint32_t i = threadIdx.x; i < n; i += kBatchSortBlock)
-            s_vals[c * n + i] = dev::gload(j.in[c] + i);
+            s_vals[c * n + i] = gload(j.in[c] + i);
     uint32_t p = 1;
     while (p < n) p <<= 1;
     for (uint32_t i = threadIdx.x; i < p; i += kBatchSortBlock) s_idx[i] = (uint16_t)i;
@@ -408,7 +419,7 @@ __global__ __launch_bounds__(kBatchSortBlock) void batch_sort(const SortJob *job
     __syncthreads();
     for (int c = 0; c < j.ncols; ++c)
         for (uint32_t i = threadIdx.x; i < n; i += kBatchSortBlock)
-            if (s_pos[i] != kDropped) dev::gstore(j.out[c] + s_pos[i], s_vals[c * n + s_idx[i]]);
+            if (s_pos[i] != kDropped) gstore(j.out[c] + s_pos[i], s_vals[c * n + s_idx[i]]);
     if (threadIdx.x == 0) *j.count = all;
 }
 

@@ -28,17 +28,6 @@ __device__ __forceinline__ uint32_t rank_in_mask(uint64_t mask) {
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
-// Device-memory access through a pointer the compiler only knows as generic
-// (one read from a job table, say): as a global access it is counted apart
-// from LDS and scalar loads, so the waits those need do not also wait for it,
-// as they would for a flat access.  p must point to device memory.
-__device__ __forceinline__ uint32_t gload(const uint32_t *p) {
-    return *(const __attribute__((address_space(1))) uint32_t *)p;
-}
-__device__ __forceinline__ void gstore(uint32_t *p, uint32_t v) {
-    *(__attribute__((address_space(1))) uint32_t *)p = v;
-}
-
 // 32-bit finaliser of MurmurHash3 (Appleby): every input bit affects every
 // output bit
 __device__ __forceinline__ uint32_t hash32(uint32_t x) {
