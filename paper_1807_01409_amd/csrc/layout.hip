@@ -224,6 +224,52 @@ __global__ void idx_count(const IdxJob *jobs, int J, uint64_t P, uint32_t *cnt, 
     }
 }
 
+// The same, one pair per wave, for launches with few pairs: each round the 64
+// lanes probe evenly spaced rows of the bound's interval and a ballot keeps
+// the part between the last probe before the bound and the first at or past
+// it, so a run of n rows takes about log64(n) dependent loads, not log2(n).
+__device__ uint64_t wave_bound(const uint32_t *col, uint64_t n, uint32_t key, bool upper) {
+    const uint64_t lane = (uint64_t)dev::lane_id();
+    uint64_t lo = 0, hi = n;  // the bound is in [lo, hi]
+    while (hi > lo) {         // wave-uniform
+        const uint64_t step = (hi - lo + dev::kWave - 1) / dev::kWave;
+        const uint64_t p = lo + lane * step;
+        bool before = false;  // the bound is past row p
+        if (p < hi) {
+            const uint32_t v = col[p];
+            before = v < key || (upper && v == key);
+        }
+        const uint64_t t = (uint64_t)__popcll(dev::ballot(before));  // a prefix of the lanes
+        const uint64_t nlo = t == 0 ? lo : lo + (t - 1) * step + 1;
+        hi = std::min<uint64_t>(hi, lo + t * step);
+        lo = nlo;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void idx_count_wave(const IdxJob *jobs, int J, uint64_t P,
+                                                      uint32_t *cnt, uint32_t *first) {
+    constexpr uint64_t kWaves = 256 / dev::kWave;
+    const uint64_t stride = (uint64_t)gridDim.x * kWaves;
+    for (uint64_t q = (uint64_t)blockIdx.x * kWaves + threadIdx.x / dev::kWave; q < P;
+         q += stride) {  // q is the same for every lane of a wave
+        const IdxJob &j = jobs[idx_job_of(jobs, J, q)];
+        const uint64_t i = q - j.pbase;
+        const uint32_t key = j.keys[i];
+        uint32_t c = 0, f = 0;
+        if (i == 0 || j.keys[i - 1] != key) {
+            const uint64_t lo = wave_bound(j.col, j.nrun, key, false);
+            const uint64_t hi = wave_bound(j.col + lo, j.nrun - lo, key, true) + lo;
+            c = (uint32_t)(hi - lo);
+            f = (uint32_t)lo;
+        }
+        if (dev::lane_id() == 0) {
+            cnt[q] = c;
+            first[q] = f;
+        }
+    }
+}
+
 // output row r (over all jobs) -> its pair (offs: exclusive sums of the run
 // lengths, P + 1 entries) -> the row of the predicate's run it copies
 __global__ void idx_expand(const IdxJob *jobs, int J, const uint64_t *offs, uint64_t P,
@@ -243,6 +289,9 @@ __global__ void idx_expand(const IdxJob *jobs, int J, const uint64_t *offs, uint
         for (int c = 0; c < j.ncols; ++c) j.out[c][at] = j.src[c] == 0 ? j.vs[row] : j.vo[row];
     }
 }
+
+// launches with at most this many (job, value) pairs search a pair per wave
+constexpr uint64_t kWavePairs = 16384;
 
 unsigned grid_for_rows(uint64_t n) {
     return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((n + 255) / 256, 16384));
@@ -310,9 +359,14 @@ void index_semijoin(tid_ctx *ctx, const tid_graph *g, const tid_pattern *pats,
         offs(ctx, (P + 1) * 8), djobs(ctx, sizeof(IdxJob) * J);
     TID_HIP(hipMemcpyAsync(djobs.get(), jobs.data(), sizeof(IdxJob) * J, hipMemcpyHostToDevice,
                            ctx->stream));
-    if (P) {
+    if (P > kWavePairs) {
         hipLaunchKernelGGL(idx_count, dim3(grid_for_rows(P)), dim3(256), 0, ctx->stream,
                            djobs.get<const IdxJob>(), J, P, cnt.get<uint32_t>(),
+                           first.get<uint32_t>());
+        TID_HIP(hipGetLastError());
+    } else if (P) {  // few pairs: a wave each, for latency
+        hipLaunchKernelGGL(idx_count_wave, dim3((unsigned)((P + 3) / 4)), dim3(256), 0,
+                           ctx->stream, djobs.get<const IdxJob>(), J, P, cnt.get<uint32_t>(),
                            first.get<uint32_t>());
         TID_HIP(hipGetLastError());
     }
